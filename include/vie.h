@@ -1,0 +1,202 @@
+/*
+ * vie.h - C ABI of the MI355X volume-integral-equation library.
+ *
+ * The method: the current-based volume integral equation for a dielectric
+ * body discretised with discontinuous piecewise-linear (PWL) voxel bases and
+ * Galerkin testing (Georgakis et al., "A Fast Volume Integral Equation Solver
+ * with Linear Basis Functions for the Accurate Computation of EM Fields in
+ * MRI", IEEE TAP 2020).  Sec. III gives the system
+ *     A x = b,  A = M_eps G - M_chi N,  b = c_e M_chi e_inc        (eq. 24)
+ * with 12 unknowns per voxel (3 components x 4 scalar bases, eq. 19-22);
+ * Sec. IV-A the FFT-accelerated product through circulant embedding of the
+ * block-Toeplitz tensors (eq. 42-43); Sec. IV-B the preconditioner
+ * P = M_eps G (eq. 17); Sec. IV-C fields and absorbed power (eq. 44).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * - Grid: Nx x Ny x Nz voxels of size dx x dy x dz (metres), box centred at
+ *   the origin; voxel centres at (n_i - (N_i - 1)/2) * d_i.
+ * - Vectors of unknowns ("x" layout): [nrhs][12][Nz][Ny][Nx], x fastest,
+ *   interleaved complex (real, imag).  Unknown index a = 4 p + (l - 1),
+ *   p in {x, y, z} -> 0..2, l = 1 (pulse), 2..4 (linear in x, y, z) (eq. 30).
+ * - Per-voxel arrays: [Nz][Ny][Nx].
+ * - precision: VIE_C64 (complex64, FP32 arithmetic) or VIE_C128 (complex128).
+ * - Time factor exp(+i w t); eps_r = eps' - i sigma / (w eps0) (eq. 2).
+ * - Device pointers are HIP device addresses (e.g. torch tensor data_ptr()).
+ *   The caller owns every buffer it passes; the context owns the operator,
+ *   the contrast and its workspaces.
+ * - All device work is ordered on the context's stream.  Calls that return
+ *   host data (norms, stats, powers) synchronise that stream.
+ * - Errors: a negative vie_status is returned and a message is kept per
+ *   thread (vie_last_error).  No exception crosses the ABI.  After an error
+ *   the context stays usable unless the status is VIE_EDEVICE.
+ */
+#ifndef VIE_H
+#define VIE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vie_ctx vie_ctx;
+
+typedef enum {
+    VIE_OK = 0,
+    VIE_EINVAL = -1,   /* bad argument (shape, pointer, option)            */
+    VIE_ENOMEM = -2,   /* device allocation failed                          */
+    VIE_EDEVICE = -3,  /* HIP runtime error                                 */
+    VIE_ENOCONV = -4,  /* solver stopped before the tolerance (x = best)    */
+    VIE_ENAN = -5,     /* non-finite input or iterate                       */
+    VIE_ESTATE = -6    /* call out of order (e.g. apply before set_grid)     */
+} vie_status;
+
+enum { VIE_C64 = 0, VIE_C128 = 1 };
+
+/* operator selector for vie_apply */
+enum {
+    VIE_OP_PREC = 0,  /* y = P^-1 A x = x - tau (G^-1 N x)          (eq. 17)  */
+    VIE_OP_A = 1,     /* y = A x = eps_r G x - chi (N x)            (eq. 24a) */
+    VIE_OP_N = 2      /* y = N x, the Galerkin N product            (eq. 25a) */
+};
+
+/* solver precision mode */
+enum {
+    VIE_SOLVE_FP64 = 0,     /* GMRES in complex128                            */
+    VIE_SOLVE_FP32_IR = 1   /* complex64 GMRES inside FP64 iterative refinement */
+};
+
+typedef struct {
+    int mode;            /* VIE_SOLVE_FP64 or VIE_SOLVE_FP32_IR               */
+    int restart;         /* GMRES restart length (paper: 50)                  */
+    int max_outer;       /* max restart cycles per solve (paper: 200)         */
+    double tol;          /* relative residual ||P^-1(b - A x)|| / ||P^-1 b||  */
+    double inner_tol;    /* FP32_IR: relative reduction per inner solve       */
+    int max_refine;      /* FP32_IR: max refinement steps                     */
+    int reorth;          /* 1: second Gram-Schmidt pass per Arnoldi step      */
+    int use_x0;          /* 1: x holds the initial guess, 0: start from zero  */
+} vie_solve_opts;
+
+typedef struct {
+    int converged;       /* 1 when the relative residual <= tol               */
+    int iterations;      /* inner GMRES iterations (Arnoldi steps)            */
+    int restarts;        /* restart cycles                                    */
+    int refinements;     /* FP64 refinement steps (FP32_IR)                   */
+    int matvecs_c64;     /* operator products in complex64                    */
+    int matvecs_c128;    /* operator products in complex128                   */
+    double rel_residual; /* final true relative residual (FP64)               */
+    double seconds;      /* wall time of the solve                            */
+} vie_solve_stats;
+
+/* -- context ------------------------------------------------------------- */
+
+/* Create a context bound to HIP device `device` and stream `stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the handle. */
+int vie_create(vie_ctx** out, int device, void* stream);
+void vie_destroy(vie_ctx* ctx);
+/* Message of the last failing call on this thread ("" if none). */
+const char* vie_last_error(void);
+/* Change the stream later calls are ordered on. */
+int vie_set_stream(vie_ctx* ctx, void* stream);
+
+/* -- grid and operator (Sec. III-A, III-C, IV-A) ---------------------------- */
+
+/* Define the voxel grid and frequency and build the operator: the 60 unique
+ * Toeplitz-defining block tensors N^{pl,ql'}(d), d in [0, N)^3 (eq. 42-43;
+ * 60 unique, Sec. V) are assembled on the device in FP64, embedded in
+ * circulants on the fft grid with the reflection signs of the PWL bases,
+ * transformed, and the octant xi_i <= M_i/2 kept in complex128 and
+ * complex64.  fft_size: NULL selects for each axis the smallest even
+ * 2/3/5-smooth M_i >= 2 N_i (2 N_i itself when smooth); otherwise each M_i
+ * must be >= 2 N_i - 1, even, 2/3/5-smooth and <= 4096.  Frees any previous
+ * grid and contrast state. */
+int vie_set_grid(vie_ctx* ctx, int nx, int ny, int nz, double dx, double dy, double dz,
+                 double freq_hz, const int* fft_size);
+
+/* Debug / parity entry: replace the operator by caller-supplied unique block
+ * tensors T_host [60][Nz][Ny][Nx] complex128 (host memory), d >= 0 octant,
+ * unique index u = 10 * pq + ll with pq over (xx, xy, xz, yy, yz, zz) and
+ * ll over (11, 12, 13, 14, 22, 23, 24, 33, 34, 44) (l <= l'), each entry being
+ * N^{(p,l),(q,l')}(d) with p <= q, l <= l'.  Requires vie_set_grid first. */
+int vie_set_toeplitz(vie_ctx* ctx, const double* T_host);
+
+/* Copy the assembled unique block tensors (layout of vie_set_toeplitz) to a
+ * host buffer of 60 * Nz * Ny * Nx complex128. */
+int vie_get_toeplitz(vie_ctx* ctx, double* T_host);
+
+/* -- materials and excitation (eq. 2, 7, 17, 27, 30-31) --------------------- */
+
+/* Per-voxel relative permittivity eps' and conductivity sigma (S/m), FP64
+ * [Nz][Ny][Nx], host (on_device = 0) or device pointers.  Computes eps_r,
+ * chi = eps_r - 1 and tau = chi / eps_r on the device.  VIE_ENAN on
+ * non-finite input, VIE_EINVAL on eps' <= 0 or sigma < 0. */
+int vie_set_contrast(vie_ctx* ctx, const double* eps_re, const double* sigma, int on_device);
+
+/* Tested incident field of a plane wave E0 pol exp(-i k0 dir . r) (eq. 30,
+ * plane wave of Sec. V-A for pol = x, dir = z), into e_t (device,
+ * [12][Nz][Ny][Nx] complex128).  pol and dir must be orthogonal unit vectors
+ * along coordinate axes. */
+int vie_incident_planewave(vie_ctx* ctx, const double pol[3], const double dir[3], double amp,
+                           void* e_t);
+
+/* Tested incident fields of nrhs Hertzian dipoles (current moment vectors in
+ * A m at positions in m, host arrays [nrhs][3]) into e_t (device,
+ * [nrhs][12][Nz][Ny][Nx] complex128), by nq^3-point Gauss quadrature per
+ * voxel on voxels with chi != 0 (others set to zero). */
+int vie_incident_dipoles(vie_ctx* ctx, int nrhs, const double* pos, const double* moment, int nq,
+                         void* e_t);
+
+/* Preconditioned right-hand side P^-1 b = c_e tau G^-1 e_t (eq. 17, 31),
+ * e_t and rhs complex128 device arrays in x layout. */
+int vie_rhs_prec(vie_ctx* ctx, int nrhs, const void* e_t, void* rhs);
+
+/* -- operator product (Sec. IV-A) ------------------------------------------ */
+
+/* y = op(x) for nrhs vectors in x layout, precision VIE_C64 or VIE_C128,
+ * device pointers, asynchronous on the context stream.  x and y must not
+ * overlap.  Requires vie_set_grid (and vie_set_contrast for OP_PREC/OP_A). */
+int vie_apply(vie_ctx* ctx, int op, int precision, int nrhs, const void* x, void* y);
+
+/* -- solve (Sec. IV-B, V: GMRES(50), left preconditioner P = M_eps G) ------- */
+
+void vie_default_opts(vie_solve_opts* opts);
+
+/* Solve P^-1 A x = P^-1 b for nrhs right-hand sides given as tested incident
+ * fields e_t (device, complex128, x layout).  x (device, complex128) receives
+ * the current coefficients (eq. 19); with opts->use_x0 it also holds the
+ * initial guess.  stats (host, nrhs entries, may be NULL).  Returns VIE_OK
+ * when every right-hand side converged, VIE_ENOCONV otherwise (x holds the
+ * last iterate). */
+int vie_solve(vie_ctx* ctx, const vie_solve_opts* opts, int nrhs, const void* e_t, void* x,
+              vie_solve_stats* stats);
+
+/* -- post-processing (Sec. IV-C, eq. 44, Sec. V-C) ------------------------- */
+
+/* Field coefficients e = x / (c_e chi) on voxels with chi != 0, zero
+ * elsewhere (eq. 6); complex128 device arrays in x layout. */
+int vie_fields(vie_ctx* ctx, int nrhs, const void* x, void* e);
+
+/* Absorbed power P_abs = 1/2 Re{x^* (c_e M_chi)^-1 G x} (eq. 44) per
+ * right-hand side, into p_abs_host[nrhs] (W). */
+int vie_absorbed_power(vie_ctx* ctx, int nrhs, const void* x, double* p_abs_host);
+
+/* Voxel power density 1/2 sigma |e|^2 averaged over each voxel (Sec. V-C),
+ * FP64 device array [nrhs][Nz][Ny][Nx], from field coefficients e. */
+int vie_power_density(vie_ctx* ctx, int nrhs, const void* e, double* p_dev);
+
+/* -- memory model (Sec. V, "unknowns memory") ------------------------------ */
+
+/* Bytes the paper counts as unknowns memory: 12 unknowns x 8 N_V padded
+ * points x 16 B (complex128) = 1536 N_V (Tables III, V, VII, VIII). */
+size_t vie_unknowns_bytes_paper(int nx, int ny, int nz);
+
+/* Device bytes this library needs to solve nrhs right-hand sides on the
+ * grid with fft size 2N: resident operator, contrast, padded FFT buffers and
+ * the Krylov basis of GMRES(restart) for the given mode. */
+int vie_footprint_bytes(int nx, int ny, int nz, int nrhs, int mode, int restart, size_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,250 @@
+"""MI355X volume-integral-equation library (PWL current-based VIE).
+
+Thin ctypes binding of the C ABI in include/vie.h: argument marshalling only,
+every step of the computation runs in the HIP library ``libvie.so``.  PyTorch
+supplies device memory and streams.  Importing fails loudly when the library
+has not been built (``python -m paper_1902_02196_amd.build``); there is no
+CPU fallback.
+
+Array layout: vectors of unknowns are torch tensors of shape
+(nrhs, 12, Nz, Ny, Nx), complex64 or complex128, on the GPU; unknown index
+a = 4 p + (l - 1) with p the field component and l the scalar basis
+(1 pulse, 2..4 linear in x, y, z).  Per-voxel arrays are (Nz, Ny, Nx).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvie.so")
+
+VIE_OK, VIE_EINVAL, VIE_ENOMEM, VIE_EDEVICE, VIE_ENOCONV, VIE_ENAN, VIE_ESTATE = 0, -1, -2, -3, -4, -5, -6
+C64, C128 = 0, 1
+OP_PREC, OP_A, OP_N = 0, 1, 2
+SOLVE_FP64, SOLVE_FP32_IR = 0, 1
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libvie.so is not built; run `python -m paper_1902_02196_amd.build` (needs hipcc)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("mode", _i), ("restart", _i), ("max_outer", _i), ("tol", _d), ("inner_tol", _d),
+                ("max_refine", _i), ("reorth", _i), ("use_x0", _i)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("converged", _i), ("iterations", _i), ("restarts", _i), ("refinements", _i),
+                ("matvecs_c64", _i), ("matvecs_c128", _i), ("rel_residual", _d), ("seconds", _d)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_sig = {
+    "vie_create": (_i, [ctypes.POINTER(_vp), _i, _vp]),
+    "vie_destroy": (None, [_vp]),
+    "vie_last_error": (ctypes.c_char_p, []),
+    "vie_set_stream": (_i, [_vp, _vp]),
+    "vie_set_grid": (_i, [_vp, _i, _i, _i, _d, _d, _d, _d, ctypes.POINTER(_i)]),
+    "vie_set_toeplitz": (_i, [_vp, _dp]),
+    "vie_get_toeplitz": (_i, [_vp, _dp]),
+    "vie_set_contrast": (_i, [_vp, _dp, _dp, _i]),
+    "vie_incident_planewave": (_i, [_vp, _dp, _dp, _d, _vp]),
+    "vie_incident_dipoles": (_i, [_vp, _i, _dp, _dp, _i, _vp]),
+    "vie_rhs_prec": (_i, [_vp, _i, _vp, _vp]),
+    "vie_apply": (_i, [_vp, _i, _i, _i, _vp, _vp]),
+    "vie_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
+    "vie_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _vp, _vp, ctypes.POINTER(SolveStats)]),
+    "vie_fields": (_i, [_vp, _i, _vp, _vp]),
+    "vie_absorbed_power": (_i, [_vp, _i, _vp, _dp]),
+    "vie_power_density": (_i, [_vp, _i, _vp, _vp]),
+    "vie_unknowns_bytes_paper": (ctypes.c_size_t, [_i, _i, _i]),
+    "vie_footprint_bytes": (_i, [_i, _i, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_size_t)]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class VieError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (status %d)" % (msg, code))
+        self.code = code
+
+
+def _check(code):
+    if code != VIE_OK:
+        raise VieError(code, _lib.vie_last_error().decode())
+    return code
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def unknowns_bytes_paper(nx, ny, nz):
+    """Unknowns memory as the paper counts it: 12 x 8 N_V x 16 B."""
+    return int(_lib.vie_unknowns_bytes_paper(nx, ny, nz))
+
+
+def footprint_bytes(nx, ny, nz, nrhs, mode, restart=50):
+    out = ctypes.c_size_t(0)
+    _check(_lib.vie_footprint_bytes(nx, ny, nz, nrhs, mode, restart, ctypes.byref(out)))
+    return int(out.value)
+
+
+def default_opts(**kw):
+    o = SolveOpts()
+    _lib.vie_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _tensor_ptr(t, dtype=None, shape=None):
+    import torch
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("expected dtype %s, got %s" % (dtype, t.dtype))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("expected shape %s, got %s" % (tuple(shape), tuple(t.shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One grid, operator and contrast on one GPU, ordered on one stream."""
+
+    def __init__(self, device=0, stream=None):
+        h = ctypes.c_void_p()
+        _check(_lib.vie_create(ctypes.byref(h), device, _stream_ptr(stream)))
+        self._h = h
+        self.N = None
+
+    def close(self):
+        if self._h:
+            _lib.vie_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        _check(_lib.vie_set_stream(self._h, _stream_ptr(stream)))
+
+    def set_grid(self, N, Delta, freq_hz, fft_size=None):
+        nx, ny, nz = (int(v) for v in N)
+        fs = None if fft_size is None else (ctypes.c_int * 3)(*[int(v) for v in fft_size])
+        _check(_lib.vie_set_grid(self._h, nx, ny, nz, float(Delta[0]), float(Delta[1]), float(Delta[2]),
+                                 float(freq_hz), fs))
+        self.N = (nx, ny, nz)
+
+    @property
+    def V(self):
+        return self.N[0] * self.N[1] * self.N[2]
+
+    def vec_shape(self, nrhs=1):
+        return (nrhs, 12, self.N[2], self.N[1], self.N[0])
+
+    def set_toeplitz(self, T_unique):
+        """T_unique: complex128 [60, Nz, Ny, Nx] (offsets d >= 0)."""
+        a = np.ascontiguousarray(T_unique, dtype=np.complex128)
+        assert a.shape == (60, self.N[2], self.N[1], self.N[0])
+        _check(_lib.vie_set_toeplitz(self._h, a.view(np.float64).ctypes.data_as(_dp)))
+
+    def get_toeplitz(self):
+        a = np.zeros((60, self.N[2], self.N[1], self.N[0]), dtype=np.complex128)
+        _check(_lib.vie_get_toeplitz(self._h, a.view(np.float64).ctypes.data_as(_dp)))
+        return a
+
+    def set_contrast(self, eps_re, sigma):
+        """eps', sigma as float64 arrays [Nz, Ny, Nx] (numpy on the host or
+        torch tensors on the GPU)."""
+        if isinstance(eps_re, np.ndarray):
+            e = np.ascontiguousarray(eps_re, dtype=np.float64)
+            s = np.ascontiguousarray(sigma, dtype=np.float64)
+            _check(_lib.vie_set_contrast(self._h, _dptr(e), _dptr(s), 0))
+        else:
+            e = ctypes.cast(_tensor_ptr(eps_re), _dp)
+            s = ctypes.cast(_tensor_ptr(sigma), _dp)
+            _check(_lib.vie_set_contrast(self._h, e, s, 1))
+
+    def incident_planewave(self, out, pol=(1.0, 0.0, 0.0), direction=(0.0, 0.0, 1.0), amp=1.0):
+        import torch
+        p = np.asarray(pol, dtype=np.float64)
+        d = np.asarray(direction, dtype=np.float64)
+        _check(_lib.vie_incident_planewave(self._h, _dptr(p), _dptr(d), float(amp),
+                                           _tensor_ptr(out, torch.complex128, self.vec_shape(1))))
+
+    def incident_dipoles(self, out, positions, moments, nq=4):
+        import torch
+        pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
+        mom = np.ascontiguousarray(moments, dtype=np.float64).reshape(-1, 3)
+        n = pos.shape[0]
+        _check(_lib.vie_incident_dipoles(self._h, n, _dptr(pos), _dptr(mom), int(nq),
+                                         _tensor_ptr(out, torch.complex128, self.vec_shape(n))))
+
+    def rhs_prec(self, e_t, out):
+        import torch
+        n = e_t.shape[0]
+        _check(_lib.vie_rhs_prec(self._h, n, _tensor_ptr(e_t, torch.complex128, self.vec_shape(n)),
+                                 _tensor_ptr(out, torch.complex128, self.vec_shape(n))))
+
+    def apply(self, x, y, op=OP_PREC):
+        import torch
+        prec = {torch.complex64: C64, torch.complex128: C128}[x.dtype]
+        n = x.shape[0]
+        _check(_lib.vie_apply(self._h, op, prec, n, _tensor_ptr(x, x.dtype, self.vec_shape(n)),
+                              _tensor_ptr(y, x.dtype, self.vec_shape(n))))
+
+    def solve(self, e_t, x, opts=None, **kw):
+        import torch
+        o = opts if opts is not None else default_opts(**kw)
+        n = e_t.shape[0]
+        st = (SolveStats * n)()
+        code = _lib.vie_solve(self._h, ctypes.byref(o), n, _tensor_ptr(e_t, torch.complex128, self.vec_shape(n)),
+                              _tensor_ptr(x, torch.complex128, self.vec_shape(n)), st)
+        if code not in (VIE_OK, VIE_ENOCONV):
+            _check(code)
+        return code, [s.as_dict() for s in st]
+
+    def fields(self, x, out):
+        import torch
+        n = x.shape[0]
+        _check(_lib.vie_fields(self._h, n, _tensor_ptr(x, torch.complex128, self.vec_shape(n)),
+                               _tensor_ptr(out, torch.complex128, self.vec_shape(n))))
+
+    def absorbed_power(self, x):
+        import torch
+        n = x.shape[0]
+        out = np.zeros(n)
+        _check(_lib.vie_absorbed_power(self._h, n, _tensor_ptr(x, torch.complex128, self.vec_shape(n)), _dptr(out)))
+        return out
+
+    def power_density(self, e, out):
+        import torch
+        n = e.shape[0]
+        _check(_lib.vie_power_density(self._h, n, _tensor_ptr(e, torch.complex128, self.vec_shape(n)),
+                                      _tensor_ptr(out, torch.float64, (n, self.N[2], self.N[1], self.N[0]))))

@@ -1,0 +1,175 @@
+// The FFT-accelerated operator product (Sec. IV-A) as five passes:
+//   P1  FFT along z, input zero-padded from Nz to Mz      [B][Nz][Ny][Nx] -> [B][Mz][Ny][Nx]
+//   P2  FFT along y, input zero-padded from Ny to My      -> [B][Mz][My][Nx]
+//   P3  FFT along x (padded), 12 x 12 block product with the circulant
+//       spectrum at every frequency, inverse FFT along x, crop to Nx (in place)
+//   P4  inverse FFT along y, crop to Ny                   -> [B][Mz][Ny][Nx]
+//   P5  inverse FFT along z, crop to Nz, then the epilogue that forms the
+//       requested operator from w = N x (Sec. IV-B):
+//         PREC:  y = x - tau G^-1 w               (P^-1 A, eq. 17)
+//         A:     y = eps_r G x - chi w            (eq. 24a)
+//         N:     y = w                            (eq. 25a)
+//         RESID: y = rhs - (x - tau G^-1 w)       (refinement residual)
+// B = 12 nrhs component arrays; the 1/(Mx My Mz) of the inverse FFT is folded
+// into the epilogue.
+#include <algorithm>
+
+#include "ctx.hpp"
+
+namespace vie {
+
+template <typename R> static const C<R>* twid(const FftAxis& a);
+template <> const C<float>* twid<float>(const FftAxis& a) { return a.tw64; }
+template <> const C<double>* twid<double>(const FftAxis& a) { return a.tw128; }
+template <typename R> static const C<R>* opspec(const Ctx& c);
+template <> const C<float>* opspec<float>(const Ctx& c) { return c.U64; }
+template <> const C<double>* opspec<double>(const Ctx& c) { return c.U128; }
+
+static int pick_tile(int n, size_t elem) {
+    // two LDS buffers of tile x n elements within 96 KiB; 4..16 pencils
+    int t = 16;
+    while (t > 4 && 2 * (size_t)t * n * elem > 96 * 1024) t /= 2;
+    return t;
+}
+
+template <typename R>
+void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs) {
+    VIE_REQUIRE(c.has_grid, VIE_ESTATE, "vie_apply before vie_set_grid");
+    if (op != OP_N) VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "operator needs vie_set_contrast");
+    const int Nx = c.N[0], Ny = c.N[1], Nz = c.N[2];
+    const int Mx = c.M[0], My = c.M[1], Mz = c.M[2];
+    const long long B = 12LL * nrhs;
+    const long long sA1 = (long long)Mz * Ny * Nx;   // per component, after P1 / P4
+    const long long sA2 = (long long)Mz * My * Nx;   // after P2 / P3
+    const size_t es = sizeof(C<R>);
+    char* ws = static_cast<char*>(c.ws.get((size_t)B * (sA1 + sA2) * es));
+    C<R>* A1 = reinterpret_cast<C<R>*>(ws);
+    C<R>* A2 = reinterpret_cast<C<R>*>(ws + (size_t)B * sA1 * es);
+    hipStream_t s = c.stream;
+    const long long V = c.V;
+
+    // P1: z
+    StridedPass p1{};
+    p1.plan = c.ax[2].plan;
+    p1.n_in = Nz;
+    p1.n_out = Mz;
+    p1.n_inner = Nx;
+    p1.tile = pick_tile(Mz, es);
+    p1.pitch = p1.tile;
+    p1.in_s1 = V;
+    p1.in_s2 = Nx;
+    p1.in_sk = (long long)Ny * Nx;
+    p1.out_s1 = sA1;
+    p1.out_s2 = Nx;
+    p1.out_sk = (long long)Ny * Nx;
+    launch_strided<R>(true, x, A1, p1, Ny, B, twid<R>(c.ax[2]), nullptr, s);
+
+    // P2: y
+    StridedPass p2{};
+    p2.plan = c.ax[1].plan;
+    p2.n_in = Ny;
+    p2.n_out = My;
+    p2.n_inner = Nx;
+    p2.tile = pick_tile(My, es);
+    p2.pitch = p2.tile;
+    p2.in_s1 = sA1;
+    p2.in_s2 = (long long)Ny * Nx;
+    p2.in_sk = Nx;
+    p2.out_s1 = sA2;
+    p2.out_s2 = (long long)My * Nx;
+    p2.out_sk = Nx;
+    launch_strided<R>(true, A1, A2, p2, Mz, B, twid<R>(c.ax[1]), nullptr, s);
+
+    // P3: x, block product
+    P3Params p3{};
+    p3.plan = c.ax[0].plan;
+    p3.Nx = Nx;
+    p3.My = My;
+    p3.Mz = Mz;
+    p3.Ox = c.O[0];
+    p3.Oy = c.O[1];
+    p3.Oz = c.O[2];
+    p3.nrhs = nrhs;
+    p3.s_b = sA2;
+    p3.s_z = (long long)My * Nx;
+    p3.s_y = Nx;
+    p3.u_e = c.Osz;
+    p3.pitch = Mx;
+    launch_p3<R>(A2, opspec<R>(c), p3, twid<R>(c.ax[0]), s);
+
+    // P4: inverse y, crop
+    StridedPass p4 = p2;
+    p4.n_in = My;
+    p4.n_out = Ny;
+    p4.in_s1 = sA2;
+    p4.in_s2 = (long long)My * Nx;
+    p4.in_sk = Nx;
+    p4.out_s1 = sA1;
+    p4.out_s2 = (long long)Ny * Nx;
+    p4.out_sk = Nx;
+    launch_strided<R>(false, A2, A1, p4, Mz, B, twid<R>(c.ax[1]), nullptr, s);
+
+    // P5: inverse z, crop, epilogue
+    StridedPass p5 = p1;
+    p5.n_in = Mz;
+    p5.n_out = Nz;
+    p5.in_s1 = sA1;
+    p5.in_s2 = Nx;
+    p5.in_sk = (long long)Ny * Nx;
+    p5.out_s1 = V;
+    p5.out_s2 = Nx;
+    p5.out_sk = (long long)Ny * Nx;
+    Epilogue<R> ep{};
+    const R scale = R(1.0 / ((double)Mx * My * Mz));
+    const double dv = c.D[0] * c.D[1] * c.D[2];
+    const double G[4] = {dv, dv / 12, dv / 12, dv / 12};
+    const C<R>* tau = nullptr;
+    const C<R>* epsr = nullptr;
+    const C<R>* chi = nullptr;
+    if constexpr (sizeof(R) == 4) {
+        tau = c.mat.tau64;
+        epsr = c.mat.epsr64;
+        chi = c.mat.chi64;
+    } else {
+        tau = c.mat.tau;
+        epsr = c.mat.eps_r;
+        chi = c.mat.chi;
+    }
+    ep.x = x;
+    ep.s1 = V;
+    for (int l = 0; l < 4; ++l) {
+        switch (op) {
+            case OP_PREC:
+                ep.a_const = 1;
+                ep.ga[l] = 1;
+                ep.b = tau;
+                ep.gb[l] = R(-scale / G[l]);
+                break;
+            case OP_A:
+                ep.a = epsr;
+                ep.ga[l] = R(G[l]);
+                ep.b = chi;
+                ep.gb[l] = -scale;
+                break;
+            case OP_N:
+                ep.a_const = 0;
+                ep.ga[l] = 0;
+                ep.b_const = 1;
+                ep.gb[l] = scale;
+                break;
+            case OP_RESID:
+                ep.a_const = -1;
+                ep.ga[l] = 1;
+                ep.b = tau;
+                ep.gb[l] = R(scale / G[l]);
+                ep.rhs = rhs;
+                break;
+        }
+    }
+    launch_strided<R>(false, A1, y, p5, Ny, B, twid<R>(c.ax[2]), &ep, s);
+}
+
+template void apply_op<float>(Ctx&, int, int, const C<float>*, C<float>*, const C<float>*);
+template void apply_op<double>(Ctx&, int, int, const C<double>*, C<double>*, const C<double>*);
+
+}  // namespace vie

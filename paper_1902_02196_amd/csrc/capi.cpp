@@ -1,0 +1,436 @@
+// extern "C" entry points (include/vie.h).  Every call catches exceptions and
+// turns them into a status code plus a thread-local message.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctx.hpp"
+
+using namespace vie;
+
+struct vie_ctx {
+    Ctx c;
+};
+
+static thread_local std::string g_err;
+
+template <typename F>
+static int guarded(F&& f) {
+    try {
+        g_err.clear();
+        f();
+        return VIE_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return VIE_EDEVICE;
+    }
+}
+
+namespace vie {
+
+Ctx::~Ctx() {
+    free_grid();
+    free_contrast();
+    ws.release();
+    small.release();
+    basis.release();
+    vecs.release();
+    if (flag) (void)hipFree(flag);
+}
+
+void Ctx::free_grid() {
+    for (auto& a : ax) {
+        if (a.tw128) (void)hipFree(a.tw128);
+        if (a.tw64) (void)hipFree(a.tw64);
+        a.tw128 = nullptr;
+        a.tw64 = nullptr;
+    }
+    if (T) (void)hipFree(T);
+    if (U128) (void)hipFree(U128);
+    if (U64) (void)hipFree(U64);
+    T = nullptr;
+    U128 = nullptr;
+    U64 = nullptr;
+    has_grid = false;
+}
+
+void Ctx::free_contrast() {
+    void* ps[] = {mat.eps_r, mat.chi, mat.tau, mat.tau64, mat.epsr64, mat.chi64, sigma};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    mat = Materials{};
+    sigma = nullptr;
+    has_contrast = false;
+}
+
+}  // namespace vie
+
+static void check_ctx(vie_ctx* ctx) { VIE_REQUIRE(ctx != nullptr, VIE_EINVAL, "null context"); }
+
+static void set_device(Ctx& c) { VIE_HIP(hipSetDevice(c.device)); }
+
+extern "C" {
+
+const char* vie_last_error(void) { return g_err.c_str(); }
+
+int vie_create(vie_ctx** out, int device, void* stream) {
+    return guarded([&] {
+        VIE_REQUIRE(out != nullptr, VIE_EINVAL, "out is null");
+        int n = 0;
+        VIE_HIP(hipGetDeviceCount(&n));
+        VIE_REQUIRE(device >= 0 && device < n, VIE_EINVAL, "no such HIP device");
+        auto* ctx = new vie_ctx();
+        ctx->c.device = device;
+        ctx->c.stream = static_cast<hipStream_t>(stream);
+        try {
+            set_device(ctx->c);
+            VIE_HIP(hipMalloc(&ctx->c.flag, sizeof(int)));
+        } catch (...) {
+            delete ctx;
+            throw;
+        }
+        *out = ctx;
+    });
+}
+
+void vie_destroy(vie_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->c.device);
+    if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
+    else (void)hipDeviceSynchronize();
+    delete ctx;
+}
+
+int vie_set_stream(vie_ctx* ctx, void* stream) {
+    return guarded([&] {
+        check_ctx(ctx);
+        ctx->c.stream = static_cast<hipStream_t>(stream);
+    });
+}
+
+int vie_set_grid(vie_ctx* ctx, int nx, int ny, int nz, double dx, double dy, double dz, double freq_hz,
+                 const int* fft_size) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1, VIE_EINVAL, "grid extents must be >= 1");
+        VIE_REQUIRE(std::isfinite(dx) && std::isfinite(dy) && std::isfinite(dz) && dx > 0 && dy > 0 && dz > 0,
+                    VIE_EINVAL, "voxel sizes must be positive");
+        VIE_REQUIRE(std::isfinite(freq_hz) && freq_hz > 0, VIE_EINVAL, "frequency must be positive");
+        const int N[3] = {nx, ny, nz};
+        int M[3];
+        for (int i = 0; i < 3; ++i) {
+            // default: the smallest even 2/3/5-smooth length >= 2N - 1 (2N when smooth)
+            M[i] = fft_size ? fft_size[i] : 2 * N[i];
+            if (!fft_size)
+                while (!smooth235(M[i])) M[i] += 2;
+        }
+        for (int i = 0; i < 3; ++i) {
+            VIE_REQUIRE(M[i] >= 2 * N[i] - 1 && M[i] % 2 == 0 && smooth235(M[i]), VIE_EINVAL,
+                        "fft size must be even, 2/3/5-smooth and >= 2N-1");
+            VIE_REQUIRE(M[i] <= 4096, VIE_EINVAL, "fft size above 4096 not supported");
+        }
+        if (c.stream) VIE_HIP(hipStreamSynchronize(c.stream));
+        c.free_grid();
+        c.free_contrast();
+        for (int i = 0; i < 3; ++i) {
+            c.N[i] = N[i];
+            c.M[i] = M[i];
+            c.O[i] = M[i] / 2 + 1;
+        }
+        c.D[0] = dx;
+        c.D[1] = dy;
+        c.D[2] = dz;
+        c.freq = freq_hz;
+        c.omega = 2.0 * M_PI * freq_hz;
+        c.k0 = c.omega * std::sqrt(kMu0 * kEps0);
+        c.V = (long long)nx * ny * nz;
+        c.Osz = (long long)c.O[0] * c.O[1] * c.O[2];
+        for (int i = 0; i < 3; ++i) {
+            c.ax[i].plan = make_plan(M[i]);
+            std::vector<double2> tw;
+            make_twiddles(M[i], tw);
+            std::vector<float2> tw32(M[i]);
+            for (int k = 0; k < M[i]; ++k) tw32[k] = make_float2((float)tw[k].x, (float)tw[k].y);
+            VIE_HIP(hipMalloc(&c.ax[i].tw128, M[i] * sizeof(double2)));
+            VIE_HIP(hipMalloc(&c.ax[i].tw64, M[i] * sizeof(float2)));
+            VIE_HIP(hipMemcpy(c.ax[i].tw128, tw.data(), M[i] * sizeof(double2), hipMemcpyHostToDevice));
+            VIE_HIP(hipMemcpy(c.ax[i].tw64, tw32.data(), M[i] * sizeof(float2), hipMemcpyHostToDevice));
+        }
+        VIE_HIP(hipMalloc(&c.T, 60 * c.V * sizeof(double2)));
+        VIE_HIP(hipMalloc(&c.U128, 60 * c.Osz * sizeof(double2)));
+        VIE_HIP(hipMalloc(&c.U64, 60 * c.Osz * sizeof(float2)));
+        AssemblyTables tab = build_assembly_tables(c.D, c.k0);
+        assemble_blocks(c.T, tab, nx, ny, nz, c.stream);
+        c.has_grid = true;
+        // operator spectra
+        const long long Mt = (long long)M[0] * M[1] * M[2];
+        double2* circ = static_cast<double2*>(c.ws.get(Mt * sizeof(double2)));
+        const double2* tws[3] = {c.ax[0].tw128, c.ax[1].tw128, c.ax[2].tw128};
+        FftPlan plans[3] = {c.ax[0].plan, c.ax[1].plan, c.ax[2].plan};
+        embed_and_transform(c.U128, c.U64, c.T, circ, nx, ny, nz, M[0], M[1], M[2], plans, tws, c.stream);
+        VIE_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+int vie_set_toeplitz(vie_ctx* ctx, const double* T_host) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_grid, VIE_ESTATE, "vie_set_toeplitz before vie_set_grid");
+        VIE_REQUIRE(T_host != nullptr, VIE_EINVAL, "T_host is null");
+        VIE_HIP(hipMemcpyAsync(c.T, T_host, 60 * c.V * sizeof(double2), hipMemcpyHostToDevice, c.stream));
+        const long long Mt = (long long)c.M[0] * c.M[1] * c.M[2];
+        double2* circ = static_cast<double2*>(c.ws.get(Mt * sizeof(double2)));
+        const double2* tws[3] = {c.ax[0].tw128, c.ax[1].tw128, c.ax[2].tw128};
+        FftPlan plans[3] = {c.ax[0].plan, c.ax[1].plan, c.ax[2].plan};
+        embed_and_transform(c.U128, c.U64, c.T, circ, c.N[0], c.N[1], c.N[2], c.M[0], c.M[1], c.M[2], plans, tws,
+                            c.stream);
+        VIE_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+int vie_get_toeplitz(vie_ctx* ctx, double* T_host) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_grid, VIE_ESTATE, "no grid");
+        VIE_REQUIRE(T_host != nullptr, VIE_EINVAL, "T_host is null");
+        VIE_HIP(hipMemcpyAsync(T_host, c.T, 60 * c.V * sizeof(double2), hipMemcpyDeviceToHost, c.stream));
+        VIE_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+int vie_set_contrast(vie_ctx* ctx, const double* eps_re, const double* sigma, int on_device) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_grid, VIE_ESTATE, "vie_set_contrast before vie_set_grid");
+        VIE_REQUIRE(eps_re && sigma, VIE_EINVAL, "null material array");
+        c.free_contrast();
+        const size_t V = (size_t)c.V;
+        VIE_HIP(hipMalloc(&c.mat.eps_r, V * sizeof(double2)));
+        VIE_HIP(hipMalloc(&c.mat.chi, V * sizeof(double2)));
+        VIE_HIP(hipMalloc(&c.mat.tau, V * sizeof(double2)));
+        VIE_HIP(hipMalloc(&c.mat.tau64, V * sizeof(float2)));
+        VIE_HIP(hipMalloc(&c.mat.epsr64, V * sizeof(float2)));
+        VIE_HIP(hipMalloc(&c.mat.chi64, V * sizeof(float2)));
+        VIE_HIP(hipMalloc(&c.sigma, V * sizeof(double)));
+        double* eps_dev = static_cast<double*>(c.small.get(V * sizeof(double)));
+        const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        VIE_HIP(hipMemcpyAsync(eps_dev, eps_re, V * sizeof(double), k, c.stream));
+        VIE_HIP(hipMemcpyAsync(c.sigma, sigma, V * sizeof(double), k, c.stream));
+        VIE_HIP(hipMemsetAsync(c.flag, 0, sizeof(int), c.stream));
+        launch_materials(eps_dev, c.sigma, c.omega * kEps0, c.mat, c.V, c.flag, c.stream);
+        int bad = 0;
+        VIE_HIP(hipMemcpyAsync(&bad, c.flag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        VIE_HIP(hipStreamSynchronize(c.stream));
+        if (bad) {
+            c.free_contrast();
+            if (bad & 1) throw Error(VIE_ENAN, "non-finite permittivity or conductivity");
+            throw Error(VIE_EINVAL, "permittivity must be > 0 and conductivity >= 0");
+        }
+        c.has_contrast = true;
+    });
+}
+
+static int axis_of(const double v[3]) {
+    int ax = -1, nz = 0;
+    for (int i = 0; i < 3; ++i)
+        if (v[i] != 0.0) {
+            ax = i;
+            ++nz;
+        }
+    return (nz == 1 && std::fabs(std::fabs(v[ax]) - 1.0) < 1e-12) ? ax : -1;
+}
+
+int vie_incident_planewave(vie_ctx* ctx, const double pol[3], const double dir[3], double amp, void* e_t) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_grid, VIE_ESTATE, "no grid");
+        VIE_REQUIRE(pol && dir && e_t, VIE_EINVAL, "null argument");
+        const int pa = axis_of(pol), da = axis_of(dir);
+        VIE_REQUIRE(pa >= 0 && da >= 0 && pa != da, VIE_EINVAL,
+                    "pol and dir must be distinct unit vectors along coordinate axes");
+        launch_planewave(static_cast<double2*>(e_t), c.N[0], c.N[1], c.N[2], c.D, c.k0, pa, da, dir[da] > 0 ? 1.0 : -1.0,
+                         amp, c.stream);
+    });
+}
+
+int vie_incident_dipoles(vie_ctx* ctx, int nrhs, const double* pos, const double* moment, int nq, void* e_t) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_grid && c.has_contrast, VIE_ESTATE, "dipoles need grid and contrast");
+        VIE_REQUIRE(nrhs >= 1 && pos && moment && e_t, VIE_EINVAL, "bad dipole arguments");
+        VIE_REQUIRE(nq >= 1 && nq <= kMaxGauss, VIE_EINVAL, "nq must be in 1..16");
+        AssemblyTables tab = build_assembly_tables(c.D, c.k0);   // holds the Gauss tables
+        std::vector<double> host(6 * (size_t)nrhs + 2 * nq);
+        for (int i = 0; i < 3 * nrhs; ++i) {
+            VIE_REQUIRE(std::isfinite(pos[i]) && std::isfinite(moment[i]), VIE_ENAN, "non-finite dipole");
+            host[i] = pos[i];
+            host[3 * nrhs + i] = moment[i];
+        }
+        for (int i = 0; i < nq; ++i) {
+            host[6 * nrhs + i] = tab.gl_x[nq][i];
+            host[6 * nrhs + nq + i] = tab.gl_w[nq][i];
+        }
+        double* dev = static_cast<double*>(c.small.get(host.size() * sizeof(double)));
+        VIE_HIP(hipMemcpyAsync(dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        launch_dipoles(static_cast<double2*>(e_t), nrhs, dev, dev + 3 * nrhs, nq, dev + 6 * nrhs, dev + 6 * nrhs + nq,
+                       c.mat.chi, c.N[0], c.N[1], c.N[2], c.D, c.k0, c.omega * kEps0, c.stream);
+        VIE_HIP(hipStreamSynchronize(c.stream));   // the host staging buffer is reused
+    });
+}
+
+int vie_rhs_prec(vie_ctx* ctx, int nrhs, const void* e_t, void* rhs) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "no contrast");
+        VIE_REQUIRE(nrhs >= 1 && e_t && rhs, VIE_EINVAL, "bad arguments");
+        const double dv = c.D[0] * c.D[1] * c.D[2];
+        const double ginv[4] = {1 / dv, 12 / dv, 12 / dv, 12 / dv};
+        launch_rhs_prec(static_cast<double2*>(rhs), static_cast<const double2*>(e_t), c.mat.tau, ginv,
+                        make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.stream);
+    });
+}
+
+int vie_apply(vie_ctx* ctx, int op, int precision, int nrhs, const void* x, void* y) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(op == VIE_OP_PREC || op == VIE_OP_A || op == VIE_OP_N, VIE_EINVAL, "unknown operator");
+        VIE_REQUIRE(nrhs >= 1 && x && y, VIE_EINVAL, "bad arguments");
+        VIE_REQUIRE(x != y, VIE_EINVAL, "x and y must not overlap");
+        if (precision == VIE_C64)
+            apply_op<float>(c, op, nrhs, static_cast<const float2*>(x), static_cast<float2*>(y), nullptr);
+        else if (precision == VIE_C128)
+            apply_op<double>(c, op, nrhs, static_cast<const double2*>(x), static_cast<double2*>(y), nullptr);
+        else
+            throw Error(VIE_EINVAL, "precision must be VIE_C64 or VIE_C128");
+    });
+}
+
+void vie_default_opts(vie_solve_opts* o) {
+    if (!o) return;
+    o->mode = VIE_SOLVE_FP64;
+    o->restart = 50;
+    o->max_outer = 200;
+    o->tol = 1e-6;
+    o->inner_tol = 1e-5;
+    o->max_refine = 400;
+    o->reorth = 1;
+    o->use_x0 = 0;
+}
+
+int vie_solve(vie_ctx* ctx, const vie_solve_opts* opts, int nrhs, const void* e_t, void* x, vie_solve_stats* stats) {
+    int rc = VIE_OK;
+    int g = guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_grid && c.has_contrast, VIE_ESTATE, "solve needs grid and contrast");
+        VIE_REQUIRE(nrhs >= 1 && e_t && x, VIE_EINVAL, "bad arguments");
+        vie_solve_opts o;
+        if (opts) o = *opts;
+        else vie_default_opts(&o);
+        VIE_REQUIRE(o.restart >= 1 && o.restart <= 200, VIE_EINVAL, "restart must be in 1..200");
+        VIE_REQUIRE(o.max_outer >= 1 && o.tol > 0 && o.tol < 1, VIE_EINVAL, "bad tolerance or max_outer");
+        VIE_REQUIRE(o.mode == VIE_SOLVE_FP64 || o.mode == VIE_SOLVE_FP32_IR, VIE_EINVAL, "unknown mode");
+        rc = solve(c, o, nrhs, static_cast<const double2*>(e_t), static_cast<double2*>(x), stats);
+        if (rc == VIE_ENOCONV) g_err = "solver stopped before reaching the tolerance";
+        if (rc == VIE_ENAN) g_err = "non-finite residual";
+    });
+    return g != VIE_OK ? g : rc;
+}
+
+int vie_fields(vie_ctx* ctx, int nrhs, const void* x, void* e) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "no contrast");
+        VIE_REQUIRE(nrhs >= 1 && x && e, VIE_EINVAL, "bad arguments");
+        launch_fields(static_cast<double2*>(e), static_cast<const double2*>(x), c.mat.chi,
+                      make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.stream);
+    });
+}
+
+int vie_absorbed_power(vie_ctx* ctx, int nrhs, const void* x, double* p_abs_host) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "no contrast");
+        VIE_REQUIRE(nrhs >= 1 && x && p_abs_host, VIE_EINVAL, "bad arguments");
+        const int nb = 256;
+        double* part = static_cast<double*>(c.small.get((size_t)nb * nrhs * sizeof(double)));
+        const double dv = c.D[0] * c.D[1] * c.D[2];
+        const double gram[4] = {dv, dv / 12, dv / 12, dv / 12};
+        launch_power_partials(part, static_cast<const double2*>(x), c.mat.chi, gram,
+                              make_double2(0.0, c.omega * kEps0), c.V, nrhs, nb, c.stream);
+        std::vector<double> h((size_t)nb * nrhs);
+        VIE_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        VIE_HIP(hipStreamSynchronize(c.stream));
+        for (int r = 0; r < nrhs; ++r) {
+            double s = 0;
+            for (int b = 0; b < nb; ++b) s += h[(size_t)r * nb + b];
+            p_abs_host[r] = s;
+        }
+    });
+}
+
+int vie_power_density(vie_ctx* ctx, int nrhs, const void* e, double* p_dev) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "no contrast");
+        VIE_REQUIRE(nrhs >= 1 && e && p_dev, VIE_EINVAL, "bad arguments");
+        launch_power_density(p_dev, static_cast<const double2*>(e), c.sigma, c.V, nrhs, c.stream);
+    });
+}
+
+size_t vie_unknowns_bytes_paper(int nx, int ny, int nz) {
+    if (nx < 1 || ny < 1 || nz < 1) return 0;
+    return (size_t)12 * 8 * (size_t)nx * ny * nz * 16;
+}
+
+int vie_footprint_bytes(int nx, int ny, int nz, int nrhs, int mode, int restart, size_t* out) {
+    return guarded([&] {
+        VIE_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1 && nrhs >= 1 && restart >= 1 && out, VIE_EINVAL, "bad arguments");
+        const size_t V = (size_t)nx * ny * nz;
+        const size_t M = 8 * V;
+        const size_t O = (size_t)(nx + 1) * (ny + 1) * (nz + 1);
+        const size_t n = 12 * V;
+        const size_t s = (mode == VIE_SOLVE_FP32_IR) ? 8 : 16;
+        size_t b = 0;
+        b += 60 * V * 16;                 // block tensors
+        b += 60 * O * (16 + 8);           // octant spectra, both precisions
+        b += V * (3 * 16 + 3 * 8 + 8);    // materials
+        b += M * 16;                      // set-up circulant (reused as FFT workspace)
+        // FFT intermediates ([B][Mz][Ny][Nx] + [B][Mz][My][Nx] = 6 n per rhs)
+        const size_t fft = 6 * n * nrhs * s;
+        const size_t fft128 = 6 * n * nrhs * 16;   // refinement residual in complex128
+        b += (mode == VIE_SOLVE_FP32_IR) ? std::max(fft, fft128) : fft;
+        b += (size_t)(restart + 1) * n * nrhs * s;  // Krylov basis
+        b += 2 * n * nrhs * 16;                      // residual and right-hand side (complex128)
+        *out = b;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Shared definitions of the HIP library: complex helpers, error handling,
+// unknown-index bookkeeping of the PWL basis.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+namespace vie {
+
+// ---------------------------------------------------------------------------
+// complex arithmetic on float2 / double2
+// ---------------------------------------------------------------------------
+template <typename R> struct cplx;
+template <> struct cplx<float> { using type = float2; };
+template <> struct cplx<double> { using type = double2; };
+template <typename R> using C = typename cplx<R>::type;
+
+template <typename R> __host__ __device__ __forceinline__ C<R> mk(R re, R im) {
+    C<R> z;
+    z.x = re;
+    z.y = im;
+    return z;
+}
+template <typename T> __host__ __device__ __forceinline__ T cadd(T a, T b) { T r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename T> __host__ __device__ __forceinline__ T csub(T a, T b) { T r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename T> __host__ __device__ __forceinline__ T cmul(T a, T b) {
+    T r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+// conj(a) * b
+template <typename T> __host__ __device__ __forceinline__ T cmulc(T a, T b) {
+    T r;
+    r.x = a.x * b.x + a.y * b.y;
+    r.y = a.x * b.y - a.y * b.x;
+    return r;
+}
+template <typename T, typename S> __host__ __device__ __forceinline__ T cscale(T a, S s) { T r; r.x = a.x * s; r.y = a.y * s; return r; }
+// multiply by -i (forward) or +i (inverse)
+template <bool FWD, typename T> __host__ __device__ __forceinline__ T mul_mi(T a) {
+    T r;
+    if (FWD) { r.x = a.y; r.y = -a.x; } else { r.x = -a.y; r.y = a.x; }
+    return r;
+}
+// acc += a * b
+template <typename T> __host__ __device__ __forceinline__ void cfma(T& acc, T a, T b) {
+    acc.x += a.x * b.x - a.y * b.y;
+    acc.y += a.x * b.y + a.y * b.x;
+}
+
+// ---------------------------------------------------------------------------
+// PWL unknown bookkeeping: a = 4 p + (l - 1); reflection signs
+// ---------------------------------------------------------------------------
+// sigma_axis(a): reflecting `axis` flips the field component along it and the
+// linear function along it (scalar basis l == axis + 2).
+constexpr __host__ __device__ __forceinline__ int refl_sign(int axis, int a) {
+    int p = a >> 2, l = (a & 3) + 1;
+    int s = 1;
+    if (p == axis) s = -s;
+    if (l == axis + 2) s = -s;
+    return s;
+}
+// bit a of the mask set where prod over the folded axes of sigma_axis(a) = -1
+constexpr __host__ __device__ __forceinline__ unsigned fold_mask(int fx, int fy, int fz) {
+    unsigned m = 0;
+    for (int a = 0; a < 12; ++a) {
+        int s = 1;
+        if (fx) s *= refl_sign(0, a);
+        if (fy) s *= refl_sign(1, a);
+        if (fz) s *= refl_sign(2, a);
+        if (s < 0) m |= (1u << a);
+    }
+    return m;
+}
+// unique-entry index of N^{(p,l),(q,l')}: 10 * pq + ll, with the sign that
+// relates the entry to the stored (p <= q, l <= l') one.
+constexpr __host__ __device__ __forceinline__ int pq_index(int p, int q) {
+    if (p > q) { int t = p; p = q; q = t; }
+    // (0,0)=0 (0,1)=1 (0,2)=2 (1,1)=3 (1,2)=4 (2,2)=5
+    return p == 0 ? q : (p == 1 ? 2 + q : 5);
+}
+constexpr __host__ __device__ __forceinline__ int ll_index(int l, int lp) {  // l, lp in 1..4
+    if (l > lp) { int t = l; l = lp; lp = t; }
+    // (1,1)=0 (1,2)=1 (1,3)=2 (1,4)=3 (2,2)=4 (2,3)=5 (2,4)=6 (3,3)=7 (3,4)=8 (4,4)=9
+    return (l - 1) * (10 - l) / 2 + (lp - l);
+}
+constexpr __host__ __device__ __forceinline__ int unique_index(int a, int b) {
+    return 10 * pq_index(a >> 2, b >> 2) + ll_index((a & 3) + 1, (b & 3) + 1);
+}
+// exchanging the scalar bases of a pulse / linear pair flips the sign
+constexpr __host__ __device__ __forceinline__ int unique_sign(int a, int b) {
+    int l = (a & 3) + 1, lp = (b & 3) + 1;
+    return (l > lp && lp == 1) ? -1 : 1;
+}
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define VIE_HIP(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            throw ::vie::Error(e_ == hipErrorOutOfMemory ? -2 : -3,                         \
+                               std::string(#call) + ": " + hipGetErrorString(e_));           \
+    } while (0)
+
+#define VIE_REQUIRE(cond, code, msg)                                   \
+    do {                                                               \
+        if (!(cond)) throw ::vie::Error((code), std::string(msg));     \
+    } while (0)
+
+}  // namespace vie

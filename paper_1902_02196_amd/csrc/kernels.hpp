@@ -1,0 +1,73 @@
+// Host-side launchers of the device kernels.
+#pragma once
+
+#include "assembly.hpp"
+#include "passes.hpp"
+
+namespace vie {
+
+// passes.hip
+template <typename R>
+void launch_strided(bool fwd, const C<R>* in, C<R>* out, const StridedPass& p, long long n_o2, long long n_o1,
+                    const C<R>* tw, const Epilogue<R>* ep, hipStream_t s);
+template <typename R>
+void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s);
+template <typename R>
+void launch_rows(bool fwd, C<R>* data, long long nrows, const FftPlan& plan, const C<R>* tw, hipStream_t s);
+
+// operator.hip
+AssemblyTables build_assembly_tables(const double D[3], double k0);
+void assemble_blocks(double2* out, const AssemblyTables& T, int Nx, int Ny, int Nz, hipStream_t s);
+int unique_refl_sign(int e, int axis);
+void embed_and_transform(double2* U128, float2* U64, const double2* T, double2* circ, int Nx, int Ny, int Nz,
+                         int Mx, int My, int Mz, const FftPlan plans[3], const double2* const tw[3], hipStream_t s);
+
+// setup.hip: materials, excitation, post-processing
+struct Materials {
+    double2* eps_r;   // per voxel
+    double2* chi;
+    double2* tau;
+    float2* tau64;
+    float2* epsr64;
+    float2* chi64;
+};
+void launch_materials(const double* eps_re, const double* sigma, double omega_eps0, Materials m, long long V,
+                      int* bad_flag, hipStream_t s);
+void launch_planewave(double2* et, int Nx, int Ny, int Nz, const double D[3], double k0, int pol, int dir,
+                      double sgn, double amp, hipStream_t s);
+void launch_dipoles(double2* et, int nrhs, const double* pos_dev, const double* mom_dev, int nq,
+                    const double* glx, const double* glw, const double2* chi, int Nx, int Ny, int Nz,
+                    const double D[3], double k0, double omega_eps0, hipStream_t s);
+void launch_rhs_prec(double2* rhs, const double2* et, const double2* tau, const double ginv[4], double2 ce,
+                     long long V, int nrhs, hipStream_t s);
+void launch_fields(double2* e, const double2* x, const double2* chi, double2 ce, long long V, int nrhs,
+                   hipStream_t s);
+void launch_power_partials(double* partial, const double2* x, const double2* chi, const double gram[4], double2 ce,
+                           long long V, int nrhs, int nblocks, hipStream_t s);
+void launch_power_density(double* p, const double2* e, const double* sigma, long long V, int nrhs, hipStream_t s);
+
+// krylov.hip: Gram-Schmidt and vector kernels, FP64 accumulation
+template <typename R>
+void launch_multidot(double2* partial, const C<R>* Vb, long long ldv, int nvec, const C<R>* w, long long n,
+                     long long rstride_v, long long rstride_w, int nrhs, int nblocks, hipStream_t s);
+void launch_reduce_partials(double2* out, const double2* partial, int nvec, int nblocks, int nrhs, hipStream_t s);
+template <typename R>
+void launch_update(C<R>* w, const C<R>* Vb, long long ldv, int nvec, const double2* h, long long n,
+                   long long rstride_v, long long rstride_w, double* norm_partial, int nrhs, int nblocks,
+                   hipStream_t s);
+void launch_reduce_norm(double* out, const double* partial, int nblocks, int nrhs, hipStream_t s);
+template <typename R>
+void launch_scale_into(C<R>* dst, const C<R>* src, const double* norms, long long n, long long rstride_dst,
+                       long long rstride_src, int nrhs, hipStream_t s);
+template <typename R>
+void launch_combine(double2* x, const C<R>* Vb, long long ldv, int nvec, const double2* y, long long n,
+                    long long rstride_v, int nrhs, hipStream_t s);
+template <typename R>
+void launch_norm_partials(double* partial, const C<R>* v, long long n, long long rstride, int nrhs, int nblocks,
+                          hipStream_t s);
+void launch_cast_down(float2* dst, const double2* src, const double* scale, long long n, int nrhs, hipStream_t s);
+void launch_cast_up(double2* dst, const float2* src, long long n, hipStream_t s);
+void launch_copy_c128(double2* dst, const double2* src, long long n, hipStream_t s);
+void launch_nonfinite(int* flag, const double2* v, long long n, hipStream_t s);
+
+}  // namespace vie

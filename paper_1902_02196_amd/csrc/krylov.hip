@@ -1,0 +1,290 @@
+// Arnoldi / GMRES vector kernels (Sec. V: restarted GMRES).  Inner products
+// and norms accumulate in FP64 whatever the storage precision; reductions run
+// in a fixed order (per-thread, wave, workgroup, then a separate pass over
+// workgroups), so results are bitwise reproducible.
+#include "kernels.hpp"
+
+namespace vie {
+
+constexpr int kTpb = 256;
+constexpr int kGroup = 8;   // basis vectors per sweep of the dot kernel
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename T> __device__ __forceinline__ double2 to_d2(T v) { return make_double2((double)v.x, (double)v.y); }
+
+// partial[(r * nvec + i) * nblocks + block] = sum over the block's elements of conj(V_i) w
+template <typename R>
+__global__ void __launch_bounds__(kTpb) k_multidot(double2* __restrict__ partial, const C<R>* __restrict__ Vb,
+                                                   long long ldv, int nvec, const C<R>* __restrict__ w, long long n,
+                                                   long long rsv, long long rsw) {
+    __shared__ double red[kTpb / 64][2 * kGroup];
+    const int r = blockIdx.y;
+    const C<R>* V = Vb + r * rsv;
+    const C<R>* wr = w + r * rsw;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long stride = (long long)gridDim.x * kTpb;
+    for (int i0 = 0; i0 < nvec; i0 += kGroup) {
+        const int ng = min(kGroup, nvec - i0);
+        double ar[kGroup], ai[kGroup];
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) ar[g] = ai[g] = 0.0;
+        for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < n; k += stride) {
+            const double2 wv = to_d2(wr[k]);
+#pragma unroll
+            for (int g = 0; g < kGroup; ++g) {
+                if (g < ng) {
+                    const double2 v = to_d2(V[(i0 + g) * ldv + k]);
+                    ar[g] += v.x * wv.x + v.y * wv.y;
+                    ai[g] += v.x * wv.y - v.y * wv.x;
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+            const double sr = wave_sum(ar[g]), si = wave_sum(ai[g]);
+            if (lane == 0) { red[wave][2 * g] = sr; red[wave][2 * g + 1] = si; }
+        }
+        __syncthreads();
+        if (threadIdx.x < ng) {
+            const int g = threadIdx.x;
+            double sr = 0, si = 0;
+            for (int wv = 0; wv < kTpb / 64; ++wv) { sr += red[wv][2 * g]; si += red[wv][2 * g + 1]; }
+            partial[((long long)r * nvec + i0 + g) * gridDim.x + blockIdx.x] = make_double2(sr, si);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename R>
+void launch_multidot(double2* partial, const C<R>* Vb, long long ldv, int nvec, const C<R>* w, long long n,
+                     long long rsv, long long rsw, int nrhs, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_multidot<R>, dim3(nblocks, nrhs), dim3(kTpb), 0, s, partial, Vb, ldv, nvec, w, n, rsv, rsw);
+    VIE_HIP(hipGetLastError());
+}
+
+__global__ void k_reduce_partials(double2* __restrict__ out, const double2* __restrict__ partial, int nblocks) {
+    // one wave per (r, i); fixed summation order
+    const long long row = blockIdx.x;
+    const double2* p = partial + row * nblocks;
+    double sr = 0, si = 0;
+    for (int b = threadIdx.x; b < nblocks; b += 64) { sr += p[b].x; si += p[b].y; }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (threadIdx.x == 0) out[row] = make_double2(sr, si);
+}
+
+void launch_reduce_partials(double2* out, const double2* partial, int nvec, int nblocks, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nvec * nrhs), dim3(64), 0, s, out, partial, nblocks);
+    VIE_HIP(hipGetLastError());
+}
+
+// w -= sum_i h_i V_i (FP64 arithmetic), and partial sums of |w|^2
+template <typename R>
+__global__ void __launch_bounds__(kTpb) k_update(C<R>* __restrict__ w, const C<R>* __restrict__ Vb, long long ldv,
+                                                 int nvec, const double2* __restrict__ h, long long n, long long rsv,
+                                                 long long rsw, double* __restrict__ norm_partial) {
+    __shared__ double red[kTpb / 64];
+    const int r = blockIdx.y;
+    const C<R>* V = Vb + r * rsv;
+    C<R>* wr = w + r * rsw;
+    const double2* hr = h + (long long)r * nvec;
+    double acc = 0.0;
+    for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < n; k += (long long)gridDim.x * kTpb) {
+        double2 wv = to_d2(wr[k]);
+        for (int i = 0; i < nvec; ++i) {
+            const double2 v = to_d2(V[i * ldv + k]);
+            const double2 hi = hr[i];
+            wv.x -= hi.x * v.x - hi.y * v.y;
+            wv.y -= hi.x * v.y + hi.y * v.x;
+        }
+        C<R> o;
+        o.x = (R)wv.x;
+        o.y = (R)wv.y;
+        wr[k] = o;
+        acc += (double)o.x * o.x + (double)o.y * o.y;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0;
+        for (int i = 0; i < kTpb / 64; ++i) s += red[i];
+        norm_partial[(long long)r * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+template <typename R>
+void launch_update(C<R>* w, const C<R>* Vb, long long ldv, int nvec, const double2* h, long long n, long long rsv,
+                   long long rsw, double* norm_partial, int nrhs, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_update<R>, dim3(nblocks, nrhs), dim3(kTpb), 0, s, w, Vb, ldv, nvec, h, n, rsv, rsw,
+                       norm_partial);
+    VIE_HIP(hipGetLastError());
+}
+
+__global__ void k_reduce_norm(double* __restrict__ out, const double* __restrict__ partial, int nblocks) {
+    const int r = blockIdx.x;
+    double s = 0;
+    for (int b = threadIdx.x; b < nblocks; b += 64) s += partial[(long long)r * nblocks + b];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) out[r] = sqrt(s);
+}
+
+void launch_reduce_norm(double* out, const double* partial, int nblocks, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_norm, dim3(nrhs), dim3(64), 0, s, out, partial, nblocks);
+    VIE_HIP(hipGetLastError());
+}
+
+template <typename R>
+__global__ void k_norm_partials(double* __restrict__ partial, const C<R>* __restrict__ v, long long n,
+                                long long rs) {
+    __shared__ double red[kTpb / 64];
+    const int r = blockIdx.y;
+    const C<R>* vr = v + r * rs;
+    double acc = 0;
+    for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < n; k += (long long)gridDim.x * kTpb) {
+        const double2 z = to_d2(vr[k]);
+        acc += z.x * z.x + z.y * z.y;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0;
+        for (int i = 0; i < kTpb / 64; ++i) s += red[i];
+        partial[(long long)r * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+template <typename R>
+void launch_norm_partials(double* partial, const C<R>* v, long long n, long long rs, int nrhs, int nblocks,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_norm_partials<R>, dim3(nblocks, nrhs), dim3(kTpb), 0, s, partial, v, n, rs);
+    VIE_HIP(hipGetLastError());
+}
+
+// dst = src / norm[r]
+template <typename R>
+__global__ void k_scale_into(C<R>* dst, const C<R>* src, const double* __restrict__ norms,
+                             long long n, long long rsd, long long rss) {
+    const int r = blockIdx.y;
+    const double nv = norms[r];
+    const double inv = nv > 0 ? 1.0 / nv : 0.0;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        const double2 z = to_d2(src[r * rss + k]);
+        C<R> o;
+        o.x = (R)(z.x * inv);
+        o.y = (R)(z.y * inv);
+        dst[r * rsd + k] = o;
+    }
+}
+
+template <typename R>
+void launch_scale_into(C<R>* dst, const C<R>* src, const double* norms, long long n, long long rsd, long long rss,
+                       int nrhs, hipStream_t s) {
+    const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_scale_into<R>, dim3(nb, nrhs), dim3(256), 0, s, dst, src, norms, n, rsd, rss);
+    VIE_HIP(hipGetLastError());
+}
+
+// x (complex128) += sum_i y_i V_i
+template <typename R>
+__global__ void k_combine(double2* __restrict__ x, const C<R>* __restrict__ Vb, long long ldv, int nvec,
+                          const double2* __restrict__ y, long long n, long long rsv) {
+    const int r = blockIdx.y;
+    const C<R>* V = Vb + r * rsv;
+    double2* xr = x + (long long)r * n;
+    const double2* yr = y + (long long)r * nvec;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        double2 acc = xr[k];
+        for (int i = 0; i < nvec; ++i) {
+            const double2 v = to_d2(V[i * ldv + k]);
+            acc.x += yr[i].x * v.x - yr[i].y * v.y;
+            acc.y += yr[i].x * v.y + yr[i].y * v.x;
+        }
+        xr[k] = acc;
+    }
+}
+
+template <typename R>
+void launch_combine(double2* x, const C<R>* Vb, long long ldv, int nvec, const double2* y, long long n,
+                    long long rsv, int nrhs, hipStream_t s) {
+    const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_combine<R>, dim3(nb, nrhs), dim3(256), 0, s, x, Vb, ldv, nvec, y, n, rsv);
+    VIE_HIP(hipGetLastError());
+}
+
+// dst (complex64) = src * scale[r]
+__global__ void k_cast_down(float2* __restrict__ dst, const double2* __restrict__ src, const double* __restrict__ sc,
+                            long long n) {
+    const int r = blockIdx.y;
+    const double s = sc ? sc[r] : 1.0;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        const double2 z = src[(long long)r * n + k];
+        dst[(long long)r * n + k] = make_float2((float)(z.x * s), (float)(z.y * s));
+    }
+}
+
+void launch_cast_down(float2* dst, const double2* src, const double* scale, long long n, int nrhs, hipStream_t s) {
+    const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_cast_down, dim3(nb, nrhs), dim3(256), 0, s, dst, src, scale, n);
+    VIE_HIP(hipGetLastError());
+}
+
+__global__ void k_cast_up(double2* __restrict__ dst, const float2* __restrict__ src, long long n) {
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x)
+        dst[k] = make_double2(src[k].x, src[k].y);
+}
+
+void launch_cast_up(double2* dst, const float2* src, long long n, hipStream_t s) {
+    const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_cast_up, dim3(nb), dim3(256), 0, s, dst, src, n);
+    VIE_HIP(hipGetLastError());
+}
+
+__global__ void k_copy(double2* __restrict__ dst, const double2* __restrict__ src, long long n) {
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x)
+        dst[k] = src[k];
+}
+
+void launch_copy_c128(double2* dst, const double2* src, long long n, hipStream_t s) {
+    const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, dst, src, n);
+    VIE_HIP(hipGetLastError());
+}
+
+__global__ void k_nonfinite(int* flag, const double2* __restrict__ v, long long n) {
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x)
+        if (!isfinite(v[k].x) || !isfinite(v[k].y)) atomicOr(flag, 1);
+}
+
+void launch_nonfinite(int* flag, const double2* v, long long n, hipStream_t s) {
+    const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_nonfinite, dim3(nb), dim3(256), 0, s, flag, v, n);
+    VIE_HIP(hipGetLastError());
+}
+
+#define INST(R)                                                                                                  \
+    template void launch_multidot<R>(double2*, const C<R>*, long long, int, const C<R>*, long long, long long,  \
+                                     long long, int, int, hipStream_t);                                          \
+    template void launch_update<R>(C<R>*, const C<R>*, long long, int, const double2*, long long, long long,   \
+                                   long long, double*, int, int, hipStream_t);                                   \
+    template void launch_scale_into<R>(C<R>*, const C<R>*, const double*, long long, long long, long long, int, \
+                                       hipStream_t);                                                             \
+    template void launch_combine<R>(double2*, const C<R>*, long long, int, const double2*, long long, long long, \
+                                    int, hipStream_t);                                                           \
+    template void launch_norm_partials<R>(double*, const C<R>*, long long, long long, int, int, hipStream_t);
+INST(float)
+INST(double)
+
+}  // namespace vie

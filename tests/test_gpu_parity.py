@@ -1,0 +1,229 @@
+"""GPU parity of the HIP library against the oracle, through the C ABI.
+
+Tolerances: operator products agree with the oracle's direct voxel-pair sum
+within 1e-11 (complex128) and 1e-5 (complex64) relative (max-norm over the
+result).  Block tensors assembled on the device agree with the oracle's
+independent quadrature within 1e-10 relative to the largest entry of each
+offset.  Solves are compared with the oracle's exact (dense LU) solution.
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import vie_inputs as vi
+from oracle import incident, matvec, physics, post, solve, toeplitz
+from tests.layout import relerr, unique_from_full, unique_from_octant, vec_from_lib, vec_to_lib, vox_to_lib
+
+pytestmark = pytest.mark.gpu
+
+F = 298e6
+K = physics.k0(F)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def vie(torch):
+    import paper_1902_02196_amd as v
+    return v
+
+
+@functools.lru_cache(None)
+def _full_blocks(N, D):
+    return toeplitz.toeplitz_full(N, D, K)
+
+
+def _ctx(vie, torch, N, D, T_full=None):
+    c = vie.Context(0)
+    c.set_grid(N, D, F)
+    if T_full is not None:
+        c.set_toeplitz(unique_from_full(T_full))
+    return c
+
+
+def _to_dev(torch, x_oracle, dtype):
+    return torch.from_numpy(vec_to_lib(x_oracle)[None]).to(device="cuda", dtype=dtype).contiguous()
+
+
+def _from_dev(y):
+    return vec_from_lib(y[0].cpu().numpy())
+
+
+CASES = [((4, 4, 4), (0.005, 0.005, 0.005)), ((5, 3, 6), (0.006, 0.005, 0.004)), ((8, 8, 8), (0.005,) * 3),
+         ((1, 2, 3), (0.004, 0.006, 0.005)), ((7, 4, 9), (0.005, 0.004, 0.006))]
+
+
+@pytest.mark.parametrize("N,D", CASES)
+def test_matvec_N_parity_same_blocks(vie, torch, N, D):
+    """FFT product on the device vs the direct voxel-pair sum, both fed the
+    oracle's block tensors (ragged sizes, non-smooth 2N padded to smooth M)."""
+    _say("matvec N parity %s" % (N,))
+    T = _full_blocks(N, D)
+    c = _ctx(vie, torch, N, D, T)
+    x = vi.complex_normal(11, (12,) + N)
+    ref = matvec.direct_N(T, x)
+    for dtype, tol in ((torch.complex128, 1e-11), (torch.complex64, 1e-5)):
+        xd = _to_dev(torch, x, dtype)
+        yd = torch.empty_like(xd)
+        c.apply(xd, yd, op=vie.OP_N)
+        torch.cuda.synchronize()
+        err = relerr(_from_dev(yd), ref)
+        _say("  %s err %.3e" % (dtype, err))
+        assert err < tol
+
+
+@pytest.mark.parametrize("N,D", CASES[:3])
+def test_device_assembly_matches_oracle(vie, torch, N, D):
+    """Block tensors assembled on the device (closed-form axis kernels, own
+    quadrature) vs the oracle's (quadrature-evaluated correlations)."""
+    _say("assembly parity %s" % (N,))
+    c = _ctx(vie, torch, N, D)
+    lib = c.get_toeplitz()
+    ref = unique_from_octant(toeplitz.toeplitz_octant(N, D, K))
+    for iz in range(N[2]):
+        for iy in range(N[1]):
+            for ix in range(N[0]):
+                a, b = lib[:, iz, iy, ix], ref[:, iz, iy, ix]
+                assert np.abs(a - b).max() <= 1e-10 * np.abs(b).max(), (ix, iy, iz)
+
+
+@pytest.mark.parametrize("N,D", CASES[:2])
+def test_preconditioned_and_plain_operators(vie, torch, N, D):
+    """P^-1 A (eq. 17) and A (eq. 24a) with a heterogeneous phantom, library
+    assembly, vs the oracle with its own blocks."""
+    _say("operators %s" % (N,))
+    c = _ctx(vie, torch, N, D)
+    e, s = vi.ellipsoid_phantom(N, D, 3)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    T = _full_blocks(N, D)
+    x = vi.complex_normal(12, (12,) + N)
+    er, ch, ta = physics.eps_r(e, s, F), physics.chi(e, s, F), physics.tau(e, s, F)
+    for op, ref in ((vie.OP_PREC, matvec.apply_prec(T, x, ta, D)), (vie.OP_A, matvec.apply_A(T, x, er, ch, D))):
+        for dtype, tol in ((torch.complex128, 1e-10), (torch.complex64, 1e-5)):
+            xd = _to_dev(torch, x, dtype)
+            yd = torch.empty_like(xd)
+            c.apply(xd, yd, op=op)
+            torch.cuda.synchronize()
+            err = relerr(_from_dev(yd), ref)
+            _say("  op %d %s err %.3e" % (op, dtype, err))
+            assert err < tol
+
+
+def test_batched_apply_equals_single(vie, torch):
+    """Several right-hand sides in one launch give the same result as one at
+    a time (bitwise: no cross-RHS reductions in the product)."""
+    N, D = (6, 5, 4), (0.005,) * 3
+    c = _ctx(vie, torch, N, D)
+    e, s = vi.ellipsoid_phantom(N, D, 4)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    xs = np.stack([vec_to_lib(vi.complex_normal(20 + r, (12,) + N)) for r in range(3)])
+    for dtype in (torch.complex64, torch.complex128):
+        xd = torch.from_numpy(xs).to("cuda", dtype)
+        yd = torch.empty_like(xd)
+        c.apply(xd, yd, op=vie.OP_PREC)
+        for r in range(3):
+            y1 = torch.empty_like(xd[r:r + 1])
+            c.apply(xd[r:r + 1].contiguous(), y1, op=vie.OP_PREC)
+            assert torch.equal(y1[0], yd[r])
+
+
+def test_planewave_and_rhs(vie, torch):
+    N, D = (5, 4, 6), (0.006, 0.005, 0.004)
+    c = _ctx(vie, torch, N, D)
+    e, s = vi.sphere(N, D, 0.012, 50.0, 0.7)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    et = torch.empty(c.vec_shape(1), dtype=torch.complex128, device="cuda")
+    c.incident_planewave(et)
+    ref = incident.planewave_tested(N, D, K)
+    assert relerr(_from_dev(et), ref) < 1e-13
+    rhs = torch.empty_like(et)
+    c.rhs_prec(et, rhs)
+    assert relerr(_from_dev(rhs), matvec.rhs_prec(ref, physics.tau(e, s, F), D, F)) < 1e-13
+
+
+def test_dipole_rhs(vie, torch):
+    N, D = (6, 5, 4), (0.005,) * 3
+    c = _ctx(vie, torch, N, D)
+    e, s = vi.ellipsoid_phantom(N, D, 5)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    pos, mom = vi.dipoles_on_cylinder(7, 2, 0.03, N[2] * D[2])
+    et = torch.empty(c.vec_shape(2), dtype=torch.complex128, device="cuda")
+    c.incident_dipoles(et, pos, mom, nq=6)
+    chi = physics.chi(e, s, F)
+    ref = incident.dipoles_tested(N, D, F, pos, mom, chi != 0, nq=6)
+    for r in range(2):
+        assert relerr(vec_from_lib(et[r].cpu().numpy()), ref[r]) < 1e-12
+
+
+@pytest.mark.parametrize("mode,tol,bound", [(0, 1e-12, 1e-9), (1, 1e-10, 1e-7)])
+def test_solve_matches_dense(vie, torch, mode, tol, bound):
+    """GMRES on the device (FP64, and FP32 + FP64 refinement) vs the oracle's
+    exact discrete solution by dense LU (4 x 4 x 4 sphere, config-1 material)."""
+    _say("solve mode %d" % mode)
+    N, D = (4, 4, 4), (0.005,) * 3
+    T = _full_blocks(N, D)
+    c = _ctx(vie, torch, N, D)
+    e, s = vi.sphere(N, D, 0.0101, 50.0, 0.7)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    tau, chi = physics.tau(e, s, F), physics.chi(e, s, F)
+    et = incident.planewave_tested(N, D, K)
+    xref = solve.solve_dense(T, tau, D, matvec.rhs_prec(et, tau, D, F))
+    etd = _to_dev(torch, et, torch.complex128)
+    xd = torch.empty_like(etd)
+    code, st = c.solve(etd, xd, mode=mode, tol=tol, restart=20)
+    _say("  stats %s" % st[0])
+    assert code == vie.VIE_OK and st[0]["converged"]
+    err = relerr(_from_dev(xd), xref)
+    _say("  err %.3e" % err)
+    assert err < bound
+    P = c.absorbed_power(xd)[0]
+    assert abs(P - post.absorbed_power(xref, chi, D, F)) / abs(P) < 10 * bound
+
+
+def test_fields_and_power_density(vie, torch):
+    N, D = (4, 3, 5), (0.005,) * 3
+    c = _ctx(vie, torch, N, D)
+    e, s = vi.ellipsoid_phantom(N, D, 9)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    x = vi.complex_normal(13, (12,) + N)
+    xd = _to_dev(torch, x, torch.complex128)
+    ed = torch.empty_like(xd)
+    c.fields(xd, ed)
+    chi = physics.chi(e, s, F)
+    eref = post.fields_from_currents(x, chi, F)
+    assert relerr(_from_dev(ed), eref) < 1e-14
+    pd = torch.empty((1,) + tuple(reversed(N)), dtype=torch.float64, device="cuda")
+    c.power_density(ed, pd)
+    assert relerr(pd[0].cpu().numpy().transpose(2, 1, 0), post.power_density(eref, s)) < 1e-13
+    P = c.absorbed_power(xd)[0]
+    assert abs(P - post.absorbed_power(x, chi, D, F)) / abs(P) < 1e-12
+
+
+def test_errors_are_reported(vie, torch):
+    c = vie.Context(0)
+    with pytest.raises(vie.VieError):
+        c.set_grid((4, 4, 4), (0.005, -1.0, 0.005), F)
+    c.set_grid((4, 4, 4), (0.005,) * 3, F)
+    e = np.ones((4, 4, 4))
+    s = np.zeros((4, 4, 4))
+    s[0, 0, 0] = np.nan
+    with pytest.raises(vie.VieError) as ei:
+        c.set_contrast(e, s)
+    assert ei.value.code == vie.VIE_ENAN
+    x = torch.zeros(c.vec_shape(1), dtype=torch.complex128, device="cuda")
+    with pytest.raises(vie.VieError) as ei:
+        c.apply(x, torch.empty_like(x), op=vie.OP_PREC)   # no contrast yet
+    assert ei.value.code == vie.VIE_ESTATE
