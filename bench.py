@@ -1,0 +1,217 @@
+"""Benchmark: solves/s of the PWL current-based VIE on one MI355X.
+
+Workload (default): 64 x 64 x 64 voxels at 3 mm, 298 MHz, a seeded 6-class
+ellipsoid tissue phantom (eps' ~ U[5, 80], sigma ~ U[0.05, 2] S/m), x-polarised
+plane wave along z; left-preconditioned GMRES(50) to 1e-6 relative residual,
+complex64 Krylov solves inside FP64 iterative refinement.  One step = one full
+solve from x = 0 (operator products, Gram-Schmidt, refinement residuals) with
+the operator, contrast and right-hand side already resident in HBM; operator
+assembly is timed separately as set-up.
+
+Printed as one JSON line: the metric, the plain FP64 solve rate for
+comparison, the operator-product bandwidth, the roofline of the kernel that
+takes the most device time (HIP events on the library stream over the timed
+region, algorithmic bytes per launch), and the oracle's rate on this host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "phantom64": dict(N=(64, 64, 64), h=0.003, f=298e6, seed=190202196 + 1),
+    "sphere16": dict(N=(16, 16, 16), h=0.005, f=298e6, seed=None),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(N, h, f, mv_per_solve, seconds_budget=25.0):
+    """The oracle's FFT operator product (FP64, scipy.fft) on this host's cores,
+    timed on a bounded sample: a few products of the same grid; the solve rate
+    is that time times the FP64 solver's operator products per solve.  The
+    oracle's own block assembly is not included (random blocks of the right
+    shape: values do not change the time)."""
+    import scipy.fft
+    from oracle import matvec
+    import vie_inputs as vi
+    cores = min(16, os.cpu_count() or 1)
+    Nx, Ny, Nz = N
+    T = vi.complex_normal(5, (12, 12, 2 * Nx - 1, 2 * Ny - 1, 2 * Nz - 1))
+    M = (2 * Nx, 2 * Ny, 2 * Nz)
+    t0 = time.perf_counter()
+    Ch = matvec.circulant_spectrum(T, M, workers=cores)
+    del T
+    t_setup = time.perf_counter() - t0
+    x = vi.complex_normal(6, (12,) + tuple(N))
+    times = []
+    t_start = time.perf_counter()
+    while len(times) < 3 and (time.perf_counter() - t_start) < seconds_budget:
+        t0 = time.perf_counter()
+        matvec.fft_N(Ch, x, workers=cores)
+        times.append(time.perf_counter() - t0)
+    t_mv = float(np.median(times))
+    return {"value": 1.0 / (t_mv * mv_per_solve), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": "%d oracle FFT operator products (FP64, scipy.fft, %d workers) on the %dx%dx%d grid, "
+                      "%.2f s each, times %d products per FP64 solve; spectrum set-up %.1f s excluded"
+                      % (len(times), cores, Nx, Ny, Nz, t_mv, mv_per_solve, t_setup)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="phantom64", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--reorth", type=int, default=0, help="second Gram-Schmidt pass (1) or not (0)")
+    ap.add_argument("--restart", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1902_02196_amd as vie
+    import vie_inputs as vi
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    W = WORKLOADS[args.workload]
+    N, h, f = W["N"], W["h"], W["f"]
+    D = (h, h, h)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    t0 = time.perf_counter()
+    ctx = vie.Context(0, stream)
+    ctx.set_grid(N, D, f)
+    torch.cuda.synchronize()
+    t_grid = time.perf_counter() - t0
+    if W["seed"] is None:
+        e, s = vi.sphere(N, D, 0.03, 50.0, 0.7)
+    else:
+        e, s = vi.ellipsoid_phantom(N, D, W["seed"])
+    ctx.set_contrast(np.ascontiguousarray(e.transpose(2, 1, 0)), np.ascontiguousarray(s.transpose(2, 1, 0)))
+    et = torch.empty(ctx.vec_shape(1), dtype=torch.complex128, device=dev)
+    ctx.incident_planewave(et)
+    x = torch.empty_like(et)
+    log("setup: grid+operator %.2f s" % t_grid)
+
+    opts_ir = vie.default_opts(mode=vie.SOLVE_FP32_IR, tol=1e-6, restart=args.restart, inner_tol=1e-5,
+                               reorth=args.reorth)
+    opts_64 = vie.default_opts(mode=vie.SOLVE_FP64, tol=1e-6, restart=args.restart, reorth=args.reorth)
+    for i in range(args.warmup):
+        code, st = ctx.solve(et, x, opts_ir)
+        log("warmup %d: %s" % (i, st[0]))
+
+    # timed region: K full solves
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        code, st = ctx.solve(et, x, opts_ir)
+        stats.append(st[0])
+        log("step %d: %s" % (i, st[0]))
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    assert code == vie.VIE_OK, "IR solve did not converge: %s" % stats[-1]
+    x_ir = x.clone()
+
+    # FP64 path for comparison (same timing discipline, one solve)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    code64, st64 = ctx.solve(et, x, opts_64)
+    torch.cuda.synchronize()
+    t_64 = time.perf_counter() - t0
+    log("fp64: %s" % st64[0])
+    x64 = x.clone()
+    e_ir = torch.empty_like(x_ir)
+    e_64 = torch.empty_like(x64)
+    ctx.fields(x_ir, e_ir)
+    ctx.fields(x64, e_64)
+    P_ir = ctx.absorbed_power(x_ir)[0]
+    P_64 = ctx.absorbed_power(x64)[0]
+    field_err = float(torch.linalg.vector_norm(e_ir - e_64) / torch.linalg.vector_norm(e_64))
+
+    # operator product alone (complex64, preconditioned), for GB/s
+    xv = torch.randn(ctx.vec_shape(1), dtype=torch.complex64, device=dev)
+    yv = torch.empty_like(xv)
+    for _ in range(3):
+        ctx.apply(xv, yv, op=vie.OP_PREC)
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nmv = 20
+    for _ in range(nmv):
+        ctx.apply(xv, yv, op=vie.OP_PREC)
+    torch.cuda.synchronize()
+    t_mv = (time.perf_counter() - t0) / nmv
+    mvprof = ctx.profile_read()
+    ctx.profile(False)
+    mv_bytes = sum(v[2] for k, v in mvprof.items() if k != "arnoldi") / nmv
+    mv_dev_ms = sum(v[0] for k, v in mvprof.items() if k != "arnoldi") / nmv
+
+    # roofline of the kernel class with the most device time in the timed solves
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, nl, by = prof[dom]
+    achieved = (by / nl) / (ms / nl * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "avg_launch_us": round(ms / nl * 1e3, 2), "bytes_per_launch": by / nl}
+    kernels = {k: {"ms": round(v[0], 3), "launches": v[1],
+                   "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None} for k, v in prof.items()}
+
+    sps = args.steps / t_total
+    out = {
+        "metric": "solves/s at 1e-6 relative residual (FP32 + FP64 refinement)",
+        "value": round(sps, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_total / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 (FP64 refinement)",
+        "data": "synthetic",
+        "config": {"workload": "%s: %dx%dx%d voxels at %.0f mm, %.0f MHz, %s, x-polarised plane wave, "
+                               "GMRES(50) to 1e-6, complex64 + FP64 refinement"
+                               % (args.workload, N[0], N[1], N[2], h * 1e3, f / 1e6,
+                                  "6-class ellipsoid phantom" if W["seed"] else "eps 50 sigma 0.7 sphere r=3 cm")},
+        "fp64_solves_per_s": round(1.0 / t_64, 4),
+        "ir_vs_fp64_speedup": round(sps * t_64, 3),
+        "field_rel_err_ir_vs_fp64": field_err,
+        "p_abs_ir_vs_fp64": abs(P_ir - P_64) / abs(P_64),
+        "iterations_ir": stats[-1]["iterations"],
+        "iterations_fp64": st64[0]["iterations"],
+        "matvec_c64_ms": round(t_mv * 1e3, 4),
+        "matvec_c64_device_ms": round(mv_dev_ms, 4),
+        "matvec_c64_GBps_algorithmic": round(mv_bytes / (mv_dev_ms * 1e-3) / 1e9, 1),
+        "setup_s": round(t_grid, 3),
+        "kernels": kernels,
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        mv_per_solve = st64[0]["matvecs_c128"]
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(N, h, f, mv_per_solve)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -185,6 +185,29 @@ int vie_absorbed_power(vie_ctx* ctx, int nrhs, const void* x, double* p_abs_host
  * FP64 device array [nrhs][Nz][Ny][Nx], from field coefficients e. */
 int vie_power_density(vie_ctx* ctx, int nrhs, const void* e, double* p_dev);
 
+/* -- profiling ------------------------------------------------------------ */
+
+/* kernel classes timed by the built-in profiler */
+enum {
+    VIE_K_FFT_Z_FWD = 0,  /* zero-padded forward FFT along z                  */
+    VIE_K_FFT_Y_FWD = 1,  /* zero-padded forward FFT along y                  */
+    VIE_K_BLOCK = 2,      /* fused x FFT, 12 x 12 block product, inverse x FFT */
+    VIE_K_FFT_Y_INV = 3,  /* inverse FFT along y with crop                    */
+    VIE_K_FFT_Z_INV = 4,  /* inverse FFT along z, crop, contrast epilogue     */
+    VIE_K_ARNOLDI = 5,    /* Gram-Schmidt kernels (dots, updates, norms)      */
+    VIE_K_COUNT = 6
+};
+
+/* enable = 1 clears the records and starts timing every launch of the
+ * classes above with HIP events on the context stream; enable = 0 stops. */
+int vie_profile(vie_ctx* ctx, int enable);
+
+/* Sum over the recorded launches of one class: device time (ms, from HIP
+ * events), launch count, and algorithmic HBM bytes (the minimum traffic of
+ * each launch: its inputs read once and its outputs written once).
+ * Synchronises the stream. */
+int vie_profile_read(vie_ctx* ctx, int kind, double* total_ms, int* launches, double* bytes);
+
 /* -- memory model (Sec. V, "unknowns memory") ------------------------------ */
 
 /* Bytes the paper counts as unknowns memory: 12 unknowns x 8 N_V padded

@@ -23,6 +23,7 @@ VIE_OK, VIE_EINVAL, VIE_ENOMEM, VIE_EDEVICE, VIE_ENOCONV, VIE_ENAN, VIE_ESTATE =
 C64, C128 = 0, 1
 OP_PREC, OP_A, OP_N = 0, 1, 2
 SOLVE_FP64, SOLVE_FP32_IR = 0, 1
+KERNELS = ("fft_z_fwd", "fft_y_fwd", "block", "fft_y_inv", "fft_z_inv", "arnoldi")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libvie.so is not built; run `python -m paper_1902_02196_amd.build` (needs hipcc)")
@@ -65,6 +66,8 @@ _sig = {
     "vie_fields": (_i, [_vp, _i, _vp, _vp]),
     "vie_absorbed_power": (_i, [_vp, _i, _vp, _dp]),
     "vie_power_density": (_i, [_vp, _i, _vp, _vp]),
+    "vie_profile": (_i, [_vp, _i]),
+    "vie_profile_read": (_i, [_vp, _i, _dp, ctypes.POINTER(_i), _dp]),
     "vie_unknowns_bytes_paper": (ctypes.c_size_t, [_i, _i, _i]),
     "vie_footprint_bytes": (_i, [_i, _i, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_size_t)]),
 }
@@ -241,6 +244,18 @@ class Context:
         n = x.shape[0]
         out = np.zeros(n)
         _check(_lib.vie_absorbed_power(self._h, n, _tensor_ptr(x, torch.complex128, self.vec_shape(n)), _dptr(out)))
+        return out
+
+    def profile(self, enable=True):
+        _check(_lib.vie_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel class: (total ms, launches, algorithmic bytes)}"""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            ms, n, b = ctypes.c_double(0), ctypes.c_int(0), ctypes.c_double(0)
+            _check(_lib.vie_profile_read(self._h, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+            out[name] = (ms.value, n.value, b.value)
         return out
 
     def power_density(self, e, out):

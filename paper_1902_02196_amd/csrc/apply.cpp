@@ -15,6 +15,7 @@
 #include <algorithm>
 
 #include "ctx.hpp"
+#include "fft_ct.hpp"
 
 namespace vie {
 
@@ -62,7 +63,11 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     p1.out_s1 = sA1;
     p1.out_s2 = Nx;
     p1.out_sk = (long long)Ny * Nx;
-    launch_strided<R>(true, x, A1, p1, Ny, B, twid<R>(c.ax[2]), nullptr, s);
+    const double bV = (double)B * V * es, bA1 = (double)B * sA1 * es, bA2 = (double)B * sA2 * es;
+    {
+        ProfScope ps(c.prof, s, VIE_K_FFT_Z_FWD, bV + bA1);
+        launch_strided<R>(true, x, A1, p1, Ny, B, twid<R>(c.ax[2]), nullptr, s);
+    }
 
     // P2: y
     StridedPass p2{};
@@ -78,7 +83,10 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     p2.out_s1 = sA2;
     p2.out_s2 = (long long)My * Nx;
     p2.out_sk = Nx;
-    launch_strided<R>(true, A1, A2, p2, Mz, B, twid<R>(c.ax[1]), nullptr, s);
+    {
+        ProfScope ps(c.prof, s, VIE_K_FFT_Y_FWD, bA1 + bA2);
+        launch_strided<R>(true, A1, A2, p2, Mz, B, twid<R>(c.ax[1]), nullptr, s);
+    }
 
     // P3: x, block product
     P3Params p3{};
@@ -95,7 +103,31 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     p3.s_y = Nx;
     p3.u_e = c.Osz;
     p3.pitch = Mx;
-    launch_p3<R>(A2, opspec<R>(c), p3, twid<R>(c.ax[0]), s);
+    {
+        // as many pencil groups per LDS pass as fit 64 KiB and the
+        // butterfly bound of the in-place passes (at most 4 siblings share
+        // an octant row)
+        // LDS holds the operator row (60 Ox) plus the pencil groups
+        const int nt = p3_threads<R>();
+        const size_t ul = 60 * (size_t)c.O[0] * es;
+        int g = 4;
+        while (g > 1 && (ul + (size_t)lds_pad(g * 12 * Mx) * es > 80 * 1024 || !rows_fit(p3.plan, g * 12, nt) ||
+                         2 * g * Mx > nt))
+            --g;
+        if (p3_ct_supported(Mx)) {
+            g = p3_ct_groups((int)es, Mx);
+        } else {
+            VIE_REQUIRE(rows_fit(p3.plan, 12, nt) && 2 * Mx <= nt && ul + (size_t)lds_pad(12 * Mx) * es <= 150 * 1024,
+                        VIE_EINVAL, "fft size along x too large");
+        }
+        p3.groups = g;
+        p3.magic_nx = magic_for((unsigned)Nx);
+        p3.magic_ox = magic_for((unsigned)c.O[0]);
+    }
+    {
+        ProfScope ps(c.prof, s, VIE_K_BLOCK, 2 * bA2 + 60.0 * c.Osz * es);
+        launch_p3<R>(A2, opspec<R>(c), p3, twid<R>(c.ax[0]), s);
+    }
 
     // P4: inverse y, crop
     StridedPass p4 = p2;
@@ -107,7 +139,10 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     p4.out_s1 = sA1;
     p4.out_s2 = (long long)Ny * Nx;
     p4.out_sk = Nx;
-    launch_strided<R>(false, A2, A1, p4, Mz, B, twid<R>(c.ax[1]), nullptr, s);
+    {
+        ProfScope ps(c.prof, s, VIE_K_FFT_Y_INV, bA2 + bA1);
+        launch_strided<R>(false, A2, A1, p4, Mz, B, twid<R>(c.ax[1]), nullptr, s);
+    }
 
     // P5: inverse z, crop, epilogue
     StridedPass p5 = p1;
@@ -166,7 +201,17 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
                 break;
         }
     }
-    launch_strided<R>(false, A1, y, p5, Ny, B, twid<R>(c.ax[2]), &ep, s);
+    {
+        // inverse z pass: intermediate in, result out, plus the epilogue's x,
+        // right-hand side and per-voxel coefficient reads
+        double extra = 0;
+        if (ep.a_const != R(0) || ep.a) extra += bV;
+        if (ep.rhs) extra += bV;
+        if (ep.a) extra += (double)V * es;
+        if (ep.b) extra += (double)V * es;
+        ProfScope ps(c.prof, s, VIE_K_FFT_Z_INV, bA1 + bV + extra);
+        launch_strided<R>(false, A1, y, p5, Ny, B, twid<R>(c.ax[2]), &ep, s);
+    }
 }
 
 template void apply_op<float>(Ctx&, int, int, const C<float>*, C<float>*, const C<float>*);

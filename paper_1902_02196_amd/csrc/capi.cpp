@@ -333,7 +333,7 @@ void vie_default_opts(vie_solve_opts* o) {
     o->tol = 1e-6;
     o->inner_tol = 1e-5;
     o->max_refine = 400;
-    o->reorth = 1;
+    o->reorth = 0;
     o->use_x0 = 0;
 }
 
@@ -402,6 +402,40 @@ int vie_power_density(vie_ctx* ctx, int nrhs, const void* e, double* p_dev) {
         VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "no contrast");
         VIE_REQUIRE(nrhs >= 1 && e && p_dev, VIE_EINVAL, "bad arguments");
         launch_power_density(p_dev, static_cast<const double2*>(e), c.sigma, c.V, nrhs, c.stream);
+    });
+}
+
+int vie_profile(vie_ctx* ctx, int enable) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_HIP(hipStreamSynchronize(c.stream));
+        if (enable) c.prof.clear();
+        c.prof.on = enable != 0;
+    });
+}
+
+int vie_profile_read(vie_ctx* ctx, int kind, double* total_ms, int* launches, double* bytes) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(kind >= 0 && kind < VIE_K_COUNT, VIE_EINVAL, "unknown kernel class");
+        VIE_HIP(hipStreamSynchronize(c.stream));
+        double ms = 0, b = 0;
+        int n = 0;
+        for (const auto& r : c.prof.recs) {
+            if (r.kind != kind) continue;
+            float t = 0;
+            VIE_HIP(hipEventElapsedTime(&t, r.a, r.b));
+            ms += t;
+            b += r.bytes;
+            ++n;
+        }
+        if (total_ms) *total_ms = ms;
+        if (launches) *launches = n;
+        if (bytes) *bytes = b;
     });
 }
 

@@ -3,7 +3,7 @@
 
 #include <vector>
 
-#include "../../include/vie.h"
+#include "vie.h"
 #include "kernels.hpp"
 
 namespace vie {
@@ -38,6 +38,47 @@ struct Scratch {
     }
 };
 
+// HIP-event timing of kernel launches, by class
+struct Profiler {
+    struct Rec { int kind; hipEvent_t a, b; double bytes; };
+    bool on = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t take() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e;
+        VIE_HIP(hipEventCreate(&e));
+        return e;
+    }
+    void clear() {
+        for (auto& r : recs) { pool.push_back(r.a); pool.push_back(r.b); }
+        recs.clear();
+    }
+    ~Profiler() {
+        clear();
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+// RAII scope that records one launch when profiling is on
+struct ProfScope {
+    Profiler& p;
+    hipStream_t s;
+    int kind;
+    double bytes;
+    hipEvent_t a = nullptr;
+    ProfScope(Profiler& p_, hipStream_t s_, int k, double b) : p(p_), s(s_), kind(k), bytes(b) {
+        if (p.on) { a = p.take(); VIE_HIP(hipEventRecord(a, s)); }
+    }
+    ~ProfScope() {
+        if (p.on && a) {
+            hipEvent_t b_ = p.take();
+            (void)hipEventRecord(b_, s);
+            p.recs.push_back(Profiler::Rec{kind, a, b_, bytes});
+        }
+    }
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -65,6 +106,8 @@ struct Ctx {
 
     // solver scratch
     Scratch basis, vecs;
+
+    Profiler prof;
 
     ~Ctx();
     void free_grid();

@@ -99,39 +99,33 @@ __device__ __forceinline__ void dft8(C<R>* v) {
 
 template <typename R, bool FWD>
 __device__ __forceinline__ void dft16(C<R>* v) {
-    // 16 = 4 x 4: length-4 DFTs over m for each q (a_{4m+q}), twiddle
-    // W16^{q k1}, then length-4 DFTs over q; output index k1 + 4 k2.
-    C<R> z[16];
+    // 16 = 4 x 4: length-4 DFTs over m of a_{4m+q} for each q (in place, so
+    // v[q + 4 k1] = Z_q[k1]), twiddles W16^{q k1}, length-4 DFTs over q for
+    // each k1 (v[4 k1 + q] -> index k2), output index k1 + 4 k2.
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        C<R> a0 = v[q], a1 = v[4 + q], a2 = v[8 + q], a3 = v[12 + q];
-        dft4<R, FWD>(a0, a1, a2, a3);
-        z[q * 4 + 0] = a0;
-        z[q * 4 + 1] = a1;
-        z[q * 4 + 2] = a2;
-        z[q * 4 + 3] = a3;
-    }
-    // twiddles W16^{q k1}, q, k1 in 1..3
+    for (int q = 0; q < 4; ++q) dft4<R, FWD>(v[q], v[4 + q], v[8 + q], v[12 + q]);
     const R c1 = R(0.92387953251128675613), s1 = R(0.38268343236508977173);
     const R c2 = R(0.70710678118654752440);
     const R sg = FWD ? R(-1) : R(1);
-    // exp(sg i 2 pi m / 16) for m = 1..9
-    const C<R> w[10] = {mk<R>(1, 0),       mk<R>(c1, sg * s1), mk<R>(c2, sg * c2), mk<R>(s1, sg * c1),
-                        mk<R>(0, sg),      mk<R>(-s1, sg * c1), mk<R>(-c2, sg * c2), mk<R>(-c1, sg * s1),
-                        mk<R>(-1, 0),      mk<R>(-c1, -sg * s1)};
+    // exp(sg i 2 pi m / 16) for m = 0..9
+    const C<R> w[10] = {mk<R>(1, 0),  mk<R>(c1, sg * s1),  mk<R>(c2, sg * c2),  mk<R>(s1, sg * c1),
+                        mk<R>(0, sg), mk<R>(-s1, sg * c1), mk<R>(-c2, sg * c2), mk<R>(-c1, sg * s1),
+                        mk<R>(-1, 0), mk<R>(-c1, -sg * s1)};
 #pragma unroll
     for (int q = 1; q < 4; ++q)
 #pragma unroll
-        for (int k1 = 1; k1 < 4; ++k1) z[q * 4 + k1] = cmul(z[q * 4 + k1], w[q * k1]);
+        for (int k1 = 1; k1 < 4; ++k1) v[q + 4 * k1] = cmul(v[q + 4 * k1], w[q * k1]);
+    // now DFT over q for each k1: the four values v[q + 4 k1], q = 0..3
 #pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) {
-        C<R> a0 = z[k1], a1 = z[4 + k1], a2 = z[8 + k1], a3 = z[12 + k1];
-        dft4<R, FWD>(a0, a1, a2, a3);
-        v[k1] = a0;
-        v[k1 + 4] = a1;
-        v[k1 + 8] = a2;
-        v[k1 + 12] = a3;
-    }
+    for (int k1 = 0; k1 < 4; ++k1) dft4<R, FWD>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // v[4 k1 + k2] holds output k1 + 4 k2: transpose the 4 x 4 index
+    C<R> t;
+    t = v[1]; v[1] = v[4]; v[4] = t;
+    t = v[2]; v[2] = v[8]; v[8] = t;
+    t = v[3]; v[3] = v[12]; v[12] = t;
+    t = v[6]; v[6] = v[9]; v[9] = t;
+    t = v[7]; v[7] = v[13]; v[13] = t;
+    t = v[11]; v[11] = v[14]; v[14] = t;
 }
 
 template <typename R, bool FWD, int RAD>
@@ -207,6 +201,104 @@ __device__ C<R>* fft_lds(C<R>* buf0, C<R>* buf1, const FftPlan& plan, int npen, 
         Y = t;
     }
     return X;
+}
+
+// ---------------------------------------------------------------------------
+// in-place variant for rows stored contiguously (row r, element k at
+// lds_pad(r * pitch + k)): every thread holds at most one butterfly per pass
+// (the caller guarantees rows * n / radix <= nthr for every radix of the
+// plan), loads its inputs, the block synchronises, then it writes.  LDS
+// addresses are padded by one element every 16 to spread the strided
+// accesses of the early passes over the banks.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int lds_pad(int a) { return a + (a >> 4); }
+
+template <typename R, bool FWD, int RAD, int NB>
+__device__ __noinline__ void stockham_rows_inplace(C<R>* buf, int n, int Ns, int nrows, int pitch,
+                                                      const C<R>* __restrict__ tw, int tid, int nthr) {
+    const int nb = n / RAD;
+    const int total = nb * nrows;
+    C<R> v[NB][RAD];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int idx = tid + q * nthr;
+        if (idx < total) {
+            const int t = idx / nb, j = idx - t * nb;
+            const int rb = t * pitch;
+#pragma unroll
+            for (int i = 0; i < RAD; ++i) v[q][i] = buf[lds_pad(rb + j + i * nb)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int idx = tid + q * nthr;
+        if (idx < total) {
+            const int t = idx / nb, j = idx - t * nb;
+            const int k = j % Ns;
+            if (Ns > 1) {
+                const int twstep = n / (Ns * RAD);
+#pragma unroll
+                for (int i = 1; i < RAD; ++i) {
+                    C<R> w = tw[i * k * twstep];
+                    if (!FWD) w.y = -w.y;
+                    v[q][i] = cmul(v[q][i], w);
+                }
+            }
+            dft_r<R, FWD, RAD>(v[q]);
+            const int rb = t * pitch + (j - k) * RAD + k;
+#pragma unroll
+            for (int i = 0; i < RAD; ++i) buf[lds_pad(rb + i * Ns)] = v[q][i];
+        }
+    }
+    __syncthreads();
+}
+
+// butterflies a thread may hold per pass: at most 16 complex registers
+__host__ __device__ constexpr int rows_max_nb(int rad) { return rad >= 16 ? 1 : rad >= 8 ? 2 : rad >= 4 ? 4 : rad == 3 ? 4 : 8; }
+
+template <typename R, bool FWD, int RAD>
+__device__ __forceinline__ void stockham_rows_dispatch(C<R>* buf, int n, int Ns, int nrows, int pitch,
+                                                       const C<R>* __restrict__ tw, int tid, int nthr) {
+    const int total = (n / RAD) * nrows;
+    constexpr int mx = rows_max_nb(RAD);
+    if (total <= nthr) stockham_rows_inplace<R, FWD, RAD, 1>(buf, n, Ns, nrows, pitch, tw, tid, nthr);
+    else if constexpr (mx >= 2) {
+        if (mx == 2 || total <= 2 * nthr) stockham_rows_inplace<R, FWD, RAD, 2>(buf, n, Ns, nrows, pitch, tw, tid, nthr);
+        else if constexpr (mx >= 4) {
+            if (mx == 4 || total <= 4 * nthr)
+                stockham_rows_inplace<R, FWD, RAD, 4>(buf, n, Ns, nrows, pitch, tw, tid, nthr);
+            else stockham_rows_inplace<R, FWD, RAD, 8>(buf, n, Ns, nrows, pitch, tw, tid, nthr);
+        }
+    }
+}
+
+// rows * n / radix <= rows_max_nb(radix) * nthr for every radix of the plan
+__host__ __device__ inline bool rows_fit(const FftPlan& plan, int nrows, int nthr) {
+    for (int s = 0; s < plan.npass; ++s) {
+        const int r = plan.radix[s];
+        if ((long long)nrows * (plan.n / r) > (long long)rows_max_nb(r) * nthr) return false;
+    }
+    return true;
+}
+
+// whole transform of nrows rows in place (requires rows_fit)
+template <typename R, bool FWD>
+__device__ void fft_rows_inplace(C<R>* buf, const FftPlan& plan, int nrows, int pitch, const C<R>* __restrict__ tw,
+                                 int tid, int nthr) {
+    int Ns = 1;
+    for (int s = 0; s < plan.npass; ++s) {
+        const int r = plan.radix[s];
+        switch (r) {
+            case 2: stockham_rows_dispatch<R, FWD, 2>(buf, plan.n, Ns, nrows, pitch, tw, tid, nthr); break;
+            case 3: stockham_rows_dispatch<R, FWD, 3>(buf, plan.n, Ns, nrows, pitch, tw, tid, nthr); break;
+            case 4: stockham_rows_dispatch<R, FWD, 4>(buf, plan.n, Ns, nrows, pitch, tw, tid, nthr); break;
+            case 5: stockham_rows_dispatch<R, FWD, 5>(buf, plan.n, Ns, nrows, pitch, tw, tid, nthr); break;
+            case 8: stockham_rows_dispatch<R, FWD, 8>(buf, plan.n, Ns, nrows, pitch, tw, tid, nthr); break;
+            default: stockham_rows_dispatch<R, FWD, 16>(buf, plan.n, Ns, nrows, pitch, tw, tid, nthr); break;
+        }
+        Ns *= r;
+    }
 }
 
 }  // namespace vie

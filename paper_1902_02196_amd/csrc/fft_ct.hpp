@@ -1,0 +1,83 @@
+// Stockham FFT of rows in LDS for a compile-time length N: the radix
+// sequence, loop bounds, index divisions and the butterflies per thread are
+// all constants, so every pass unrolls into straight-line code.  Same
+// algorithm as fft.hpp: pass s with radix r and span Ns maps butterfly j
+// (k = j mod Ns) from X[j + i N/r] to Y[(j - k) r + k + i Ns], in place with
+// the inputs of a pass staged in registers between two barriers.  Twiddles
+// W_N^m are read from a copy of the table in LDS.
+#pragma once
+
+#include "fft.hpp"
+
+namespace vie {
+
+// radix of pass s for length n (0 past the last pass): 16s first, then one
+// 8 / 4 / 2 for the rest of the power of two, then 3s, then 5s
+__host__ __device__ constexpr int ct_radix(int n, int s) {
+    int m = n, idx = 0;
+    while (m % 16 == 0) { if (idx == s) return 16; m /= 16; ++idx; }
+    if (m % 8 == 0) { if (idx == s) return 8; m /= 8; ++idx; }
+    if (m % 4 == 0) { if (idx == s) return 4; m /= 4; ++idx; }
+    if (m % 2 == 0) { if (idx == s) return 2; m /= 2; ++idx; }
+    while (m % 3 == 0) { if (idx == s) return 3; m /= 3; ++idx; }
+    while (m % 5 == 0) { if (idx == s) return 5; m /= 5; ++idx; }
+    return 0;
+}
+
+template <typename R, bool FWD, int N, int RAD, int NS, int NTHR, int MAXROWS>
+__device__ __noinline__ void ct_pass(C<R>* buf, const C<R>* twl, int rows, int pitch, int tid) {
+    constexpr int nb = N / RAD;
+    constexpr int NB = (MAXROWS * nb + NTHR - 1) / NTHR;
+    constexpr int twstep = N / (NS * RAD);
+    const int total = rows * nb;
+    C<R> v[NB][RAD];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int idx = tid + q * NTHR;
+        if (idx < total) {
+            const int t = idx / nb, j = idx - t * nb;
+            const int rb = t * pitch + j;
+#pragma unroll
+            for (int i = 0; i < RAD; ++i) v[q][i] = buf[lds_pad(rb + i * nb)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int idx = tid + q * NTHR;
+        if (idx < total) {
+            const int t = idx / nb, j = idx - t * nb;
+            const int k = j % NS;
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int i = 1; i < RAD; ++i) {
+                    C<R> w = twl[i * k * twstep];
+                    if (!FWD) w.y = -w.y;
+                    v[q][i] = cmul(v[q][i], w);
+                }
+            }
+            dft_r<R, FWD, RAD>(v[q]);
+            const int rb = t * pitch + (j - k) * RAD + k;
+#pragma unroll
+            for (int i = 0; i < RAD; ++i) buf[lds_pad(rb + i * NS)] = v[q][i];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename R, bool FWD, int N, int S, int NS, int NTHR, int MAXROWS>
+__device__ __forceinline__ void ct_passes(C<R>* buf, const C<R>* twl, int rows, int pitch, int tid) {
+    constexpr int r = ct_radix(N, S);
+    if constexpr (r > 0) {
+        ct_pass<R, FWD, N, r, NS, NTHR, MAXROWS>(buf, twl, rows, pitch, tid);
+        ct_passes<R, FWD, N, S + 1, NS * r, NTHR, MAXROWS>(buf, twl, rows, pitch, tid);
+    }
+}
+
+// exact floor(e / d) for e * d < 2^32 with magic = ceil(2^32 / d)
+__host__ __device__ __forceinline__ unsigned magic_for(unsigned d) {
+    return (unsigned)((0x100000000ULL + d - 1) / d);
+}
+__device__ __forceinline__ int fast_div(unsigned e, unsigned magic) { return (int)__umulhi(e, magic); }
+
+}  // namespace vie

@@ -12,6 +12,8 @@ void launch_strided(bool fwd, const C<R>* in, C<R>* out, const StridedPass& p, l
                     const C<R>* tw, const Epilogue<R>* ep, hipStream_t s);
 template <typename R>
 void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s);
+bool p3_ct_supported(int n);
+int p3_ct_groups(int es, int n);
 template <typename R>
 void launch_rows(bool fwd, C<R>* data, long long nrows, const FftPlan& plan, const C<R>* tw, hipStream_t s);
 

@@ -3,6 +3,7 @@
 // that crops and applies contrast / Gram scaling (Sec. IV-B).
 #include "kernels.hpp"
 #include "passes.hpp"
+#include "fft_ct.hpp"
 
 namespace vie {
 
@@ -74,81 +75,307 @@ constexpr Orbits make_orbits() {
     return o;
 }
 
-// y[a] += s u x[b] over the orbit of unique entry E (all compile time)
-template <typename R, int E, int K>
-__device__ __forceinline__ void orbit_member(C<R>* yv, const C<R>* xv, C<R> u) {
-    constexpr Orbits o = make_orbits();
-    if constexpr (K < o.cnt[E]) {
-        constexpr int a = o.m[E][K].a, b = o.m[E][K].b, sg = o.m[E][K].s;
-        if constexpr (sg > 0) cfma(yv[a], u, xv[b]);
-        else cfma(yv[a], mk<R>(-u.x, -u.y), xv[b]);
-        orbit_member<R, E, K + 1>(yv, xv, u);
+// y += sum_b sign(A, b) U[unique(A, b)] x[b] for one output row A; the
+// unique index and sign are compile-time constants
+template <typename R, int A, int B>
+__device__ __forceinline__ void row_dot(C<R>& y, const C<R>* xv, const C<R>* Urow, long long ue, int ox) {
+    constexpr int e = unique_index(A, B);
+    constexpr int sg = unique_sign(A, B);
+    const C<R> u = Urow[e * ue + ox];
+    if constexpr (sg > 0) cfma(y, u, xv[B]);
+    else cfma(y, mk<R>(-u.x, -u.y), xv[B]);
+    if constexpr (B + 1 < 12) row_dot<R, A, B + 1>(y, xv, Urow, ue, ox);
+}
+
+// rows [A, AEND) of the 12 x 12 block product into yv[A - A0]
+template <typename R, int A0, int A, int AEND>
+__device__ __forceinline__ void rows_product(C<R>* yv, const C<R>* xv, const C<R>* Urow, long long ue, int ox) {
+    if constexpr (A < AEND) {
+        C<R> y = mk<R>(0, 0);
+        row_dot<R, A, 0>(y, xv, Urow, ue, ox);
+        yv[A - A0] = y;
+        rows_product<R, A0, A + 1, AEND>(yv, xv, Urow, ue, ox);
     }
 }
 
-template <typename R, int E>
-__device__ __forceinline__ void block_product(C<R>* yv, const C<R>* xv, const C<R>* __restrict__ Urow, long long ue,
-                                              int ox) {
-    if constexpr (E < 60) {
-        orbit_member<R, E, 0>(yv, xv, Urow[E * ue + ox]);
-        block_product<R, E + 1>(yv, xv, Urow, ue, ox);
+// rows [6 h, 6 h + 6) (split 2) or [3 h, 3 h + 3) (split 4)
+template <typename R, int SPLIT>
+__device__ __forceinline__ void part_product(int h, C<R>* yv, const C<R>* xv, const C<R>* Urow, long long ue,
+                                             int ox) {
+    if constexpr (SPLIT == 2) {
+        if (h == 0) rows_product<R, 0, 0, 6>(yv, xv, Urow, ue, ox);
+        else rows_product<R, 6, 6, 12>(yv, xv, Urow, ue, ox);
+    } else {
+        if (h == 0) rows_product<R, 0, 0, 3>(yv, xv, Urow, ue, ox);
+        else if (h == 1) rows_product<R, 3, 3, 6>(yv, xv, Urow, ue, ox);
+        else if (h == 2) rows_product<R, 6, 6, 9>(yv, xv, Urow, ue, ox);
+        else rows_product<R, 9, 9, 12>(yv, xv, Urow, ue, ox);
     }
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) k_p3(C<R>* __restrict__ A, const C<R>* __restrict__ U, P3Params p,
-                                            const C<R>* __restrict__ tw) {
+// One workgroup per octant row (xi_z', xi_y'): the up to four pencils
+// (+-xi_y, +-xi_z) that share it, for every right-hand side.  The operator
+// row (60 unique entries x Ox frequencies) is staged in LDS once.  `groups`
+// pencil groups (12 component rows each) then go through LDS together:
+// load (zero-padded from Nx to Mx), forward FFT in place, block product per
+// frequency (SPLIT threads per column, each a slice of the 12 output rows),
+// inverse FFT, store the first Nx.
+template <typename R, int SPLIT>
+__global__ void __launch_bounds__(p3_threads<R>()) k_p3(C<R>* __restrict__ A, const C<R>* __restrict__ U,
+                                                        P3Params p, const C<R>* __restrict__ tw) {
     extern __shared__ unsigned char smem_raw[];
-    C<R>* buf0 = reinterpret_cast<C<R>*>(smem_raw);
-    C<R>* buf1 = buf0 + 12 * p.pitch;
+    C<R>* Ul = reinterpret_cast<C<R>*>(smem_raw);
+    C<R>* buf = Ul + 60 * p.Ox;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int Mx = p.plan.n;
-    const int row = blockIdx.x;            // octant row (oz, oy)
+    const int row = blockIdx.x;
     const int oz = row / p.Oy, oy = row - oz * p.Oy;
     const int ny_sib = (oy == 0 || 2 * oy == p.My) ? 1 : 2;
     const int nz_sib = (oz == 0 || 2 * oz == p.Mz) ? 1 : 2;
-    const C<R>* Urow = U + (long long)(oz * p.Oy + oy) * p.Ox;
-    for (int r = 0; r < p.nrhs; ++r)
-        for (int sz = 0; sz < nz_sib; ++sz)
-            for (int sy = 0; sy < ny_sib; ++sy) {
-                const int z = sz ? p.Mz - oz : oz;
-                const int y = sy ? p.My - oy : oy;
-                C<R>* base = A + (long long)r * 12 * p.s_b + z * p.s_z + y * p.s_y;
-                for (int idx = tid; idx < 12 * Mx; idx += nthr) {
-                    const int c = idx / Mx, k = idx - c * Mx;
-                    buf0[c * p.pitch + k] = k < p.Nx ? base[c * p.s_b + k] : mk<R>(0, 0);
-                }
-                __syncthreads();
-                C<R>* X = fft_lds<R, true, true>(buf0, buf1, p.plan, 12, p.pitch, 1, tw, tid, nthr);
-                C<R>* Y = (X == buf0) ? buf1 : buf0;
-                for (int xi = tid; xi < Mx; xi += nthr) {
-                    const int fx = 2 * xi > Mx;
-                    const int ox = fx ? Mx - xi : xi;
-                    const unsigned mask = fold_mask(fx, sy, sz);
-                    C<R> xv[12], yv[12];
+    const int nsib = ny_sib * nz_sib;
+    const int nwork = nsib * p.nrhs;
+    {
+        const C<R>* Urow = U + (long long)(oz * p.Oy + oy) * p.Ox;
+        for (int idx = tid; idx < 60 * p.Ox; idx += nthr) {
+            const int e = idx / p.Ox, ox = idx - e * p.Ox;
+            Ul[idx] = Urow[e * p.u_e + ox];
+        }
+    }
+    constexpr int RP = 12 / SPLIT;   // output rows per thread
+    for (int w0 = 0; w0 < nwork; w0 += p.groups) {
+        const int G = min(p.groups, nwork - w0);
+        for (int idx = tid; idx < G * 12 * Mx; idx += nthr) {
+            const int g = idx / (12 * Mx), rem = idx - g * 12 * Mx;
+            const int c = rem / Mx, k = rem - c * Mx;
+            const int wk = w0 + g, r = wk / nsib, sib = wk - r * nsib;
+            const int z = (sib / ny_sib) ? p.Mz - oz : oz;
+            const int y = (sib % ny_sib) ? p.My - oy : oy;
+            C<R> v = mk<R>(0, 0);
+            if (k < p.Nx) v = A[(long long)(r * 12 + c) * p.s_b + z * p.s_z + y * p.s_y + k];
+            buf[lds_pad((g * 12 + c) * p.pitch + k)] = v;
+        }
+        __syncthreads();
+        fft_rows_inplace<R, true>(buf, p.plan, G * 12, p.pitch, tw, tid, nthr);
+        {
+            const int ncol = G * Mx;
+            const bool act = tid < SPLIT * ncol;
+            const int h = tid / ncol, col = tid - h * ncol;
+            const int g = col / Mx, xi = col - g * Mx;
+            C<R> xv[12], yv[RP];
+            unsigned mask = 0;
+            int ox = 0;
+            if (act) {
+                const int wk = w0 + g, sib = wk % nsib;
+                const int sz = sib / ny_sib, sy = sib % ny_sib;
+                const int fx = 2 * xi > Mx;
+                ox = fx ? Mx - xi : xi;
+                mask = fold_mask(fx, sy, sz);
 #pragma unroll
-                    for (int a = 0; a < 12; ++a) {
-                        C<R> v = X[a * p.pitch + xi];
-                        if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
-                        xv[a] = v;
-                        yv[a] = mk<R>(0, 0);
-                    }
-                    block_product<R, 0>(yv, xv, Urow, p.u_e, ox);
-#pragma unroll
-                    for (int a = 0; a < 12; ++a) {
-                        C<R> v = yv[a];
-                        if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
-                        Y[a * p.pitch + xi] = v;
-                    }
+                for (int a = 0; a < 12; ++a) {
+                    C<R> v = buf[lds_pad((g * 12 + a) * p.pitch + xi)];
+                    if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                    xv[a] = v;
                 }
-                __syncthreads();
-                C<R>* Z = fft_lds<R, false, true>(Y, X, p.plan, 12, p.pitch, 1, tw, tid, nthr);
-                for (int idx = tid; idx < 12 * p.Nx; idx += nthr) {
-                    const int c = idx / p.Nx, k = idx - c * p.Nx;
-                    base[c * p.s_b + k] = Z[c * p.pitch + k];
-                }
-                __syncthreads();
             }
+            __syncthreads();
+            if (act) {
+                part_product<R, SPLIT>(h, yv, xv, Ul, p.Ox, ox);
+#pragma unroll
+                for (int i = 0; i < RP; ++i) {
+                    const int a = RP * h + i;
+                    C<R> v = yv[i];
+                    if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                    buf[lds_pad((g * 12 + a) * p.pitch + xi)] = v;
+                }
+            }
+        }
+        __syncthreads();
+        fft_rows_inplace<R, false>(buf, p.plan, G * 12, p.pitch, tw, tid, nthr);
+        for (int idx = tid; idx < G * 12 * p.Nx; idx += nthr) {
+            const int g = idx / (12 * p.Nx), rem = idx - g * 12 * p.Nx;
+            const int c = rem / p.Nx, k = rem - c * p.Nx;
+            const int wk = w0 + g, r = wk / nsib, sib = wk - r * nsib;
+            const int z = (sib / ny_sib) ? p.Mz - oz : oz;
+            const int y = (sib % ny_sib) ? p.My - oy : oy;
+            A[(long long)(r * 12 + c) * p.s_b + z * p.s_z + y * p.s_y + k] = buf[lds_pad((g * 12 + c) * p.pitch + k)];
+        }
+        __syncthreads();
+    }
+}
+
+// Same x pass for compile-time FFT lengths N: the operator row and the
+// twiddle table are staged in LDS once, global gathers and scatters keep up
+// to eight loads in flight per thread (fast division by Nx), and the FFT
+// passes unroll completely.
+template <typename R, int N>
+__global__ void __launch_bounds__(p3_threads<R>()) k_p3_ct(C<R>* __restrict__ A, const C<R>* __restrict__ U,
+                                                           P3Params p, const C<R>* __restrict__ tw) {
+    constexpr int NT = p3_threads<R>();
+    constexpr int GMAX = p3_gmax(sizeof(C<R>), N, NT);
+    constexpr int MAXROWS = 12 * GMAX;
+    constexpr int OX = N / 2 + 1;
+    constexpr int SPLIT = (4 * GMAX * N <= NT) ? 4 : 2;
+    constexpr int RP = 12 / SPLIT;
+    extern __shared__ unsigned char smem_raw[];
+    C<R>* Ul = reinterpret_cast<C<R>*>(smem_raw);
+    C<R>* twl = Ul + 60 * OX;
+    C<R>* buf = twl + N;
+    __shared__ long long rowoff[MAXROWS];
+    const int tid = threadIdx.x;
+    const int row = blockIdx.x;
+    const int oz = row / p.Oy, oy = row - oz * p.Oy;
+    const int ny_sib = (oy == 0 || 2 * oy == p.My) ? 1 : 2;
+    const int nz_sib = (oz == 0 || 2 * oz == p.Mz) ? 1 : 2;
+    const int nsib = ny_sib * nz_sib;
+    const int nwork = nsib * p.nrhs;
+    {
+        const C<R>* Urow = U + (long long)(oz * p.Oy + oy) * OX;
+        constexpr int TOT = 60 * OX;
+        for (int b0 = 0; b0 < TOT; b0 += 8 * NT) {
+            C<R> v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int e = b0 + tid + i * NT;
+                if (e < TOT) {
+                    const int eu = e / OX, ox = e - eu * OX;
+                    v[i] = Urow[eu * p.u_e + ox];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int e = b0 + tid + i * NT;
+                if (e < TOT) Ul[e] = v[i];
+            }
+        }
+        for (int m = tid; m < N; m += NT) twl[m] = tw[m];
+    }
+    for (int w0 = 0; w0 < nwork; w0 += p.groups) {
+        const int G = min(p.groups, nwork - w0);
+        const int rows = 12 * G;
+        if (tid < rows) {
+            const int g = tid / 12, c = tid - 12 * g;
+            const int wk = w0 + g, r = wk / nsib, sib = wk - r * nsib;
+            const int z = (sib / ny_sib) ? p.Mz - oz : oz;
+            const int y = (sib % ny_sib) ? p.My - oy : oy;
+            rowoff[tid] = (long long)(r * 12 + c) * p.s_b + (long long)z * p.s_z + (long long)y * p.s_y;
+        }
+        __syncthreads();
+        // gather rows x Nx, zero the padding
+        const int tot = rows * p.Nx;
+        for (int b0 = 0; b0 < tot; b0 += 8 * NT) {
+            C<R> v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int e = b0 + tid + i * NT;
+                if (e < tot) {
+                    const int rr = fast_div((unsigned)e, p.magic_nx), k = e - rr * p.Nx;
+                    v[i] = A[rowoff[rr] + k];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int e = b0 + tid + i * NT;
+                if (e < tot) {
+                    const int rr = fast_div((unsigned)e, p.magic_nx), k = e - rr * p.Nx;
+                    buf[lds_pad(rr * N + k)] = v[i];
+                }
+            }
+        }
+        for (int e = tid; e < rows * N; e += NT) {
+            const int rr = e / N, k = e - rr * N;
+            if (k >= p.Nx) buf[lds_pad(e)] = mk<R>(0, 0);
+        }
+        __syncthreads();
+        ct_passes<R, true, N, 0, 1, NT, MAXROWS>(buf, twl, rows, N, tid);
+        {
+            const int ncol = G * N;
+            const bool act = tid < SPLIT * ncol;
+            const int h = tid / ncol, col = tid - h * ncol;
+            const int g = col / N, xi = col - g * N;
+            C<R> xv[12], yv[RP];
+            unsigned mask = 0;
+            int ox = 0;
+            if (act) {
+                const int wk = w0 + g, sib = wk % nsib;
+                const int sz = sib / ny_sib, sy = sib % ny_sib;
+                const int fx = 2 * xi > N;
+                ox = fx ? N - xi : xi;
+                mask = fold_mask(fx, sy, sz);
+#pragma unroll
+                for (int a = 0; a < 12; ++a) {
+                    C<R> v = buf[lds_pad((g * 12 + a) * N + xi)];
+                    if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                    xv[a] = v;
+                }
+            }
+            __syncthreads();
+            if (act) {
+                part_product<R, SPLIT>(h, yv, xv, Ul, OX, ox);
+#pragma unroll
+                for (int i = 0; i < RP; ++i) {
+                    const int a = RP * h + i;
+                    C<R> v = yv[i];
+                    if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                    buf[lds_pad((g * 12 + a) * N + xi)] = v;
+                }
+            }
+        }
+        __syncthreads();
+        ct_passes<R, false, N, 0, 1, NT, MAXROWS>(buf, twl, rows, N, tid);
+        for (int b0 = 0; b0 < tot; b0 += 8 * NT) {
+            C<R> v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int e = b0 + tid + i * NT;
+                if (e < tot) {
+                    const int rr = fast_div((unsigned)e, p.magic_nx), k = e - rr * p.Nx;
+                    v[i] = buf[lds_pad(rr * N + k)];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int e = b0 + tid + i * NT;
+                if (e < tot) {
+                    const int rr = fast_div((unsigned)e, p.magic_nx), k = e - rr * p.Nx;
+                    A[rowoff[rr] + k] = v[i];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// lengths with a compile-time kernel
+#define VIE_P3_LENGTHS(X) X(8) X(16) X(32) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
+
+bool p3_ct_supported(int n) {
+    switch (n) {
+#define CASE(n_) case n_:
+        VIE_P3_LENGTHS(CASE)
+#undef CASE
+        return true;
+        default: return false;
+    }
+}
+
+int p3_ct_groups(int es, int n) { return p3_gmax(es, n, es == 8 ? 1024 : 512); }
+
+template <typename R, int N>
+static void launch_p3_ct_n(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
+    constexpr int NT = p3_threads<R>();
+    constexpr int GMAX = p3_gmax(sizeof(C<R>), N, NT);
+    VIE_REQUIRE(p.groups >= 1 && p.groups <= GMAX && p.Ox == N / 2 + 1, -1, "x pass: bad group count");
+    const size_t lds = (size_t)p3_lds_bytes(sizeof(C<R>), N, GMAX);
+    static bool attr = false;
+    if (!attr) {
+        // allow more than the default 64 KiB of dynamic LDS; a refusal shows
+        // up as a launch error below, so clear the status here
+        (void)hipFuncSetAttribute((const void*)k_p3_ct<R, N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_p3_ct<R, N>), dim3(p.Oy * p.Oz), dim3(NT), lds, s, A, U, p, tw);
+    VIE_HIP(hipGetLastError());
 }
 
 // ---------------------------------------------------------------------------
@@ -187,7 +414,8 @@ static void launch_strided_t(const C<R>* in, C<R>* out, const StridedPass& p, lo
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void*)k_strided<R, FWD, EPI>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
+                                  96 * 1024);
+        (void)hipGetLastError();
         attr = true;
     }
     hipLaunchKernelGGL((k_strided<R, FWD, EPI>), grid, dim3(256), lds, s, in, out, p, tw, ep);
@@ -210,13 +438,26 @@ void launch_strided(bool fwd, const C<R>* in, C<R>* out, const StridedPass& p, l
 
 template <typename R>
 void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
-    size_t lds = 2 * 12 * (size_t)p.pitch * sizeof(C<R>);
+    switch (p.plan.n) {
+#define CASE(n_) case n_: launch_p3_ct_n<R, n_>(A, U, p, tw, s); return;
+        VIE_P3_LENGTHS(CASE)
+#undef CASE
+        default: break;
+    }
+    const int nt = p3_threads<R>();
+    VIE_REQUIRE(rows_fit(p.plan, p.groups * 12, nt) && 2 * p.groups * p.plan.n <= nt, -1,
+                "x pass: more butterflies or columns than threads");
+    size_t lds = (60 * (size_t)p.Ox + lds_pad(p.groups * 12 * p.pitch) + 2) * sizeof(C<R>);
+    const bool split4 = 4 * p.groups * p.plan.n <= nt;
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void*)k_p3<R>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute((const void*)k_p3<R, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        (void)hipFuncSetAttribute((const void*)k_p3<R, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        (void)hipGetLastError();
         attr = true;
     }
-    hipLaunchKernelGGL((k_p3<R>), dim3(p.Oy * p.Oz), dim3(256), lds, s, A, U, p, tw);
+    if (split4) hipLaunchKernelGGL((k_p3<R, 4>), dim3(p.Oy * p.Oz), dim3(nt), lds, s, A, U, p, tw);
+    else hipLaunchKernelGGL((k_p3<R, 2>), dim3(p.Oy * p.Oz), dim3(nt), lds, s, A, U, p, tw);
     VIE_HIP(hipGetLastError());
 }
 

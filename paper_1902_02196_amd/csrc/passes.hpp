@@ -46,6 +46,27 @@ struct P3Params {
     long long s_b, s_z, s_y;   // strides of the [B][Mz][My][Nx] buffer
     long long u_e;             // stride between unique operator entries
     int pitch;                 // LDS row pitch (>= Mx)
+    int groups;                // pencil groups (12 rows each) per LDS pass
+    unsigned magic_nx;         // fast division by Nx
+    unsigned magic_ox;         // fast division by Ox
 };
+
+// workgroup size of the x pass: complex64 1024 threads (128 VGPRs each),
+// complex128 512 threads (256 VGPRs each)
+template <typename R> constexpr int p3_threads() { return sizeof(R) == 4 ? 1024 : 512; }
+
+// LDS bytes of the x pass: operator row, twiddles, padded pencil groups
+__host__ __device__ constexpr long long p3_lds_bytes(int es, int n, int g) {
+    const long long rows = (long long)g * 12 * n;
+    return ((long long)60 * (n / 2 + 1) + n + rows + rows / 16 + 4) * es;
+}
+
+// pencil groups per LDS pass for the compile-time-length kernels: as many as
+// fit 96 KiB of LDS (and two threads per frequency column), at most four
+__host__ __device__ constexpr int p3_gmax(int es, int n, int nthr) {
+    int g = 4;
+    while (g > 1 && (p3_lds_bytes(es, n, g) > 96 * 1024 || 2 * g * n > nthr)) --g;
+    return g;
+}
 
 }  // namespace vie

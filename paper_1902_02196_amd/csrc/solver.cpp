@@ -111,6 +111,11 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
             C<R>* w = Vb + (long long)(j + 1) * ldv;
             apply_op<R>(c, OP_PREC, na, vj, w, nullptr);
             const int nvec = j + 1;
+            // Gram-Schmidt traffic: each pass reads the basis and w for the
+            // dots, then the basis again and w read+write for the update
+            const double pass_bytes = (double)na * n * sizeof(C<R>) * (2.0 * nvec + 3.0);
+            {
+            ProfScope ps(c.prof, c.stream, VIE_K_ARNOLDI, (o.reorth ? 2 : 1) * pass_bytes + (double)na * n * sizeof(C<R>) * 2);
             launch_multidot<R>(L.partial, Vb, ldv, nvec, w, n, n, n, na, nb, c.stream);
             launch_reduce_partials(L.h1, L.partial, nvec, nb, na, c.stream);
             launch_update<R>(w, Vb, ldv, nvec, L.h1, n, n, n, L.npart, na, nb, c.stream);
@@ -121,6 +126,7 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
             }
             launch_reduce_norm(L.nrm, L.npart, nb, na, c.stream);
             launch_scale_into<R>(w, w, L.nrm, n, n, n, na, c.stream);
+            }
             VIE_HIP(hipMemcpyAsync(h1.data(), L.h1, (size_t)na * nvec * sizeof(double2), hipMemcpyDeviceToHost,
                                    c.stream));
             if (o.reorth)
