@@ -98,6 +98,11 @@ def main():
     ctx.set_grid(N, D, f)
     torch.cuda.synchronize()
     t_grid = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tune64 = ctx.autotune(vie.C64, 1)
+    tune128 = ctx.autotune(vie.C128, 1)
+    t_tune = time.perf_counter() - t0
+    log("autotune %.2f s: c64 %s, c128 %s" % (t_tune, tune64, tune128))
     if W["seed"] is None:
         e, s = vi.sphere(N, D, 0.03, 50.0, 0.7)
     else:
@@ -203,6 +208,7 @@ def main():
         "matvec_c64_device_ms": round(mv_dev_ms, 4),
         "matvec_c64_GBps_algorithmic": round(mv_bytes / (mv_dev_ms * 1e-3) / 1e9, 1),
         "setup_s": round(t_grid, 3),
+        "autotune": {"c64": tune64[0], "c128": tune128[0], "seconds": round(t_tune, 2)},
         "kernels": kernels,
         "roofline": roofline,
     }

@@ -185,6 +185,19 @@ int vie_absorbed_power(vie_ctx* ctx, int nrhs, const void* x, double* p_abs_host
  * FP64 device array [nrhs][Nz][Ny][Nx], from field coefficients e. */
 int vie_power_density(vie_ctx* ctx, int nrhs, const void* e, double* p_dev);
 
+/* -- autotuning ------------------------------------------------------------ */
+
+/* Time the candidate launch shapes of the operator product (x-pass variant,
+ * workgroups per octant row, pencils per workgroup of the z and y passes)
+ * for this grid, precision and number of right-hand sides, and keep the
+ * fastest for later calls with the same (precision, nrhs).  choice (may be
+ * NULL) receives {variant, workgroups per row, z tile, y tile}; best_ms (may
+ * be NULL) the time of one product with them.  Allocates two temporary
+ * vectors; synchronises the stream.  Every shape computes the same sums; the
+ * x-pass variants add the 144 block terms in different orders, so results
+ * agree to rounding. */
+int vie_autotune(vie_ctx* ctx, int precision, int nrhs, int* choice, double* best_ms);
+
 /* -- profiling ------------------------------------------------------------ */
 
 /* kernel classes timed by the built-in profiler */

@@ -66,6 +66,7 @@ _sig = {
     "vie_fields": (_i, [_vp, _i, _vp, _vp]),
     "vie_absorbed_power": (_i, [_vp, _i, _vp, _dp]),
     "vie_power_density": (_i, [_vp, _i, _vp, _vp]),
+    "vie_autotune": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _dp]),
     "vie_profile": (_i, [_vp, _i]),
     "vie_profile_read": (_i, [_vp, _i, _dp, ctypes.POINTER(_i), _dp]),
     "vie_unknowns_bytes_paper": (ctypes.c_size_t, [_i, _i, _i]),
@@ -245,6 +246,13 @@ class Context:
         out = np.zeros(n)
         _check(_lib.vie_absorbed_power(self._h, n, _tensor_ptr(x, torch.complex128, self.vec_shape(n)), _dptr(out)))
         return out
+
+    def autotune(self, precision=C64, nrhs=1):
+        """Pick the fastest launch shapes for this grid; returns (choice, ms)."""
+        ch = (ctypes.c_int * 4)()
+        ms = ctypes.c_double(0)
+        _check(_lib.vie_autotune(self._h, precision, nrhs, ch, ctypes.byref(ms)))
+        return {"variant": ch[0], "sib_blocks": ch[1], "tile_z": ch[2], "tile_y": ch[3]}, ms.value
 
     def profile(self, enable=True):
         _check(_lib.vie_profile(self._h, 1 if enable else 0))

@@ -35,17 +35,28 @@ static int pick_tile(int n, size_t elem) {
 
 template <typename R>
 void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs) {
+    Tune tn;
+    {
+        auto it = c.tune.find({sizeof(R) == 4 ? 0 : 1, nrhs});
+        if (it != c.tune.end()) tn = it->second;
+    }
     VIE_REQUIRE(c.has_grid, VIE_ESTATE, "vie_apply before vie_set_grid");
     if (op != OP_N) VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "operator needs vie_set_contrast");
     const int Nx = c.N[0], Ny = c.N[1], Nz = c.N[2];
     const int Mx = c.M[0], My = c.M[1], Mz = c.M[2];
     const long long B = 12LL * nrhs;
-    const long long sA1 = (long long)Mz * Ny * Nx;   // per component, after P1 / P4
-    const long long sA2 = (long long)Mz * My * Nx;   // after P2 / P3
+    // intermediate layouts per right-hand side [Mz][Ny|My][12][Nx]: the 12
+    // components of one (z, y) row are adjacent, so a pencil group of the x
+    // pass is one contiguous block; planes are padded so that rows used
+    // together are not a large power of two apart
+    const long long row = 12LL * Nx;
+    const long long pl1 = (long long)Ny * row + 32, pl2 = (long long)My * row + 32;
+    const long long sR1 = (long long)Mz * pl1 + 96;   // per right-hand side, after P1 / P4
+    const long long sR2 = (long long)Mz * pl2 + 96;   // after P2 / P3
     const size_t es = sizeof(C<R>);
-    char* ws = static_cast<char*>(c.ws.get((size_t)B * (sA1 + sA2) * es));
+    char* ws = static_cast<char*>(c.ws.get((size_t)nrhs * (sR1 + sR2) * es));
     C<R>* A1 = reinterpret_cast<C<R>*>(ws);
-    C<R>* A2 = reinterpret_cast<C<R>*>(ws + (size_t)B * sA1 * es);
+    C<R>* A2 = reinterpret_cast<C<R>*>(ws + (size_t)nrhs * sR1 * es);
     hipStream_t s = c.stream;
     const long long V = c.V;
 
@@ -55,15 +66,17 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     p1.n_in = Nz;
     p1.n_out = Mz;
     p1.n_inner = Nx;
-    p1.tile = pick_tile(Mz, es);
+    p1.tile = tn.tile_z ? tn.tile_z : pick_tile(Mz, es);
     p1.pitch = p1.tile;
-    p1.in_s1 = V;
+    p1.in_s1 = 12 * V;
+    p1.in_sc = V;
     p1.in_s2 = Nx;
     p1.in_sk = (long long)Ny * Nx;
-    p1.out_s1 = sA1;
-    p1.out_s2 = Nx;
-    p1.out_sk = (long long)Ny * Nx;
-    const double bV = (double)B * V * es, bA1 = (double)B * sA1 * es, bA2 = (double)B * sA2 * es;
+    p1.out_s1 = sR1;
+    p1.out_sc = Nx;
+    p1.out_s2 = row;
+    p1.out_sk = pl1;
+    const double bV = (double)B * V * es, bA1 = (double)B * Mz * Ny * Nx * es, bA2 = (double)B * Mz * My * Nx * es;
     {
         ProfScope ps(c.prof, s, VIE_K_FFT_Z_FWD, bV + bA1);
         launch_strided<R>(true, x, A1, p1, Ny, B, twid<R>(c.ax[2]), nullptr, s);
@@ -75,14 +88,16 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     p2.n_in = Ny;
     p2.n_out = My;
     p2.n_inner = Nx;
-    p2.tile = pick_tile(My, es);
+    p2.tile = tn.tile_y ? tn.tile_y : pick_tile(My, es);
     p2.pitch = p2.tile;
-    p2.in_s1 = sA1;
-    p2.in_s2 = (long long)Ny * Nx;
-    p2.in_sk = Nx;
-    p2.out_s1 = sA2;
-    p2.out_s2 = (long long)My * Nx;
-    p2.out_sk = Nx;
+    p2.in_s1 = sR1;
+    p2.in_sc = Nx;
+    p2.in_s2 = pl1;
+    p2.in_sk = row;
+    p2.out_s1 = sR2;
+    p2.out_sc = Nx;
+    p2.out_s2 = pl2;
+    p2.out_sk = row;
     {
         ProfScope ps(c.prof, s, VIE_K_FFT_Y_FWD, bA1 + bA2);
         launch_strided<R>(true, A1, A2, p2, Mz, B, twid<R>(c.ax[1]), nullptr, s);
@@ -98,10 +113,11 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     p3.Oy = c.O[1];
     p3.Oz = c.O[2];
     p3.nrhs = nrhs;
-    p3.s_b = sA2;
-    p3.s_z = (long long)My * Nx;
-    p3.s_y = Nx;
-    p3.u_e = c.Osz;
+    p3.s_r = sR2;
+    p3.s_c = Nx;
+    p3.s_z = pl2;
+    p3.s_y = row;
+    p3.u_e = c.O[0];
     p3.pitch = Mx;
     {
         // as many pencil groups per LDS pass as fit 64 KiB and the
@@ -114,8 +130,17 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
         while (g > 1 && (ul + (size_t)lds_pad(g * 12 * Mx) * es > 80 * 1024 || !rows_fit(p3.plan, g * 12, nt) ||
                          2 * g * Mx > nt))
             --g;
+        p3.sib_blocks = 1;
+        p3.variant = 0;
         if (p3_ct_supported(Mx)) {
-            g = p3_ct_groups((int)es, Mx);
+            // light variant (one pencil group per workgroup) unless the
+            // autotuner chose the staged one; the staged variant shares the
+            // operator row among all siblings and right-hand sides of a
+            // workgroup
+            p3.variant = tn.p3_variant >= 0 ? tn.p3_variant : 1;
+            p3.sib_blocks = tn.p3_sib_blocks ? tn.p3_sib_blocks : 1;
+            g = std::min(p3_ct_groups((int)es, Mx), (4 / p3.sib_blocks) * nrhs);
+            g = std::max(g, 1);
         } else {
             VIE_REQUIRE(rows_fit(p3.plan, 12, nt) && 2 * Mx <= nt && ul + (size_t)lds_pad(12 * Mx) * es <= 150 * 1024,
                         VIE_EINVAL, "fft size along x too large");
@@ -133,12 +158,14 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     StridedPass p4 = p2;
     p4.n_in = My;
     p4.n_out = Ny;
-    p4.in_s1 = sA2;
-    p4.in_s2 = (long long)My * Nx;
-    p4.in_sk = Nx;
-    p4.out_s1 = sA1;
-    p4.out_s2 = (long long)Ny * Nx;
-    p4.out_sk = Nx;
+    p4.in_s1 = sR2;
+    p4.in_sc = Nx;
+    p4.in_s2 = pl2;
+    p4.in_sk = row;
+    p4.out_s1 = sR1;
+    p4.out_sc = Nx;
+    p4.out_s2 = pl1;
+    p4.out_sk = row;
     {
         ProfScope ps(c.prof, s, VIE_K_FFT_Y_INV, bA2 + bA1);
         launch_strided<R>(false, A2, A1, p4, Mz, B, twid<R>(c.ax[1]), nullptr, s);
@@ -148,10 +175,12 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     StridedPass p5 = p1;
     p5.n_in = Mz;
     p5.n_out = Nz;
-    p5.in_s1 = sA1;
-    p5.in_s2 = Nx;
-    p5.in_sk = (long long)Ny * Nx;
-    p5.out_s1 = V;
+    p5.in_s1 = sR1;
+    p5.in_sc = Nx;
+    p5.in_s2 = row;
+    p5.in_sk = pl1;
+    p5.out_s1 = 12 * V;
+    p5.out_sc = V;
     p5.out_s2 = Nx;
     p5.out_sk = (long long)Ny * Nx;
     Epilogue<R> ep{};
@@ -171,7 +200,6 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
         chi = c.mat.chi;
     }
     ep.x = x;
-    ep.s1 = V;
     for (int l = 0; l < 4; ++l) {
         switch (op) {
             case OP_PREC:

@@ -405,6 +405,24 @@ int vie_power_density(vie_ctx* ctx, int nrhs, const void* e, double* p_dev) {
     });
 }
 
+int vie_autotune(vie_ctx* ctx, int precision, int nrhs, int* choice, double* best_ms) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_grid, VIE_ESTATE, "autotune needs a grid");
+        VIE_REQUIRE(precision == VIE_C64 || precision == VIE_C128, VIE_EINVAL, "bad precision");
+        VIE_REQUIRE(nrhs >= 1, VIE_EINVAL, "nrhs must be >= 1");
+        Tune t = autotune(c, precision, nrhs, best_ms);
+        if (choice) {
+            choice[0] = t.p3_variant;
+            choice[1] = t.p3_sib_blocks;
+            choice[2] = t.tile_z;
+            choice[3] = t.tile_y;
+        }
+    });
+}
+
 int vie_profile(vie_ctx* ctx, int enable) {
     return guarded([&] {
         check_ctx(ctx);

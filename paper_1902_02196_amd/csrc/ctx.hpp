@@ -1,6 +1,7 @@
 // Library context: grid, resident operator, materials, workspaces.
 #pragma once
 
+#include <map>
 #include <vector>
 
 #include "vie.h"
@@ -79,6 +80,15 @@ struct ProfScope {
     }
 };
 
+// launch shapes of the operator product, chosen per (precision, nrhs) by
+// the autotuner; zeros mean the built-in defaults
+struct Tune {
+    int p3_variant = -1;     // -1 default, 0 staged operator row, 1 light
+    int p3_sib_blocks = 0;   // staged variant: workgroups per octant row
+    int tile_z = 0;          // strided passes: pencils per workgroup
+    int tile_y = 0;
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -108,6 +118,7 @@ struct Ctx {
     Scratch basis, vecs;
 
     Profiler prof;
+    std::map<std::pair<int, int>, Tune> tune;   // (precision, nrhs) -> shapes
 
     ~Ctx();
     void free_grid();
@@ -123,6 +134,9 @@ void make_twiddles(int n, std::vector<double2>& tw);
 enum { OP_PREC = 0, OP_A = 1, OP_N = 2, OP_RESID = 3 };
 template <typename R>
 void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs);
+
+// autotuner (tune.cpp): fastest launch shapes for (precision, nrhs)
+Tune autotune(Ctx& c, int precision, int nrhs, double* best_ms);
 
 // solver (solver.cpp)
 int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2* x, vie_solve_stats* st);

@@ -25,7 +25,7 @@ __host__ __device__ constexpr int ct_radix(int n, int s) {
 }
 
 template <typename R, bool FWD, int N, int RAD, int NS, int NTHR, int MAXROWS>
-__device__ __noinline__ void ct_pass(C<R>* buf, const C<R>* twl, int rows, int pitch, int tid) {
+__device__ __forceinline__ void ct_pass(C<R>* buf, const C<R>* twl, int rows, int pitch, int tid) {
     constexpr int nb = N / RAD;
     constexpr int NB = (MAXROWS * nb + NTHR - 1) / NTHR;
     constexpr int twstep = N / (NS * RAD);

@@ -7,7 +7,7 @@
 namespace vie {
 
 constexpr int kTpb = 256;
-constexpr int kGroup = 8;   // basis vectors per sweep of the dot kernel
+constexpr int kGroup = 16;  // basis vectors per sweep of the dot kernel
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -17,15 +17,36 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 template <typename T> __device__ __forceinline__ double2 to_d2(T v) { return make_double2((double)v.x, (double)v.y); }
 
+// 16-byte units: a pair of complex64 or one complex128
+template <typename R> struct Unit;
+template <> struct Unit<float> {
+    using T = float4;
+    static constexpr int per = 2;
+    __device__ static double2 get(const T& u, int h) { return h ? make_double2(u.z, u.w) : make_double2(u.x, u.y); }
+    __device__ static void set(T& u, int h, double2 v) {
+        if (h) { u.z = (float)v.x; u.w = (float)v.y; } else { u.x = (float)v.x; u.y = (float)v.y; }
+    }
+};
+template <> struct Unit<double> {
+    using T = double2;
+    static constexpr int per = 1;
+    __device__ static double2 get(const T& u, int) { return u; }
+    __device__ static void set(T& u, int, double2 v) { u = v; }
+};
+
 // partial[(r * nvec + i) * nblocks + block] = sum over the block's elements of conj(V_i) w
+// (vectors read in 16-byte units; n must be a multiple of the unit size)
 template <typename R>
 __global__ void __launch_bounds__(kTpb) k_multidot(double2* __restrict__ partial, const C<R>* __restrict__ Vb,
                                                    long long ldv, int nvec, const C<R>* __restrict__ w, long long n,
                                                    long long rsv, long long rsw) {
+    using U = Unit<R>;
+    using T = typename U::T;
     __shared__ double red[kTpb / 64][2 * kGroup];
     const int r = blockIdx.y;
-    const C<R>* V = Vb + r * rsv;
-    const C<R>* wr = w + r * rsw;
+    const T* V = reinterpret_cast<const T*>(Vb + r * rsv);
+    const T* wr = reinterpret_cast<const T*>(w + r * rsw);
+    const long long nu = n / U::per, ldu = ldv / U::per;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long stride = (long long)gridDim.x * kTpb;
     for (int i0 = 0; i0 < nvec; i0 += kGroup) {
@@ -33,14 +54,18 @@ __global__ void __launch_bounds__(kTpb) k_multidot(double2* __restrict__ partial
         double ar[kGroup], ai[kGroup];
 #pragma unroll
         for (int g = 0; g < kGroup; ++g) ar[g] = ai[g] = 0.0;
-        for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < n; k += stride) {
-            const double2 wv = to_d2(wr[k]);
+        for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < nu; k += stride) {
+            const T wu = wr[k];
 #pragma unroll
             for (int g = 0; g < kGroup; ++g) {
                 if (g < ng) {
-                    const double2 v = to_d2(V[(i0 + g) * ldv + k]);
-                    ar[g] += v.x * wv.x + v.y * wv.y;
-                    ai[g] += v.x * wv.y - v.y * wv.x;
+                    const T vu = V[(i0 + g) * ldu + k];
+#pragma unroll
+                    for (int h = 0; h < U::per; ++h) {
+                        const double2 v = U::get(vu, h), wv = U::get(wu, h);
+                        ar[g] += v.x * wv.x + v.y * wv.y;
+                        ai[g] += v.x * wv.y - v.y * wv.x;
+                    }
                 }
             }
         }
@@ -88,25 +113,38 @@ template <typename R>
 __global__ void __launch_bounds__(kTpb) k_update(C<R>* __restrict__ w, const C<R>* __restrict__ Vb, long long ldv,
                                                  int nvec, const double2* __restrict__ h, long long n, long long rsv,
                                                  long long rsw, double* __restrict__ norm_partial) {
+    using U = Unit<R>;
+    using T = typename U::T;
     __shared__ double red[kTpb / 64];
     const int r = blockIdx.y;
-    const C<R>* V = Vb + r * rsv;
-    C<R>* wr = w + r * rsw;
+    const T* V = reinterpret_cast<const T*>(Vb + r * rsv);
+    T* wr = reinterpret_cast<T*>(w + r * rsw);
+    const long long nu = n / U::per, ldu = ldv / U::per;
     const double2* hr = h + (long long)r * nvec;
     double acc = 0.0;
-    for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < n; k += (long long)gridDim.x * kTpb) {
-        double2 wv = to_d2(wr[k]);
+    for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < nu; k += (long long)gridDim.x * kTpb) {
+        T wu = wr[k];
+        double2 wv[U::per];
+#pragma unroll
+        for (int q = 0; q < U::per; ++q) wv[q] = U::get(wu, q);
         for (int i = 0; i < nvec; ++i) {
-            const double2 v = to_d2(V[i * ldv + k]);
+            const T vu = V[i * ldu + k];
             const double2 hi = hr[i];
-            wv.x -= hi.x * v.x - hi.y * v.y;
-            wv.y -= hi.x * v.y + hi.y * v.x;
+#pragma unroll
+            for (int q = 0; q < U::per; ++q) {
+                const double2 v = U::get(vu, q);
+                wv[q].x -= hi.x * v.x - hi.y * v.y;
+                wv[q].y -= hi.x * v.y + hi.y * v.x;
+            }
         }
-        C<R> o;
-        o.x = (R)wv.x;
-        o.y = (R)wv.y;
-        wr[k] = o;
-        acc += (double)o.x * o.x + (double)o.y * o.y;
+#pragma unroll
+        for (int q = 0; q < U::per; ++q) U::set(wu, q, wv[q]);
+        wr[k] = wu;
+#pragma unroll
+        for (int q = 0; q < U::per; ++q) {
+            const double2 o = U::get(wu, q);   // the stored (rounded) value
+            acc += o.x * o.x + o.y * o.y;
+        }
     }
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;

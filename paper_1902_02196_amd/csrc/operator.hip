@@ -367,16 +367,20 @@ __global__ void k_embed(double2* __restrict__ circ, const double2* __restrict__ 
     circ[j] = val;
 }
 
-// keep the octant xi_i <= M_i / 2 of a transformed circulant
+// keep the octant xi_i <= M_i / 2 of a transformed circulant, stored as
+// U[oz][oy][e][ox] (the 60 entries of one (oz, oy) row together)
 __global__ void k_octant(double2* __restrict__ U128, float2* __restrict__ U64, const double2* __restrict__ circ,
-                         int Mx, int My, int Ox, int Oy, int Oz) {
+                         int e, int Mx, int My, int Ox, int Oy, int Oz) {
     const long long O = (long long)Ox * Oy * Oz;
     const long long o = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (o >= O) return;
-    const int ox = int(o % Ox), oy = int((o / Ox) % Oy), oz = int(o / ((long long)Ox * Oy));
+    const int ox = int(o % Ox);
+    const long long row = o / Ox;   // oz * Oy + oy
+    const int oy = int(row % Oy), oz = int(row / Oy);
     const double2 v = circ[((long long)oz * My + oy) * Mx + ox];
-    U128[o] = v;
-    U64[o] = make_float2((float)v.x, (float)v.y);
+    const long long dst = (row * 60 + e) * Ox + ox;
+    U128[dst] = v;
+    U64[dst] = make_float2((float)v.x, (float)v.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -426,6 +430,7 @@ void embed_and_transform(double2* U128, float2* U64, const double2* T, double2* 
         pz.tile = 16;
         pz.pitch = 16;
         pz.in_s1 = pz.out_s1 = 0;
+        pz.in_sc = pz.out_sc = 0;
         pz.in_s2 = pz.out_s2 = Mx;          // o2 = y
         pz.in_sk = pz.out_sk = (long long)Mx * My;
         launch_strided<double>(true, circ, circ, pz, My, 1, tw[2], nullptr, s);
@@ -436,12 +441,13 @@ void embed_and_transform(double2* U128, float2* U64, const double2* T, double2* 
         py.tile = 16;
         py.pitch = 16;
         py.in_s1 = py.out_s1 = 0;
+        py.in_sc = py.out_sc = 0;
         py.in_s2 = py.out_s2 = (long long)Mx * My;   // o2 = z
         py.in_sk = py.out_sk = Mx;
         launch_strided<double>(true, circ, circ, py, Mz, 1, tw[1], nullptr, s);
         launch_rows<double>(true, circ, (long long)My * Mz, plans[0], tw[0], s);
-        hipLaunchKernelGGL(k_octant, dim3((unsigned)((O + 255) / 256)), dim3(256), 0, s, U128 + e * O, U64 + e * O,
-                           circ, Mx, My, Ox, Oy, Oz);
+        hipLaunchKernelGGL(k_octant, dim3((unsigned)((O + 255) / 256)), dim3(256), 0, s, U128, U64, circ, e, Mx, My,
+                           Ox, Oy, Oz);
         VIE_HIP(hipGetLastError());
     }
 }

@@ -18,9 +18,10 @@ __global__ void __launch_bounds__(256) k_strided(const C<R>* in, C<R>* out,
     C<R>* buf1 = buf0 + p.plan.n * p.pitch;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int t0 = blockIdx.x * p.tile;
-    const long long o2 = blockIdx.y, o1 = blockIdx.z;
+    const long long o2 = blockIdx.y;
+    const int o1 = blockIdx.z, rr = o1 / 12, cc = o1 - 12 * rr;
     const int tw_n = min(p.tile, p.n_inner - t0);
-    const C<R>* src = in + o1 * p.in_s1 + o2 * p.in_s2 + t0;
+    const C<R>* src = in + rr * p.in_s1 + cc * p.in_sc + o2 * p.in_s2 + t0;
     const int n = p.plan.n;
     // load (zero-padded beyond n_in and beyond the inner extent)
     for (int idx = tid; idx < n * p.tile; idx += nthr) {
@@ -31,15 +32,16 @@ __global__ void __launch_bounds__(256) k_strided(const C<R>* in, C<R>* out,
     }
     __syncthreads();
     C<R>* res = fft_lds<R, FWD, false>(buf0, buf1, p.plan, p.tile, 1, p.pitch, tw, tid, nthr);
-    C<R>* dst = out + o1 * p.out_s1 + o2 * p.out_s2 + t0;
+    const long long obase = rr * p.out_s1 + cc * p.out_sc;
+    C<R>* dst = out + obase + o2 * p.out_s2 + t0;
     for (int idx = tid; idx < p.n_out * p.tile; idx += nthr) {
         const int k = idx / p.tile, t = idx - k * p.tile;
         if (t >= tw_n) continue;
         C<R> w = res[k * p.pitch + t];
         if (EPI) {
-            const long long e = o1 * p.out_s1 + o2 * p.out_s2 + k * p.out_sk + t0 + t;   // element
-            const long long v = e - o1 * p.out_s1;                                       // voxel
-            const int l = int(o1 % 12) & 3;
+            const long long v = o2 * p.out_s2 + k * p.out_sk + t0 + t;   // voxel
+            const long long e = obase + v;                                  // element
+            const int l = cc & 3;
             C<R> bv = ep.b ? ep.b[v] : mk<R>(ep.b_const, 0);
             C<R> y = cscale(cmul(bv, w), ep.gb[l]);
             if (ep.a || ep.a_const != R(0)) {
@@ -135,7 +137,7 @@ __global__ void __launch_bounds__(p3_threads<R>()) k_p3(C<R>* __restrict__ A, co
     const int nsib = ny_sib * nz_sib;
     const int nwork = nsib * p.nrhs;
     {
-        const C<R>* Urow = U + (long long)(oz * p.Oy + oy) * p.Ox;
+        const C<R>* Urow = U + (long long)(oz * p.Oy + oy) * 60 * p.Ox;
         for (int idx = tid; idx < 60 * p.Ox; idx += nthr) {
             const int e = idx / p.Ox, ox = idx - e * p.Ox;
             Ul[idx] = Urow[e * p.u_e + ox];
@@ -151,7 +153,7 @@ __global__ void __launch_bounds__(p3_threads<R>()) k_p3(C<R>* __restrict__ A, co
             const int z = (sib / ny_sib) ? p.Mz - oz : oz;
             const int y = (sib % ny_sib) ? p.My - oy : oy;
             C<R> v = mk<R>(0, 0);
-            if (k < p.Nx) v = A[(long long)(r * 12 + c) * p.s_b + z * p.s_z + y * p.s_y + k];
+            if (k < p.Nx) v = A[(long long)r * p.s_r + c * p.s_c + z * p.s_z + y * p.s_y + k];
             buf[lds_pad((g * 12 + c) * p.pitch + k)] = v;
         }
         __syncthreads();
@@ -197,7 +199,7 @@ __global__ void __launch_bounds__(p3_threads<R>()) k_p3(C<R>* __restrict__ A, co
             const int wk = w0 + g, r = wk / nsib, sib = wk - r * nsib;
             const int z = (sib / ny_sib) ? p.Mz - oz : oz;
             const int y = (sib % ny_sib) ? p.My - oy : oy;
-            A[(long long)(r * 12 + c) * p.s_b + z * p.s_z + y * p.s_y + k] = buf[lds_pad((g * 12 + c) * p.pitch + k)];
+            A[(long long)r * p.s_r + c * p.s_c + z * p.s_z + y * p.s_y + k] = buf[lds_pad((g * 12 + c) * p.pitch + k)];
         }
         __syncthreads();
     }
@@ -222,24 +224,24 @@ __global__ void __launch_bounds__(p3_threads<R>()) k_p3_ct(C<R>* __restrict__ A,
     C<R>* buf = twl + N;
     __shared__ long long rowoff[MAXROWS];
     const int tid = threadIdx.x;
-    const int row = blockIdx.x;
+    const int row = blockIdx.x / p.sib_blocks, sb = blockIdx.x - row * p.sib_blocks;
     const int oz = row / p.Oy, oy = row - oz * p.Oy;
     const int ny_sib = (oy == 0 || 2 * oy == p.My) ? 1 : 2;
     const int nz_sib = (oz == 0 || 2 * oz == p.Mz) ? 1 : 2;
     const int nsib = ny_sib * nz_sib;
-    const int nwork = nsib * p.nrhs;
+    // this workgroup's siblings: sb, sb + sib_blocks, ... (< nsib)
+    const int my_nsib = sb < nsib ? (nsib - sb + p.sib_blocks - 1) / p.sib_blocks : 0;
+    if (my_nsib == 0) return;   // uniform over the workgroup
+    const int nwork = my_nsib * p.nrhs;
     {
-        const C<R>* Urow = U + (long long)(oz * p.Oy + oy) * OX;
+        const C<R>* Urow = U + (long long)(oz * p.Oy + oy) * 60 * OX;
         constexpr int TOT = 60 * OX;
         for (int b0 = 0; b0 < TOT; b0 += 8 * NT) {
             C<R> v[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int e = b0 + tid + i * NT;
-                if (e < TOT) {
-                    const int eu = e / OX, ox = e - eu * OX;
-                    v[i] = Urow[eu * p.u_e + ox];
-                }
+                if (e < TOT) v[i] = Urow[e];
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
@@ -254,10 +256,10 @@ __global__ void __launch_bounds__(p3_threads<R>()) k_p3_ct(C<R>* __restrict__ A,
         const int rows = 12 * G;
         if (tid < rows) {
             const int g = tid / 12, c = tid - 12 * g;
-            const int wk = w0 + g, r = wk / nsib, sib = wk - r * nsib;
+            const int wk = w0 + g, r = wk / my_nsib, sib = sb + (wk - r * my_nsib) * p.sib_blocks;
             const int z = (sib / ny_sib) ? p.Mz - oz : oz;
             const int y = (sib % ny_sib) ? p.My - oy : oy;
-            rowoff[tid] = (long long)(r * 12 + c) * p.s_b + (long long)z * p.s_z + (long long)y * p.s_y;
+            rowoff[tid] = (long long)r * p.s_r + (long long)c * p.s_c + (long long)z * p.s_z + (long long)y * p.s_y;
         }
         __syncthreads();
         // gather rows x Nx, zero the padding
@@ -296,7 +298,7 @@ __global__ void __launch_bounds__(p3_threads<R>()) k_p3_ct(C<R>* __restrict__ A,
             unsigned mask = 0;
             int ox = 0;
             if (act) {
-                const int wk = w0 + g, sib = wk % nsib;
+                const int wk = w0 + g, sib = sb + (wk % my_nsib) * p.sib_blocks;
                 const int sz = sib / ny_sib, sy = sib % ny_sib;
                 const int fx = 2 * xi > N;
                 ox = fx ? N - xi : xi;
@@ -345,6 +347,129 @@ __global__ void __launch_bounds__(p3_threads<R>()) k_p3_ct(C<R>* __restrict__ A,
     }
 }
 
+// Light variant of the x pass: one workgroup of 256 threads per pencil group
+// (one right-hand side, one of the up to four sibling pencils of an octant
+// row), 12 rows of N in LDS and nothing else, so that many workgroups share a
+// CU.  The block product runs one thread per frequency in the orbit form: each
+// of the 60 unique operator values is read once (from L2: the four siblings
+// of a row read the same values) and applied to the up to four positions it
+// fills.
+constexpr int kP3SmallThreads = 256;
+
+template <typename R, int E, int K>
+__device__ __forceinline__ void orbit_apply(C<R>* yv, const C<R>* xv, C<R> u) {
+    constexpr Orbits o = make_orbits();
+    if constexpr (K < o.cnt[E]) {
+        constexpr int a = o.m[E][K].a, b = o.m[E][K].b, sg = o.m[E][K].s;
+        if constexpr (sg > 0) cfma(yv[a], u, xv[b]);
+        else cfma(yv[a], mk<R>(-u.x, -u.y), xv[b]);
+        orbit_apply<R, E, K + 1>(yv, xv, u);
+    }
+}
+
+template <typename R, int E>
+__device__ __forceinline__ void orbit_product(C<R>* yv, const C<R>* xv, const C<R>* __restrict__ Ur, int ox, int OXs) {
+    if constexpr (E < 60) {
+        orbit_apply<R, E, 0>(yv, xv, Ur[E * OXs + ox]);
+        orbit_product<R, E + 1>(yv, xv, Ur, ox, OXs);
+    }
+}
+
+template <typename R, int N>
+__global__ void __launch_bounds__(kP3SmallThreads) k_p3_small(C<R>* __restrict__ A, const C<R>* __restrict__ U,
+                                                              P3Params p, const C<R>* __restrict__ tw) {
+    constexpr int NT = kP3SmallThreads;
+    constexpr int OX = N / 2 + 1;
+    extern __shared__ unsigned char smem_raw[];
+    C<R>* twl = reinterpret_cast<C<R>*>(smem_raw);
+    C<R>* buf = twl + N;
+    const int tid = threadIdx.x;
+    // block -> (right-hand side, octant row, sibling)
+    const int sib = blockIdx.x & 3;
+    const int row = (blockIdx.x >> 2) % (p.Oy * p.Oz);
+    const int r = (blockIdx.x >> 2) / (p.Oy * p.Oz);
+    const int oz = row / p.Oy, oy = row - oz * p.Oy;
+    const int ny_sib = (oy == 0 || 2 * oy == p.My) ? 1 : 2;
+    const int nz_sib = (oz == 0 || 2 * oz == p.Mz) ? 1 : 2;
+    if (sib >= ny_sib * nz_sib) return;   // uniform over the workgroup
+    const int sz = sib / ny_sib, sy = sib - sz * ny_sib;
+    const int z = sz ? p.Mz - oz : oz;
+    const int y = sy ? p.My - oy : oy;
+    C<R>* base = A + (long long)r * p.s_r + (long long)z * p.s_z + (long long)y * p.s_y;   // 12 rows of Nx, stride s_c
+    for (int m = tid; m < N; m += NT) twl[m] = tw[m];
+    // gather (the 12 rows are one contiguous block when s_c == Nx)
+    const int tot = 12 * p.Nx;
+    for (int b0 = 0; b0 < tot; b0 += 4 * NT) {
+        C<R> v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = b0 + tid + i * NT;
+            if (e < tot) {
+                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
+                v[i] = base[(long long)c * p.s_c + k];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = b0 + tid + i * NT;
+            if (e < tot) {
+                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
+                buf[lds_pad(c * N + k)] = v[i];
+            }
+        }
+    }
+    for (int e = tid; e < 12 * N; e += NT) {
+        const int c = e / N, k = e - c * N;
+        if (k >= p.Nx) buf[lds_pad(e)] = mk<R>(0, 0);
+    }
+    __syncthreads();
+    ct_passes<R, true, N, 0, 1, NT, 12>(buf, twl, 12, N, tid);
+    {
+        const C<R>* Ur = U + (long long)row * 60 * OX;
+        for (int xi = tid; xi < N; xi += NT) {
+            const int fx = 2 * xi > N;
+            const int ox = fx ? N - xi : xi;
+            const unsigned mask = fold_mask(fx, sy, sz);
+            C<R> xv[12], yv[12];
+#pragma unroll
+            for (int a = 0; a < 12; ++a) {
+                C<R> v = buf[lds_pad(a * N + xi)];
+                if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                xv[a] = v;
+                yv[a] = mk<R>(0, 0);
+            }
+            orbit_product<R, 0>(yv, xv, Ur, ox, OX);
+#pragma unroll
+            for (int a = 0; a < 12; ++a) {
+                C<R> v = yv[a];
+                if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                buf[lds_pad(a * N + xi)] = v;   // own column: in place
+            }
+        }
+    }
+    __syncthreads();
+    ct_passes<R, false, N, 0, 1, NT, 12>(buf, twl, 12, N, tid);
+    for (int b0 = 0; b0 < tot; b0 += 4 * NT) {
+        C<R> v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = b0 + tid + i * NT;
+            if (e < tot) {
+                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
+                v[i] = buf[lds_pad(c * N + k)];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = b0 + tid + i * NT;
+            if (e < tot) {
+                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
+                base[(long long)c * p.s_c + k] = v[i];
+            }
+        }
+    }
+}
+
 // lengths with a compile-time kernel
 #define VIE_P3_LENGTHS(X) X(8) X(16) X(32) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
 
@@ -358,14 +483,23 @@ bool p3_ct_supported(int n) {
     }
 }
 
-int p3_ct_groups(int es, int n) { return p3_gmax(es, n, es == 8 ? 1024 : 512); }
+int p3_ct_groups(int es, int n) { return p3_gmax(es, n, 512); }
+
+template <typename R, int N>
+static void launch_p3_small_n(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
+    const size_t lds = ((size_t)N + lds_pad(12 * N) + 2) * sizeof(C<R>);
+    const long long nblk = 4LL * p.Oy * p.Oz * p.nrhs;
+    VIE_REQUIRE(nblk < (1LL << 31), -1, "x pass: too many workgroups");
+    hipLaunchKernelGGL((k_p3_small<R, N>), dim3((unsigned)nblk), dim3(kP3SmallThreads), lds, s, A, U, p, tw);
+    VIE_HIP(hipGetLastError());
+}
 
 template <typename R, int N>
 static void launch_p3_ct_n(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
     constexpr int NT = p3_threads<R>();
     constexpr int GMAX = p3_gmax(sizeof(C<R>), N, NT);
     VIE_REQUIRE(p.groups >= 1 && p.groups <= GMAX && p.Ox == N / 2 + 1, -1, "x pass: bad group count");
-    const size_t lds = (size_t)p3_lds_bytes(sizeof(C<R>), N, GMAX);
+    const size_t lds = (size_t)p3_lds_bytes(sizeof(C<R>), N, p.groups);
     static bool attr = false;
     if (!attr) {
         // allow more than the default 64 KiB of dynamic LDS; a refusal shows
@@ -374,7 +508,8 @@ static void launch_p3_ct_n(C<R>* A, const C<R>* U, const P3Params& p, const C<R>
         (void)hipGetLastError();
         attr = true;
     }
-    hipLaunchKernelGGL((k_p3_ct<R, N>), dim3(p.Oy * p.Oz), dim3(NT), lds, s, A, U, p, tw);
+    VIE_REQUIRE(p.sib_blocks == 1 || p.sib_blocks == 2 || p.sib_blocks == 4, -1, "x pass: bad sibling split");
+    hipLaunchKernelGGL((k_p3_ct<R, N>), dim3(p.Oy * p.Oz * p.sib_blocks), dim3(NT), lds, s, A, U, p, tw);
     VIE_HIP(hipGetLastError());
 }
 
@@ -439,7 +574,11 @@ void launch_strided(bool fwd, const C<R>* in, C<R>* out, const StridedPass& p, l
 template <typename R>
 void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
     switch (p.plan.n) {
-#define CASE(n_) case n_: launch_p3_ct_n<R, n_>(A, U, p, tw, s); return;
+#define CASE(n_)                                                                          \
+    case n_:                                                                             \
+        if (p.variant == 1) launch_p3_small_n<R, n_>(A, U, p, tw, s);                    \
+        else launch_p3_ct_n<R, n_>(A, U, p, tw, s);                                      \
+        return;
         VIE_P3_LENGTHS(CASE)
 #undef CASE
         default: break;

@@ -1,0 +1,83 @@
+// Autotuner for the launch shapes of the operator product: times each
+// candidate with HIP events on the context stream and keeps the fastest per
+// (precision, nrhs).  The candidates only change the work distribution; the
+// two x-pass variants add the terms of the block product in different
+// orders, so their results agree to rounding.
+#include <vector>
+
+#include "ctx.hpp"
+
+namespace vie {
+
+template <typename R>
+static double time_apply(Ctx& c, int nrhs, const C<R>* x, C<R>* y, int reps) {
+    hipEvent_t a, b;
+    VIE_HIP(hipEventCreate(&a));
+    VIE_HIP(hipEventCreate(&b));
+    apply_op<R>(c, OP_N, nrhs, x, y, nullptr);   // warm up this shape
+    VIE_HIP(hipEventRecord(a, c.stream));
+    for (int i = 0; i < reps; ++i) apply_op<R>(c, OP_N, nrhs, x, y, nullptr);
+    VIE_HIP(hipEventRecord(b, c.stream));
+    VIE_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    VIE_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms / reps;
+}
+
+template <typename R>
+static Tune tune_t(Ctx& c, int nrhs, double* best_ms) {
+    const size_t n = (size_t)12 * c.V * nrhs;
+    C<R>* x = nullptr;
+    C<R>* y = nullptr;
+    VIE_HIP(hipMalloc(&x, n * sizeof(C<R>)));
+    VIE_HIP(hipMalloc(&y, n * sizeof(C<R>)));
+    VIE_HIP(hipMemsetAsync(x, 0, n * sizeof(C<R>), c.stream));
+    const int key0 = sizeof(R) == 4 ? 0 : 1;
+    std::vector<Tune> cands;
+    for (int var = 0; var <= 1; ++var)
+        for (int sb : {1, 2, 4}) {
+            if (var == 1 && sb != 1) continue;
+            for (int tz : {8, 16})
+                for (int ty : {8, 16}) {
+                    Tune t;
+                    t.p3_variant = var;
+                    t.p3_sib_blocks = sb;
+                    t.tile_z = tz;
+                    t.tile_y = ty;
+                    // keep the two-buffer tile within 96 KiB of LDS
+                    if (2LL * tz * c.M[2] * sizeof(C<R>) > 96 * 1024 || 2LL * ty * c.M[1] * sizeof(C<R>) > 96 * 1024)
+                        continue;
+                    cands.push_back(t);
+                }
+        }
+    Tune best;
+    double bms = 1e30;
+    const int reps = c.V * nrhs > 4000000 ? 2 : 5;
+    try {
+        for (const Tune& t : cands) {
+            c.tune[{key0, nrhs}] = t;
+            const double ms = time_apply<R>(c, nrhs, x, y, reps);
+            if (ms < bms) {
+                bms = ms;
+                best = t;
+            }
+        }
+    } catch (...) {
+        (void)hipFree(x);
+        (void)hipFree(y);
+        throw;
+    }
+    VIE_HIP(hipFree(x));
+    VIE_HIP(hipFree(y));
+    c.tune[{key0, nrhs}] = best;
+    if (best_ms) *best_ms = bms;
+    return best;
+}
+
+Tune autotune(Ctx& c, int precision, int nrhs, double* best_ms) {
+    return precision == VIE_C64 ? tune_t<float>(c, nrhs, best_ms) : tune_t<double>(c, nrhs, best_ms);
+}
+
+}  // namespace vie

@@ -227,3 +227,22 @@ def test_errors_are_reported(vie, torch):
     with pytest.raises(vie.VieError) as ei:
         c.apply(x, torch.empty_like(x), op=vie.OP_PREC)   # no contrast yet
     assert ei.value.code == vie.VIE_ESTATE
+
+
+def test_autotuned_shapes_keep_results(vie, torch):
+    """Every launch shape the autotuner may pick computes the same product
+    (to rounding: the x-pass variants sum the block terms in another order)."""
+    N, D = (16, 12, 10), (0.005,) * 3
+    c = _ctx(vie, torch, N, D)
+    e, s = vi.ellipsoid_phantom(N, D, 8)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    x = torch.from_numpy(np.stack([vec_to_lib(vi.complex_normal(30 + r, (12,) + N)) for r in range(2)]))
+    for dtype, tol in ((torch.complex64, 2e-6), (torch.complex128, 1e-13)):
+        xd = x.to("cuda", dtype)
+        y0 = torch.empty_like(xd)
+        c.apply(xd, y0, op=vie.OP_PREC)
+        choice, ms = c.autotune(vie.C64 if dtype == torch.complex64 else vie.C128, 2)
+        _say("  autotune %s: %s %.3f ms" % (dtype, choice, ms))
+        y1 = torch.empty_like(xd)
+        c.apply(xd, y1, op=vie.OP_PREC)
+        assert float((y1 - y0).abs().max() / y0.abs().max()) < tol
