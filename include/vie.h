@@ -185,6 +185,14 @@ int vie_absorbed_power(vie_ctx* ctx, int nrhs, const void* x, double* p_abs_host
  * FP64 device array [nrhs][Nz][Ny][Nx], from field coefficients e. */
 int vie_power_density(vie_ctx* ctx, int nrhs, const void* e, double* p_dev);
 
+/* -- utilities -------------------------------------------------------------- */
+
+/* Device copy of n complex128 values (src, dst device pointers, not
+ * overlapping) on the context stream: a plain streaming kernel of known
+ * traffic (16 n bytes read, 16 n written), used to calibrate memory
+ * counters. */
+int vie_copy(vie_ctx* ctx, const void* src, void* dst, long long n);
+
 /* -- autotuning ------------------------------------------------------------ */
 
 /* Time the candidate launch shapes of the operator product (x-pass variant,
@@ -207,8 +215,9 @@ enum {
     VIE_K_BLOCK = 2,      /* fused x FFT, 12 x 12 block product, inverse x FFT */
     VIE_K_FFT_Y_INV = 3,  /* inverse FFT along y with crop                    */
     VIE_K_FFT_Z_INV = 4,  /* inverse FFT along z, crop, contrast epilogue     */
-    VIE_K_ARNOLDI = 5,    /* Gram-Schmidt kernels (dots, updates, norms)      */
-    VIE_K_COUNT = 6
+    VIE_K_GS_DOT = 5,     /* Gram-Schmidt inner products (and their reduction) */
+    VIE_K_GS_UPDATE = 6,  /* Gram-Schmidt update, norm and normalisation      */
+    VIE_K_COUNT = 7
 };
 
 /* enable = 1 clears the records and starts timing every launch of the

@@ -23,7 +23,7 @@ VIE_OK, VIE_EINVAL, VIE_ENOMEM, VIE_EDEVICE, VIE_ENOCONV, VIE_ENAN, VIE_ESTATE =
 C64, C128 = 0, 1
 OP_PREC, OP_A, OP_N = 0, 1, 2
 SOLVE_FP64, SOLVE_FP32_IR = 0, 1
-KERNELS = ("fft_z_fwd", "fft_y_fwd", "block", "fft_y_inv", "fft_z_inv", "arnoldi")
+KERNELS = ("fft_z_fwd", "fft_y_fwd", "block", "fft_y_inv", "fft_z_inv", "gs_dot", "gs_update")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libvie.so is not built; run `python -m paper_1902_02196_amd.build` (needs hipcc)")
@@ -66,6 +66,7 @@ _sig = {
     "vie_fields": (_i, [_vp, _i, _vp, _vp]),
     "vie_absorbed_power": (_i, [_vp, _i, _vp, _dp]),
     "vie_power_density": (_i, [_vp, _i, _vp, _vp]),
+    "vie_copy": (_i, [_vp, _vp, _vp, ctypes.c_longlong]),
     "vie_autotune": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _dp]),
     "vie_profile": (_i, [_vp, _i]),
     "vie_profile_read": (_i, [_vp, _i, _dp, ctypes.POINTER(_i), _dp]),
@@ -246,6 +247,12 @@ class Context:
         out = np.zeros(n)
         _check(_lib.vie_absorbed_power(self._h, n, _tensor_ptr(x, torch.complex128, self.vec_shape(n)), _dptr(out)))
         return out
+
+    def copy(self, src, dst):
+        """Device copy of complex128 tensors (plain streaming kernel)."""
+        import torch
+        assert src.dtype == torch.complex128 and dst.shape == src.shape
+        _check(_lib.vie_copy(self._h, _tensor_ptr(src), _tensor_ptr(dst), src.numel()))
 
     def autotune(self, precision=C64, nrhs=1):
         """Pick the fastest launch shapes for this grid; returns (choice, ms)."""

@@ -405,6 +405,16 @@ int vie_power_density(vie_ctx* ctx, int nrhs, const void* e, double* p_dev) {
     });
 }
 
+int vie_copy(vie_ctx* ctx, const void* src, void* dst, long long n) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(src && dst && n >= 0, VIE_EINVAL, "bad copy arguments");
+        if (n > 0) launch_copy_c128(static_cast<double2*>(dst), static_cast<const double2*>(src), n, c.stream);
+    });
+}
+
 int vie_autotune(vie_ctx* ctx, int precision, int nrhs, int* choice, double* best_ms) {
     return guarded([&] {
         check_ctx(ctx);

@@ -384,10 +384,16 @@ __global__ void __launch_bounds__(kP3SmallThreads) k_p3_small(C<R>* __restrict__
     C<R>* twl = reinterpret_cast<C<R>*>(smem_raw);
     C<R>* buf = twl + N;
     const int tid = threadIdx.x;
-    // block -> (right-hand side, octant row, sibling)
-    const int sib = blockIdx.x & 3;
-    const int row = (blockIdx.x >> 2) % (p.Oy * p.Oz);
-    const int r = (blockIdx.x >> 2) / (p.Oy * p.Oz);
+    // block -> (octant row, right-hand side, sibling).  Workgroups are dealt
+    // to the 8 XCDs round-robin by index, so the 4 * nrhs workgroups that read
+    // one operator row get indices congruent modulo 8: they run on one XCD
+    // and share its L2.
+    const int K = 4 * p.nrhs;
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+    const int row = (q / K) * 8 + xcd;
+    if (row >= p.Oy * p.Oz) return;       // padding rows, uniform over the workgroup
+    const int kk = q - (q / K) * K;
+    const int r = kk >> 2, sib = kk & 3;
     const int oz = row / p.Oy, oy = row - oz * p.Oy;
     const int ny_sib = (oy == 0 || 2 * oy == p.My) ? 1 : 2;
     const int nz_sib = (oz == 0 || 2 * oz == p.Mz) ? 1 : 2;
@@ -488,7 +494,8 @@ int p3_ct_groups(int es, int n) { return p3_gmax(es, n, 512); }
 template <typename R, int N>
 static void launch_p3_small_n(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
     const size_t lds = ((size_t)N + lds_pad(12 * N) + 2) * sizeof(C<R>);
-    const long long nblk = 4LL * p.Oy * p.Oz * p.nrhs;
+    const long long rows8 = ((long long)p.Oy * p.Oz + 7) / 8 * 8;
+    const long long nblk = rows8 * 4LL * p.nrhs;
     VIE_REQUIRE(nblk < (1LL << 31), -1, "x pass: too many workgroups");
     hipLaunchKernelGGL((k_p3_small<R, N>), dim3((unsigned)nblk), dim3(kP3SmallThreads), lds, s, A, U, p, tw);
     VIE_HIP(hipGetLastError());

@@ -111,21 +111,28 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
             C<R>* w = Vb + (long long)(j + 1) * ldv;
             apply_op<R>(c, OP_PREC, na, vj, w, nullptr);
             const int nvec = j + 1;
-            // Gram-Schmidt traffic: each pass reads the basis and w for the
-            // dots, then the basis again and w read+write for the update
-            const double pass_bytes = (double)na * n * sizeof(C<R>) * (2.0 * nvec + 3.0);
-            {
-            ProfScope ps(c.prof, c.stream, VIE_K_ARNOLDI, (o.reorth ? 2 : 1) * pass_bytes + (double)na * n * sizeof(C<R>) * 2);
-            launch_multidot<R>(L.partial, Vb, ldv, nvec, w, n, n, n, na, nb, c.stream);
-            launch_reduce_partials(L.h1, L.partial, nvec, nb, na, c.stream);
-            launch_update<R>(w, Vb, ldv, nvec, L.h1, n, n, n, L.npart, na, nb, c.stream);
-            if (o.reorth) {
-                launch_multidot<R>(L.partial, Vb, ldv, nvec, w, n, n, n, na, nb, c.stream);
-                launch_reduce_partials(L.h2, L.partial, nvec, nb, na, c.stream);
-                launch_update<R>(w, Vb, ldv, nvec, L.h2, n, n, n, L.npart, na, nb, c.stream);
-            }
-            launch_reduce_norm(L.nrm, L.npart, nb, na, c.stream);
-            launch_scale_into<R>(w, w, L.nrm, n, n, n, na, c.stream);
+            // Gram-Schmidt, per pass: the dot kernel reads the j + 1 basis
+            // vectors and w (w once per group of 16 basis vectors); the
+            // update reads them again and writes w; normalising reads and
+            // writes w once more
+            const double vb = (double)na * n * sizeof(C<R>);
+            const double dot_bytes = vb * (nvec + (nvec + 15) / 16);
+            const double upd_bytes = vb * (nvec + 2);
+            for (int pass = 0; pass < (o.reorth ? 2 : 1); ++pass) {
+                double2* hp = pass ? L.h2 : L.h1;
+                {
+                    ProfScope ps(c.prof, c.stream, VIE_K_GS_DOT, dot_bytes);
+                    launch_multidot<R>(L.partial, Vb, ldv, nvec, w, n, n, n, na, nb, c.stream);
+                    launch_reduce_partials(hp, L.partial, nvec, nb, na, c.stream);
+                }
+                {
+                    ProfScope ps(c.prof, c.stream, VIE_K_GS_UPDATE, upd_bytes + (pass == (o.reorth ? 1 : 0) ? 2 * vb : 0));
+                    launch_update<R>(w, Vb, ldv, nvec, hp, n, n, n, L.npart, na, nb, c.stream);
+                    if (pass == (o.reorth ? 1 : 0)) {
+                        launch_reduce_norm(L.nrm, L.npart, nb, na, c.stream);
+                        launch_scale_into<R>(w, w, L.nrm, n, n, n, na, c.stream);
+                    }
+                }
             }
             VIE_HIP(hipMemcpyAsync(h1.data(), L.h1, (size_t)na * nvec * sizeof(double2), hipMemcpyDeviceToHost,
                                    c.stream));
