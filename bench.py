@@ -100,12 +100,114 @@ def cpu_baseline(N, h, f, mv_per_solve, seconds_budget=25.0):
                       % (len(times), cores, Nx, Ny, Nz, t_mv, mv_per_solve, t_setup)}
 
 
+SERVING = dict(edges=(32, 48, 64, 96, 128), h=0.003, freqs=(128e6, 298e6), rate=20.0, max_rhs=8,
+               seed=190202196 + 4)
+
+
+def serving_stream(n_req, seed):
+    """Seeded finite Poisson stream: arrival offsets (s) and per-request
+    (edge, frequency, dipole count, phantom seed, dipole seed)."""
+    import vie_inputs as vi
+    g = vi.rng(seed)
+    gaps = g.exponential(1.0 / SERVING["rate"], size=n_req)
+    t = np.cumsum(gaps) - gaps[0]
+    reqs = []
+    for i in range(n_req):
+        edge = int(g.choice(SERVING["edges"]))
+        f = float(g.choice(SERVING["freqs"]))
+        nrhs = int(g.integers(1, SERVING["max_rhs"] + 1))
+        reqs.append((edge, f, nrhs, seed + 1000 + i, seed + 2000 + i))
+    return t, reqs
+
+
+def serving_main(args):
+    """Continuous-batching server fed by a seeded Poisson stream: latency
+    percentiles (completion - arrival) and sustained solve rate."""
+    import threading
+    import torch
+    import paper_1902_02196_amd as vie
+    import vie_inputs as vi
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    h = SERVING["h"]
+    t_arr, reqs = serving_stream(args.requests, SERVING["seed"])
+    inputs = []
+    for edge, f, nrhs, pseed, dseed in reqs:
+        N = (edge, edge, edge)
+        e, s = vi.ellipsoid_phantom(N, (h, h, h), pseed)
+        pos, mom = vi.dipoles_on_cylinder(dseed, nrhs, 0.75 * edge * h, edge * h)
+        inputs.append((N, f, np.ascontiguousarray(e.transpose(2, 1, 0)),
+                       np.ascontiguousarray(s.transpose(2, 1, 0)), pos, mom))
+    log("serving stream: %s" % [(r[0], int(r[1] / 1e6), r[2]) for r in reqs])
+    srv = vie.Server(0, hbm_budget=int(args.hbm_budget_gb * 2 ** 30), max_slots=args.slots)
+
+    def submit(i):
+        N, f, e, s, pos, mom = inputs[i]
+        return srv.submit(N, (h, h, h), f, e, s, pos, mom, mode=vie.SOLVE_FP32_IR, tol=1e-6,
+                          restart=args.restart)
+
+    # warm-up request (kernel loading, first allocations), left out of the stats
+    wid = submit(0)
+    srv.wait()
+    ids = []
+    t0 = time.perf_counter()
+    for i in range(len(inputs)):
+        delay = t_arr[i] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(submit(i))
+        log("submitted %d at %.3f s" % (i, time.perf_counter() - t0))
+    srv.wait()
+    wall = time.perf_counter() - t0
+    st = srv.stats(first_id=wid + 1)
+    infos = [srv.poll(i) for i in ids]
+    bad = [(i, d["status"], d["message"]) for i, d in zip(ids, infos) if d["status"] != 0]
+    assert not bad, bad
+    nrhs_total = sum(r[2] for r in reqs)
+    srv.close()
+    out = {
+        "metric": "serving: solves/s at 1e-6 relative residual with p50/p99 latency (continuous batching)",
+        "value": round(len(ids) / st["makespan_s"], 4),
+        "unit": "requests/s",
+        "n_gpus": 1,
+        "steps": len(ids),
+        "warmup": 1,
+        "ms_per_step": round(1e3 * st["makespan_s"] / len(ids), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 (FP64 refinement)",
+        "data": "synthetic",
+        "config": {"workload": "serving: %d requests, Poisson arrivals at %.0f req/s, edge in %s voxels at %.0f mm, "
+                               "1-%d dipoles, %s MHz, 6-class ellipsoid phantoms, GMRES(%d) to 1e-6, "
+                               "%d slots, %.0f GiB budget"
+                               % (len(ids), SERVING["rate"], list(SERVING["edges"]), h * 1e3, SERVING["max_rhs"],
+                                  [int(v / 1e6) for v in SERVING["freqs"]], args.restart, args.slots,
+                                  args.hbm_budget_gb)},
+        "p50_s": round(st["p50_s"], 4),
+        "p99_s": round(st["p99_s"], 4),
+        "mean_s": round(st["mean_s"], 4),
+        "rhs_solves_per_s": round(nrhs_total / st["makespan_s"], 4),
+        "offered_req_per_s": SERVING["rate"],
+        "makespan_s": round(st["makespan_s"], 3),
+        "wall_s": round(wall, 3),
+        "peak_running": st["peak_running"],
+        "peak_bytes": st["peak_bytes"],
+        "iterations": [d["iterations"] for d in infos],
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="phantom64", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="phantom64", choices=sorted(WORKLOADS) + ["serving"])
+    ap.add_argument("--requests", type=int, default=12, help="serving: requests in the stream")
+    ap.add_argument("--slots", type=int, default=4, help="serving: concurrent solves")
+    ap.add_argument("--hbm-budget-gb", type=float, default=200.0, help="serving: admission budget")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--reorth", type=int, default=0, help="second Gram-Schmidt pass (1) or not (0)")
     ap.add_argument("--restart", type=int, default=50)
@@ -114,6 +216,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "serving":
+        return serving_main(args)
 
     import torch
     import paper_1902_02196_amd as vie

@@ -230,6 +230,73 @@ int vie_profile(vie_ctx* ctx, int enable);
  * Synchronises the stream. */
 int vie_profile_read(vie_ctx* ctx, int kind, double* total_ms, int* launches, double* bytes);
 
+/* -- serving: continuous batching of solve requests ------------------------ */
+
+typedef struct vie_server vie_server;
+
+/* One solve request: its own grid, tissue map (host [Nz][Ny][Nx], eps' and
+ * sigma), nrhs Hertzian-dipole excitations (host [nrhs][3] positions in m and
+ * current moments in A m) and solver options (mode VIE_SOLVE_*, tol <= 0 for
+ * 1e-6, restart <= 0 for 50).  Inputs are copied at submission.  x_out (host
+ * [nrhs][12][Nz][Ny][Nx] complex128) and p_abs_out (host [nrhs]) are optional
+ * and must stay valid until the request is done. */
+typedef struct {
+    int nx, ny, nz;
+    double dx, dy, dz, freq_hz;
+    const double* eps_re;
+    const double* sigma;
+    int nrhs;
+    const double* pos;
+    const double* moment;
+    int mode;
+    double tol;
+    int restart;
+    double* x_out;
+    double* p_abs_out;
+} vie_request;
+
+typedef struct {
+    int done;            /* 1 when finished                                   */
+    int status;          /* vie_status of the solve                           */
+    double t_arrival;    /* seconds since the server started                  */
+    double t_start;      /* admission time                                    */
+    double t_end;        /* completion time                                   */
+    size_t footprint;    /* device bytes reserved for it at admission         */
+    int iterations;      /* most GMRES iterations over its right-hand sides   */
+    double rel_residual; /* largest final relative residual                   */
+    char message[192];   /* error text when status != VIE_OK                  */
+} vie_request_info;
+
+typedef struct {
+    int completed, queued, running, peak_running;
+    double p50_s, p99_s, mean_s; /* latency = completion - arrival            */
+    double makespan_s;           /* first arrival to last completion          */
+    size_t peak_bytes;           /* largest sum of admitted footprints         */
+} vie_serving_stats;
+
+/* Create a server on HIP device `device` that admits requests while the sum
+ * of their footprints (vie_footprint_bytes plus the request vectors) stays
+ * within hbm_budget bytes and at most max_slots run at once.  Each admitted
+ * request runs on its own worker thread, context and stream. */
+int vie_server_create(vie_server** out, int device, size_t hbm_budget, int max_slots);
+
+/* Queue a request (returns at once); *id identifies it.  VIE_ENOMEM when its
+ * footprint exceeds the whole budget, VIE_EINVAL on bad arguments. */
+int vie_server_submit(vie_server* s, const vie_request* r, long long* id);
+
+/* State and timing of a request. */
+int vie_server_poll(vie_server* s, long long id, vie_request_info* info);
+
+/* Block until every submitted request has finished. */
+int vie_server_wait(vie_server* s);
+
+/* Latency percentiles (nearest rank) and counts over finished requests with
+ * id >= first_id (to leave out a warm-up prefix). */
+int vie_server_stats(vie_server* s, long long first_id, vie_serving_stats* out);
+
+/* Wait for running requests, drop queued ones, free everything. */
+void vie_server_destroy(vie_server* s);
+
 /* -- memory model (Sec. V, "unknowns memory") ------------------------------ */
 
 /* Bytes the paper counts as unknowns memory: 12 unknowns x 8 N_V padded

@@ -48,6 +48,23 @@ class SolveStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("nx", _i), ("ny", _i), ("nz", _i), ("dx", _d), ("dy", _d), ("dz", _d), ("freq_hz", _d),
+                ("eps_re", _dp), ("sigma", _dp), ("nrhs", _i), ("pos", _dp), ("moment", _dp), ("mode", _i),
+                ("tol", _d), ("restart", _i), ("x_out", _dp), ("p_abs_out", _dp)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("done", _i), ("status", _i), ("t_arrival", _d), ("t_start", _d), ("t_end", _d),
+                ("footprint", ctypes.c_size_t), ("iterations", _i), ("rel_residual", _d),
+                ("message", ctypes.c_char * 192)]
+
+
+class ServingStats(ctypes.Structure):
+    _fields_ = [("completed", _i), ("queued", _i), ("running", _i), ("peak_running", _i), ("p50_s", _d),
+                ("p99_s", _d), ("mean_s", _d), ("makespan_s", _d), ("peak_bytes", ctypes.c_size_t)]
+
+
 _sig = {
     "vie_create": (_i, [ctypes.POINTER(_vp), _i, _vp]),
     "vie_destroy": (None, [_vp]),
@@ -70,6 +87,12 @@ _sig = {
     "vie_autotune": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _dp]),
     "vie_profile": (_i, [_vp, _i]),
     "vie_profile_read": (_i, [_vp, _i, _dp, ctypes.POINTER(_i), _dp]),
+    "vie_server_create": (_i, [ctypes.POINTER(_vp), _i, ctypes.c_size_t, _i]),
+    "vie_server_submit": (_i, [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_longlong)]),
+    "vie_server_poll": (_i, [_vp, ctypes.c_longlong, ctypes.POINTER(RequestInfo)]),
+    "vie_server_wait": (_i, [_vp]),
+    "vie_server_stats": (_i, [_vp, ctypes.c_longlong, ctypes.POINTER(ServingStats)]),
+    "vie_server_destroy": (None, [_vp]),
     "vie_unknowns_bytes_paper": (ctypes.c_size_t, [_i, _i, _i]),
     "vie_footprint_bytes": (_i, [_i, _i, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_size_t)]),
 }
@@ -278,3 +301,75 @@ class Context:
         n = e.shape[0]
         _check(_lib.vie_power_density(self._h, n, _tensor_ptr(e, torch.complex128, self.vec_shape(n)),
                                       _tensor_ptr(out, torch.float64, (n, self.N[2], self.N[1], self.N[0]))))
+
+
+class Server:
+    """Continuous-batching solve server on one GPU (C++ scheduler and worker
+    threads in the library).  Requests are admitted while their device
+    footprints fit ``hbm_budget`` bytes and at most ``max_slots`` run at once;
+    each runs on its own context and stream.  Results land in host arrays
+    owned by this object until :meth:`result` hands them out."""
+
+    def __init__(self, device=0, hbm_budget=64 << 30, max_slots=4):
+        h = ctypes.c_void_p()
+        _check(_lib.vie_server_create(ctypes.byref(h), int(device), int(hbm_budget), int(max_slots)))
+        self._h = h
+        self._held = {}
+
+    def close(self):
+        if self._h:
+            _lib.vie_server_destroy(self._h)
+            self._h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, N, Delta, freq_hz, eps_re, sigma, positions, moments, mode=SOLVE_FP32_IR, tol=1e-6,
+               restart=50, want_x=False):
+        """Queue one request (nrhs = number of dipoles); returns its id."""
+        nx, ny, nz = (int(v) for v in N)
+        e = np.ascontiguousarray(eps_re, dtype=np.float64)
+        sg = np.ascontiguousarray(sigma, dtype=np.float64)
+        if e.shape != (nz, ny, nx) or sg.shape != (nz, ny, nx):
+            raise ValueError("eps_re and sigma must have shape (Nz, Ny, Nx)")
+        pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
+        mom = np.ascontiguousarray(moments, dtype=np.float64).reshape(-1, 3)
+        if pos.shape != mom.shape:
+            raise ValueError("positions and moments differ in length")
+        n = pos.shape[0]
+        p_abs = np.zeros(n)
+        x = np.zeros((n, 12, nz, ny, nx), dtype=np.complex128) if want_x else None
+        r = Request(nx, ny, nz, float(Delta[0]), float(Delta[1]), float(Delta[2]), float(freq_hz), _dptr(e),
+                    _dptr(sg), n, _dptr(pos), _dptr(mom), int(mode), float(tol), int(restart),
+                    x.view(np.float64).ctypes.data_as(_dp) if want_x else None, _dptr(p_abs))
+        rid = ctypes.c_longlong(-1)
+        _check(_lib.vie_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
+        self._held[rid.value] = (p_abs, x)
+        return rid.value
+
+    def poll(self, rid):
+        info = RequestInfo()
+        _check(_lib.vie_server_poll(self._h, int(rid), ctypes.byref(info)))
+        d = {k: getattr(info, k) for k, _ in info._fields_}
+        d["message"] = info.message.decode(errors="replace")
+        return d
+
+    def result(self, rid):
+        """(info, absorbed power per dipole, x or None) of a finished request."""
+        info = self.poll(rid)
+        if not info["done"]:
+            raise VieError(VIE_ESTATE, "request %d is not finished" % rid)
+        p_abs, x = self._held[rid]
+        return info, p_abs, x
+
+    def wait(self):
+        _check(_lib.vie_server_wait(self._h))
+
+    def stats(self, first_id=0):
+        st = ServingStats()
+        _check(_lib.vie_server_stats(self._h, int(first_id), ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_}

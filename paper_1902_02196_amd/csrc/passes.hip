@@ -1,6 +1,7 @@
 // FFT-matvec passes (Sec. IV-A): strided zero-padded FFT passes along z and
 // y, the fused x pass with the per-frequency block product, and the epilogue
 // that crops and applies contrast / Gram scaling (Sec. IV-B).
+#include <mutex>
 #include "kernels.hpp"
 #include "passes.hpp"
 #include "fft_ct.hpp"
@@ -507,14 +508,14 @@ static void launch_p3_ct_n(C<R>* A, const C<R>* U, const P3Params& p, const C<R>
     constexpr int GMAX = p3_gmax(sizeof(C<R>), N, NT);
     VIE_REQUIRE(p.groups >= 1 && p.groups <= GMAX && p.Ox == N / 2 + 1, -1, "x pass: bad group count");
     const size_t lds = (size_t)p3_lds_bytes(sizeof(C<R>), N, p.groups);
-    static bool attr = false;
-    if (!attr) {
-        // allow more than the default 64 KiB of dynamic LDS; a refusal shows
-        // up as a launch error below, so clear the status here
+    // allow more than the default 64 KiB of dynamic LDS (once per process;
+    // the size is fixed per instantiation); a refusal shows up as a launch
+    // error below, so clear the status here
+    static std::once_flag once;
+    std::call_once(once, [&] {
         (void)hipFuncSetAttribute((const void*)k_p3_ct<R, N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)hipGetLastError();
-        attr = true;
-    }
+    });
     VIE_REQUIRE(p.sib_blocks == 1 || p.sib_blocks == 2 || p.sib_blocks == 4, -1, "x pass: bad sibling split");
     hipLaunchKernelGGL((k_p3_ct<R, N>), dim3(p.Oy * p.Oz * p.sib_blocks), dim3(NT), lds, s, A, U, p, tw);
     VIE_HIP(hipGetLastError());
@@ -553,13 +554,12 @@ static void launch_strided_t(const C<R>* in, C<R>* out, const StridedPass& p, lo
                              const C<R>* tw, const Epilogue<R>& ep, hipStream_t s) {
     dim3 grid((p.n_inner + p.tile - 1) / p.tile, (unsigned)n_o2, (unsigned)n_o1);
     size_t lds = 2 * (size_t)p.plan.n * p.pitch * sizeof(C<R>);
-    static bool attr = false;
-    if (!attr) {
+    static std::once_flag once;
+    std::call_once(once, [] {
         (void)hipFuncSetAttribute((const void*)k_strided<R, FWD, EPI>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   96 * 1024);
         (void)hipGetLastError();
-        attr = true;
-    }
+    });
     hipLaunchKernelGGL((k_strided<R, FWD, EPI>), grid, dim3(256), lds, s, in, out, p, tw, ep);
     VIE_HIP(hipGetLastError());
 }
@@ -595,13 +595,12 @@ void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStr
                 "x pass: more butterflies or columns than threads");
     size_t lds = (60 * (size_t)p.Ox + lds_pad(p.groups * 12 * p.pitch) + 2) * sizeof(C<R>);
     const bool split4 = 4 * p.groups * p.plan.n <= nt;
-    static bool attr = false;
-    if (!attr) {
+    static std::once_flag once;
+    std::call_once(once, [] {
         (void)hipFuncSetAttribute((const void*)k_p3<R, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
         (void)hipFuncSetAttribute((const void*)k_p3<R, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
         (void)hipGetLastError();
-        attr = true;
-    }
+    });
     if (split4) hipLaunchKernelGGL((k_p3<R, 4>), dim3(p.Oy * p.Oz), dim3(nt), lds, s, A, U, p, tw);
     else hipLaunchKernelGGL((k_p3<R, 2>), dim3(p.Oy * p.Oz), dim3(nt), lds, s, A, U, p, tw);
     VIE_HIP(hipGetLastError());
