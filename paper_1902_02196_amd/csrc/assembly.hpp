@@ -40,4 +40,36 @@ struct AssemblyTables {
     int order_duffy;    // order of each Duffy factor
 };
 
+// Separable far-field assembly.  Away from the singular corner (max |d_i| >= 2)
+// every geometry of every entry is integrated with the same Gauss order n on
+// each axis, so all 60 entries sample the Green's function on one common
+// tensor grid per offset: per axis, n points on [-D, 0], n on [0, D] and the
+// three point-mass abscissae -D, 0, D (P = 2 n + 3 in all).  An entry term is
+// then sum_{ijk} Wx[kx][i] Wy[ky][j] Wz[kz][k] g(d Delta + w_ijk), the W the
+// axis-kernel weights at the grid points (zero where the kernel has no
+// support); points with two or more point-mass axes carry no weight and are
+// left out.  The sum is contracted one axis at a time.
+constexpr int kFarBands = 5;
+constexpr int kFarPMax = 31;       // 2 * 14 + 3
+constexpr int kFarTerms = 120;     // (entry, term) pairs, at most 2 terms per entry
+
+struct FarBand {
+    int n, P;                      // Gauss order, grid points per axis
+    int dlo, dhi;                  // offsets with dlo <= max |d_i| <= dhi
+    double w[3][kFarPMax];         // abscissae per axis
+    double W[3][16][kFarPMax];     // weight of axis kernel pair (kt, kb) at each abscissa
+    int ispt[kFarPMax];            // 1 for the point-mass abscissae
+};
+
+struct FarTables {
+    FarBand band[kFarBands];
+    int nterm;                     // flattened (entry, term) list
+    int term_kx[kFarTerms];        // axis-kernel pair along x
+    int term_pair[kFarTerms];      // index into the (ky, kz) pair list
+    double term_coef[kFarTerms];
+    int ent_first[60], ent_count[60];
+    int npair;
+    int pair_ky[kFarTerms], pair_kz[kFarTerms];
+};
+
 }  // namespace vie

@@ -1,6 +1,7 @@
 // Operator set-up (Sec. III-C, IV-A): assembly of the 60 unique
 // Toeplitz-defining block tensors on the device, circulant embedding with the
 // reflection signs of the PWL bases, forward FFT, octant extraction.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -301,6 +302,204 @@ __host__ __device__ __forceinline__ int far_order(int dinf, int near) {
     return 4;
 }
 
+// Gauss order bands of far_order for offsets beyond the singular corner
+static const int kBandLo[kFarBands] = {2, 3, 5, 9, 17};
+static const int kBandHi[kFarBands] = {2, 4, 8, 16, 1 << 30};
+
+FarTables build_far_tables(const AssemblyTables& T) {
+    FarTables F{};
+    for (int b = 0; b < kFarBands; ++b) {
+        FarBand& B = F.band[b];
+        B.dlo = kBandLo[b];
+        B.dhi = kBandHi[b];
+        B.n = far_order(B.dlo, T.order_near);
+        B.P = 2 * B.n + 3;
+        const double* gx = T.gl_x[B.n];
+        const double* gw = T.gl_w[B.n];
+        for (int i = 0; i < B.P; ++i) B.ispt[i] = i >= 2 * B.n;
+        for (int ax = 0; ax < 3; ++ax) {
+            const double D = T.D[ax];
+            for (int a = 0; a < B.n; ++a) {
+                B.w[ax][a] = -D + D * gx[a];
+                B.w[ax][B.n + a] = D * gx[a];
+            }
+            for (int m = 0; m < 3; ++m) B.w[ax][2 * B.n + m] = (m - 1) * D;
+            for (int k = 0; k < 16; ++k) {
+                const AxisKernel& K = T.ker[ax * 16 + k];
+                for (int a = 0; a < B.n; ++a) {
+                    B.W[ax][k][a] = horner(K.left, B.w[ax][a]) * gw[a] * D;
+                    B.W[ax][k][B.n + a] = horner(K.right, B.w[ax][B.n + a]) * gw[a] * D;
+                }
+                for (int m = 0; m < 3; ++m) B.W[ax][k][2 * B.n + m] = K.pts[m];
+            }
+        }
+    }
+    F.nterm = 0;
+    F.npair = 0;
+    for (int e = 0; e < 60; ++e) {
+        const EntryTerms& E = T.ent[e];
+        F.ent_first[e] = F.nterm;
+        F.ent_count[e] = E.nterm;
+        for (int t = 0; t < E.nterm; ++t) {
+            const int ky = E.ker[t][1] % 16, kz = E.ker[t][2] % 16;
+            int p = 0;
+            while (p < F.npair && !(F.pair_ky[p] == ky && F.pair_kz[p] == kz)) ++p;
+            if (p == F.npair) {
+                F.pair_ky[p] = ky;
+                F.pair_kz[p] = kz;
+                ++F.npair;
+            }
+            F.term_kx[F.nterm] = E.ker[t][0] % 16;
+            F.term_pair[F.nterm] = p;
+            F.term_coef[F.nterm] = E.coef[t];
+            ++F.nterm;
+        }
+    }
+    return F;
+}
+
+// The separable sum of one offset evaluated serially (host reference of the
+// parallel kernel below; same grid, same contraction order).
+void assemble_far_serial(const FarTables& F, const AssemblyTables& T, int b, const int d[3], double2* out60) {
+    const FarBand& B = F.band[b];
+    const int P = B.P;
+    std::vector<double2> S(F.nterm, make_double2(0, 0)), t1(P * 16), t2(F.npair);
+    std::vector<double2> slab(P * P);
+    for (int i = 0; i < P; ++i) {
+        const double rx = d[0] * T.D[0] + B.w[0][i];
+        for (int j = 0; j < P; ++j)
+            for (int k = 0; k < P; ++k) {
+                const double ry = d[1] * T.D[1] + B.w[1][j], rz = d[2] * T.D[2] + B.w[2][k];
+                slab[j * P + k] = (B.ispt[i] + B.ispt[j] + B.ispt[k] > 1)
+                                      ? make_double2(0, 0)
+                                      : green(sqrt(rx * rx + ry * ry + rz * rz), T.k0);
+            }
+        for (int j = 0; j < P; ++j)
+            for (int kz = 0; kz < 16; ++kz) {
+                double2 a = make_double2(0, 0);
+                for (int k = 0; k < P; ++k) {
+                    a.x += B.W[2][kz][k] * slab[j * P + k].x;
+                    a.y += B.W[2][kz][k] * slab[j * P + k].y;
+                }
+                t1[j * 16 + kz] = a;
+            }
+        for (int p = 0; p < F.npair; ++p) {
+            double2 a = make_double2(0, 0);
+            for (int j = 0; j < P; ++j) {
+                a.x += B.W[1][F.pair_ky[p]][j] * t1[j * 16 + F.pair_kz[p]].x;
+                a.y += B.W[1][F.pair_ky[p]][j] * t1[j * 16 + F.pair_kz[p]].y;
+            }
+            t2[p] = a;
+        }
+        for (int t = 0; t < F.nterm; ++t) {
+            const double wx = B.W[0][F.term_kx[t]][i];
+            S[t].x += wx * t2[F.term_pair[t]].x;
+            S[t].y += wx * t2[F.term_pair[t]].y;
+        }
+    }
+    for (int e = 0; e < 60; ++e) {
+        double2 a = make_double2(0, 0);
+        for (int t = F.ent_first[e]; t < F.ent_first[e] + F.ent_count[e]; ++t) {
+            a.x += F.term_coef[t] * S[t].x;
+            a.y += F.term_coef[t] * S[t].y;
+        }
+        out60[e] = a;
+    }
+}
+
+// One wavefront per offset (grid-stride over the offsets of the cube that
+// holds the band, those below the band skipped).  Per x abscissa: the (y, z) slab of Green's values, the z
+// contraction for all 16 kernel pairs, the y contraction for the (ky, kz)
+// pairs in use, and the x accumulation of every (entry, term) sum.
+template <int P>
+__global__ void __launch_bounds__(64) k_assemble_far(double2* __restrict__ out, const FarTables* __restrict__ Fg,
+                                                     int b, double Dx, double Dy, double Dz, double k0, int Nx,
+                                                     int Ny, int Nz, int cx, int cy, int cz) {
+    __shared__ double2 slab[P * P];
+    __shared__ double2 t1[P * 16];
+    __shared__ double2 t2[kFarTerms];
+    const FarTables& F = *Fg;
+    const FarBand& B = F.band[b];
+    const int tid = threadIdx.x;
+    const long long V = (long long)Nx * Ny * Nz;
+    const int nterm = F.nterm, npair = F.npair;
+    // offsets of the band lie in the cube [0, cx) x [0, cy) x [0, cz)
+    const long long ncube = (long long)cx * cy * cz;
+    for (long long q = blockIdx.x; q < ncube; q += gridDim.x) {
+        const int d0 = int(q % cx), d1 = int((q / cx) % cy), d2 = int(q / ((long long)cx * cy));
+        const long long v = ((long long)d2 * Ny + d1) * Nx + d0;
+        const int dinf = max(d0, max(d1, d2));
+        if (dinf < B.dlo || dinf > B.dhi) continue;   // uniform over the workgroup
+        double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0);   // terms tid, tid + 64
+        for (int i = 0; i < P; ++i) {
+            const double rx = d0 * Dx + B.w[0][i];
+            const int pi = B.ispt[i];
+            for (int idx = tid; idx < P * P; idx += 64) {
+                const int j = idx / P, k = idx - j * P;
+                double2 g = make_double2(0, 0);
+                if (pi + B.ispt[j] + B.ispt[k] <= 1) {
+                    const double ry = d1 * Dy + B.w[1][j], rz = d2 * Dz + B.w[2][k];
+                    g = green(sqrt(rx * rx + ry * ry + rz * rz), k0);
+                }
+                slab[idx] = g;
+            }
+            __syncthreads();
+            for (int idx = tid; idx < P * 16; idx += 64) {
+                const int j = idx >> 4, kz = idx & 15;
+                const double* wz = B.W[2][kz];
+                double2 a = make_double2(0, 0);
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    const double2 g = slab[j * P + k];
+                    a.x += wz[k] * g.x;
+                    a.y += wz[k] * g.y;
+                }
+                t1[idx] = a;
+            }
+            __syncthreads();
+            for (int p = tid; p < npair; p += 64) {
+                const double* wy = B.W[1][F.pair_ky[p]];
+                const int kz = F.pair_kz[p];
+                double2 a = make_double2(0, 0);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    const double2 u = t1[j * 16 + kz];
+                    a.x += wy[j] * u.x;
+                    a.y += wy[j] * u.y;
+                }
+                t2[p] = a;
+            }
+            __syncthreads();
+            if (tid < nterm) {
+                const double wx = B.W[0][F.term_kx[tid]][i];
+                const double2 u = t2[F.term_pair[tid]];
+                s0.x += wx * u.x;
+                s0.y += wx * u.y;
+            }
+            if (tid + 64 < nterm) {
+                const double wx = B.W[0][F.term_kx[tid + 64]][i];
+                const double2 u = t2[F.term_pair[tid + 64]];
+                s1.x += wx * u.x;
+                s1.y += wx * u.y;
+            }
+            __syncthreads();
+        }
+        // combine the terms of each entry (t2 reused for the term sums)
+        if (tid < nterm) t2[tid] = s0;
+        if (tid + 64 < nterm) t2[tid + 64] = s1;
+        __syncthreads();
+        if (tid < 60) {
+            double2 a = make_double2(0, 0);
+            for (int t = F.ent_first[tid]; t < F.ent_first[tid] + F.ent_count[tid]; ++t) {
+                a.x += F.term_coef[t] * t2[t].x;
+                a.y += F.term_coef[t] * t2[t].y;
+            }
+            out[(long long)tid * V + v] = a;
+        }
+        __syncthreads();
+    }
+}
+
 // N^{e}(d) for one unique entry and one offset d >= 0
 __host__ __device__ double2 assemble_entry(const AssemblyTables& T, int e, const int d[3]) {
     const int dinf = max(d[0], max(d[1], d[2]));
@@ -332,14 +531,17 @@ __host__ __device__ double2 assemble_entry(const AssemblyTables& T, int e, const
     return acc;
 }
 
-__global__ void __launch_bounds__(128) k_assemble(double2* __restrict__ out, const AssemblyTables* __restrict__ Tg,
-                                                  int Nx, int Ny, int Nz, int e_begin) {
+// entry-by-entry assembly of the offsets at the singular corner,
+// d in {0, 1}^3 (those may touch the singular point; Duffy rules)
+__global__ void __launch_bounds__(64) k_assemble_near(double2* __restrict__ out, const AssemblyTables* __restrict__ Tg,
+                                                      int Nx, int Ny, int Nz) {
     const long long V = (long long)Nx * Ny * Nz;
-    const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const int e = e_begin + blockIdx.y;
-    if (v >= V) return;
-    const int d[3] = {int(v % Nx), int((v / Nx) % Ny), int(v / ((long long)Nx * Ny))};
-    out[(long long)e * V + v] = assemble_entry(*Tg, e, d);
+    const int e = blockIdx.x;
+    const int c = threadIdx.x;
+    if (c >= 8) return;
+    const int d[3] = {c & 1, (c >> 1) & 1, c >> 2};
+    if (d[0] >= Nx || d[1] >= Ny || d[2] >= Nz) return;
+    out[(long long)e * V + ((long long)d[2] * Ny + d[1]) * Nx + d[0]] = assemble_entry(*Tg, e, d);
 }
 
 // circulant embedding of one unique entry on the M grid ([Mz][My][Mx]):
@@ -387,19 +589,47 @@ __global__ void k_octant(double2* __restrict__ U128, float2* __restrict__ U64, c
 // host entry points
 // ---------------------------------------------------------------------------
 void assemble_blocks(double2* out, const AssemblyTables& T, int Nx, int Ny, int Nz, hipStream_t s) {
+    const FarTables F = build_far_tables(T);
+    VIE_REQUIRE(F.nterm <= kFarTerms && F.npair <= kFarTerms, -1, "assembly: term table overflow");
     AssemblyTables* dT = nullptr;
+    FarTables* dF = nullptr;
     VIE_HIP(hipMalloc(&dT, sizeof(AssemblyTables)));
+    VIE_HIP(hipMalloc(&dF, sizeof(FarTables)));
     VIE_HIP(hipMemcpyAsync(dT, &T, sizeof(AssemblyTables), hipMemcpyHostToDevice, s));
+    VIE_HIP(hipMemcpyAsync(dF, &F, sizeof(FarTables), hipMemcpyHostToDevice, s));
     const long long V = (long long)Nx * Ny * Nz;
-    dim3 block(128);
-    // chunk over entries so that a single launch stays short
-    for (int e0 = 0; e0 < 60; e0 += 6) {
-        dim3 grid((unsigned)((V + block.x - 1) / block.x), 6);
-        hipLaunchKernelGGL(k_assemble, grid, block, 0, s, out, dT, Nx, Ny, Nz, e0);
+    hipLaunchKernelGGL(k_assemble_near, dim3(60), dim3(64), 0, s, out, dT, Nx, Ny, Nz);
+    VIE_HIP(hipGetLastError());
+    const int dmax = std::max(Nx, std::max(Ny, Nz)) - 1;
+    for (int b = 0; b < kFarBands; ++b) {
+        const FarBand& B = F.band[b];
+        if (B.dlo > dmax) break;
+        // offsets in the band: the cube of edge min(dhi, dmax) + 1 minus the one of edge dlo
+        const int hi = std::min(B.dhi, dmax) + 1;
+        const int cx = std::min(hi, Nx), cy = std::min(hi, Ny), cz = std::min(hi, Nz);
+        const long long cnt = (long long)cx * cy * cz -
+                              (long long)std::min(B.dlo, Nx) * std::min(B.dlo, Ny) * std::min(B.dlo, Nz);
+        const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>(cnt, 1 << 16));
+        const double* D = T.D;
+#define FAR_CASE(P_)                                                                                        \
+    case P_:                                                                                                \
+        hipLaunchKernelGGL(k_assemble_far<P_>, dim3(grid), dim3(64), 0, s, out, dF, b, D[0], D[1], D[2], T.k0, \
+                           Nx, Ny, Nz, cx, cy, cz);                                                         \
+        break;
+        switch (B.P) {
+            FAR_CASE(31)
+            FAR_CASE(21)
+            FAR_CASE(17)
+            FAR_CASE(13)
+            FAR_CASE(11)
+            default: throw Error(-1, "assembly: unsupported Gauss order band");
+        }
+#undef FAR_CASE
         VIE_HIP(hipGetLastError());
     }
     VIE_HIP(hipStreamSynchronize(s));
     VIE_HIP(hipFree(dT));
+    VIE_HIP(hipFree(dF));
 }
 
 // reflection sign of unique entry e along an axis (same for its whole orbit)

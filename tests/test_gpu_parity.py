@@ -100,6 +100,22 @@ def test_device_assembly_matches_oracle(vie, torch, N, D):
                 assert np.abs(a - b).max() <= 1e-10 * np.abs(b).max(), (ix, iy, iz)
 
 
+def test_device_assembly_far_offsets(vie, torch):
+    """Sampled offsets in every Gauss-order band of the device assembly (up to
+    max |d_i| = 39) vs the oracle's blocks at the same offsets."""
+    from tests.layout import UNIQUE_AB
+    N, D = (40, 24, 20), (0.005, 0.004, 0.006)
+    c = _ctx(vie, torch, N, D)
+    lib = c.get_toeplitz()
+    offs = [(2, 0, 0), (2, 2, 2), (0, 1, 2), (3, 1, 0), (4, 4, 4), (5, 0, 0), (8, 8, 8), (7, 2, 5), (9, 0, 0),
+            (16, 3, 1), (12, 12, 12), (17, 0, 0), (25, 10, 3), (39, 23, 19), (0, 0, 19), (0, 23, 0), (33, 1, 18)]
+    ref = toeplitz.galerkin_blocks(np.array(offs), D, K)
+    for (ix, iy, iz), blk in zip(offs, ref):
+        b = np.array([blk[a, bb] for a, bb in UNIQUE_AB])
+        a = lib[:, iz, iy, ix]
+        assert np.abs(a - b).max() <= 1e-10 * np.abs(b).max(), (ix, iy, iz)
+
+
 @pytest.mark.parametrize("N,D", CASES[:2])
 def test_preconditioned_and_plain_operators(vie, torch, N, D):
     """P^-1 A (eq. 17) and A (eq. 24a) with a heterogeneous phantom, library
