@@ -85,6 +85,7 @@ _sig = {
     "vie_power_density": (_i, [_vp, _i, _vp, _vp]),
     "vie_copy": (_i, [_vp, _vp, _vp, ctypes.c_longlong]),
     "vie_autotune": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _dp]),
+    "vie_set_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(_i)]),
     "vie_profile": (_i, [_vp, _i]),
     "vie_profile_read": (_i, [_vp, _i, _dp, ctypes.POINTER(_i), _dp]),
     "vie_server_create": (_i, [ctypes.POINTER(_vp), _i, ctypes.c_size_t, _i]),
@@ -283,6 +284,12 @@ class Context:
         ms = ctypes.c_double(0)
         _check(_lib.vie_autotune(self._h, precision, nrhs, ch, ctypes.byref(ms)))
         return {"variant": ch[0], "sib_blocks": ch[1], "tile_z": ch[2], "tile_y": ch[3]}, ms.value
+
+    def set_tuning(self, choice, precision=C64, nrhs=1):
+        """Install launch shapes (a dict as autotune returns) without timing."""
+        ch = (ctypes.c_int * 4)(int(choice["variant"]), int(choice["sib_blocks"]), int(choice["tile_z"]),
+                                int(choice["tile_y"]))
+        _check(_lib.vie_set_tuning(self._h, precision, nrhs, ch))
 
     def profile(self, enable=True):
         _check(_lib.vie_profile(self._h, 1 if enable else 0))

@@ -433,6 +433,34 @@ int vie_autotune(vie_ctx* ctx, int precision, int nrhs, int* choice, double* bes
     });
 }
 
+int vie_set_tuning(vie_ctx* ctx, int precision, int nrhs, const int* choice) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        VIE_REQUIRE(c.has_grid, VIE_ESTATE, "tuning needs a grid");
+        VIE_REQUIRE(precision == VIE_C64 || precision == VIE_C128, VIE_EINVAL, "bad precision");
+        VIE_REQUIRE(nrhs >= 1 && choice, VIE_EINVAL, "bad arguments");
+        const int es = precision == VIE_C64 ? 8 : 16;
+        Tune t;
+        t.p3_variant = choice[0];
+        t.p3_sib_blocks = choice[1];
+        t.tile_z = choice[2];
+        t.tile_y = choice[3];
+        VIE_REQUIRE(t.p3_variant >= 0 && t.p3_variant <= 4, VIE_EINVAL, "unknown x-pass variant");
+        VIE_REQUIRE(t.p3_variant != 3 || p3_pref_fits(c.M[0]), VIE_EINVAL,
+                    "x-pass variant 3 needs an fft length <= 128 along x");
+        VIE_REQUIRE(t.p3_variant == 0 || p3_ct_supported(c.M[0]), VIE_EINVAL,
+                    "x-pass variants 1 to 4 need a compiled fft length along x");
+        VIE_REQUIRE(t.p3_variant != 2 || p3_quad_fits(es, c.M[0]), VIE_EINVAL,
+                    "x-pass variant 2 is complex64 only and needs its rows to fit LDS");
+        VIE_REQUIRE(t.p3_sib_blocks == 1 || (t.p3_variant == 0 && (t.p3_sib_blocks == 2 || t.p3_sib_blocks == 4)),
+                    VIE_EINVAL, "workgroups per row must be 1 (or 2, 4 for variant 0)");
+        VIE_REQUIRE(strided_tile_ok(es, c.M[2], t.tile_z) && strided_tile_ok(es, c.M[1], t.tile_y), VIE_EINVAL,
+                    "tile not available for this fft size (8 or 16, or 32 with a compiled length)");
+        c.tune[{precision == VIE_C64 ? 0 : 1, nrhs}] = t;
+    });
+}
+
 int vie_profile(vie_ctx* ctx, int enable) {
     return guarded([&] {
         check_ctx(ctx);

@@ -48,9 +48,15 @@ template <bool FWD, typename T> __host__ __device__ __forceinline__ T mul_mi(T a
     return r;
 }
 // acc += a * b
+__host__ __device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
+
+// acc += a * b as four fused multiply-adds
 template <typename T> __host__ __device__ __forceinline__ void cfma(T& acc, T a, T b) {
-    acc.x += a.x * b.x - a.y * b.y;
-    acc.y += a.x * b.y + a.y * b.x;
+    acc.x = fma_(a.x, b.x, acc.x);
+    acc.x = fma_(-a.y, b.y, acc.x);
+    acc.y = fma_(a.x, b.y, acc.y);
+    acc.y = fma_(a.y, b.x, acc.y);
 }
 
 // ---------------------------------------------------------------------------

@@ -14,6 +14,10 @@ template <typename R>
 void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s);
 bool p3_ct_supported(int n);
 int p3_ct_groups(int es, int n);
+bool p3_quad_fits(int es, int n);
+bool p3_pref_fits(int n);
+bool strided_ct_fits(int es, int n, int tile);
+bool strided_tile_ok(int es, int n, int tile);
 template <typename R>
 void launch_rows(bool fwd, C<R>* data, long long nrows, const FftPlan& plan, const C<R>* tw, hipStream_t s);
 

@@ -56,6 +56,65 @@ __global__ void __launch_bounds__(256) k_strided(const C<R>* in, C<R>* out,
     }
 }
 
+// Compile-time-length strided pass: the tile's T pencils are held as T rows
+// of N in LDS (one buffer, padded) and transformed in place by the unrolled
+// Stockham passes; loads and stores run along t, T consecutive elements.
+template <typename R, bool FWD, bool EPI, int N, int T>
+__global__ void __launch_bounds__(256) k_strided_ct(const C<R>* in, C<R>* out, StridedPass p,
+                                                    const C<R>* __restrict__ tw, Epilogue<R> ep) {
+    constexpr int NT = 256;
+    extern __shared__ unsigned char smem_raw[];
+    C<R>* twl = reinterpret_cast<C<R>*>(smem_raw);
+    C<R>* buf = twl + N;
+    const int tid = threadIdx.x;
+    const int t0 = blockIdx.x * T;
+    const long long o2 = blockIdx.y;
+    const int o1 = blockIdx.z, rr = o1 / 12, cc = o1 - 12 * rr;
+    const int tw_n = min(T, p.n_inner - t0);
+    const C<R>* src = in + rr * p.in_s1 + cc * p.in_sc + o2 * p.in_s2 + t0;
+    for (int m = tid; m < N; m += NT) twl[m] = tw[m];
+    constexpr int LN = N * T;
+    constexpr int LPT = (LN + NT - 1) / NT;
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+        const int idx = tid + i * NT;
+        if (LN % NT == 0 || idx < LN) {
+            const int k = idx / T, t = idx - k * T;
+            C<R> v = mk<R>(0, 0);
+            if (k < p.n_in && t < tw_n) v = src[k * p.in_sk + t];
+            buf[lds_pad(t * N + k)] = v;
+        }
+    }
+    __syncthreads();
+    ct_passes<R, FWD, N, 0, 1, NT, T>(buf, twl, T, N, tid);
+    const long long obase = rr * p.out_s1 + cc * p.out_sc;
+    C<R>* dst = out + obase + o2 * p.out_s2 + t0;
+    const int l = cc & 3;
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+        const int idx = tid + i * NT;
+        if (LN % NT == 0 || idx < LN) {
+            const int k = idx / T, t = idx - k * T;
+            if (k < p.n_out && t < tw_n) {
+                C<R> w = buf[lds_pad(t * N + k)];
+                if (EPI) {
+                    const long long v = o2 * p.out_s2 + k * p.out_sk + t0 + t;   // voxel
+                    const long long e = obase + v;                                  // element
+                    C<R> bv = ep.b ? ep.b[v] : mk<R>(ep.b_const, 0);
+                    C<R> y = cscale(cmul(bv, w), ep.gb[l]);
+                    if (ep.a || ep.a_const != R(0)) {
+                        C<R> av = ep.a ? ep.a[v] : mk<R>(ep.a_const, 0);
+                        y = cadd(y, cscale(cmul(av, ep.x[e]), ep.ga[l]));
+                    }
+                    if (ep.rhs) y = cadd(y, ep.rhs[e]);
+                    w = y;
+                }
+                dst[k * p.out_sk + t] = w;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // fused x pass
 // ---------------------------------------------------------------------------
@@ -368,15 +427,15 @@ __device__ __forceinline__ void orbit_apply(C<R>* yv, const C<R>* xv, C<R> u) {
     }
 }
 
-template <typename R, int E>
+template <typename R, int E, int EEND = 60>
 __device__ __forceinline__ void orbit_product(C<R>* yv, const C<R>* xv, const C<R>* __restrict__ Ur, int ox, int OXs) {
-    if constexpr (E < 60) {
+    if constexpr (E < EEND) {
         orbit_apply<R, E, 0>(yv, xv, Ur[E * OXs + ox]);
-        orbit_product<R, E + 1>(yv, xv, Ur, ox, OXs);
+        orbit_product<R, E + 1, EEND>(yv, xv, Ur, ox, OXs);
     }
 }
 
-template <typename R, int N>
+template <typename R, int N, int SPLIT>
 __global__ void __launch_bounds__(kP3SmallThreads) k_p3_small(C<R>* __restrict__ A, const C<R>* __restrict__ U,
                                                               P3Params p, const C<R>* __restrict__ tw) {
     constexpr int NT = kP3SmallThreads;
@@ -431,8 +490,8 @@ __global__ void __launch_bounds__(kP3SmallThreads) k_p3_small(C<R>* __restrict__
     }
     __syncthreads();
     ct_passes<R, true, N, 0, 1, NT, 12>(buf, twl, 12, N, tid);
-    {
-        const C<R>* Ur = U + (long long)row * 60 * OX;
+    const C<R>* Ur = U + (long long)row * 60 * OX;
+    if constexpr (SPLIT == 1) {
         for (int xi = tid; xi < N; xi += NT) {
             const int fx = 2 * xi > N;
             const int ox = fx ? N - xi : xi;
@@ -451,6 +510,46 @@ __global__ void __launch_bounds__(kP3SmallThreads) k_p3_small(C<R>* __restrict__
                 C<R> v = yv[a];
                 if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
                 buf[lds_pad(a * N + xi)] = v;   // own column: in place
+            }
+        }
+    } else {
+        // two threads per frequency column, each summing half of the 60
+        // unique entries; the second half's partial sums pass through the
+        // column's LDS slots.  Every thread runs every round (barriers).
+        constexpr int HALF = NT / 2;
+        const int h = tid / HALF;
+        for (int c0 = 0; c0 < N; c0 += HALF) {
+            const int xi = c0 + (tid - h * HALF);
+            const bool act = xi < N;
+            const int fx = 2 * xi > N;
+            const int ox = fx ? N - xi : xi;
+            const unsigned mask = fold_mask(fx, sy, sz);
+            C<R> xv[12], yv[12];
+            if (act) {
+#pragma unroll
+                for (int a = 0; a < 12; ++a) {
+                    C<R> v = buf[lds_pad(a * N + xi)];
+                    if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                    xv[a] = v;
+                    yv[a] = mk<R>(0, 0);
+                }
+                if (h == 0) orbit_product<R, 0, 30>(yv, xv, Ur, ox, OX);
+                else orbit_product<R, 30, 60>(yv, xv, Ur, ox, OX);
+            }
+            __syncthreads();   // the column's inputs are read by both halves
+            if (act && h == 1) {
+#pragma unroll
+                for (int a = 0; a < 12; ++a) buf[lds_pad(a * N + xi)] = yv[a];
+            }
+            __syncthreads();
+            if (act && h == 0) {
+#pragma unroll
+                for (int a = 0; a < 12; ++a) {
+                    const C<R> o = buf[lds_pad(a * N + xi)];
+                    C<R> v = mk<R>(yv[a].x + o.x, yv[a].y + o.y);
+                    if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                    buf[lds_pad(a * N + xi)] = v;
+                }
             }
         }
     }
@@ -477,6 +576,286 @@ __global__ void __launch_bounds__(kP3SmallThreads) k_p3_small(C<R>* __restrict__
     }
 }
 
+// Prefetching variant of the light x pass (fft lengths up to 128): as the
+// light variant, but the workgroup first issues the loads of its operator row
+// (60 Ox values, contiguous) into registers, so that they are in flight
+// during the gather and the forward FFT, then parks the row in LDS; the block
+// product reads the operator from LDS.
+template <typename R, int E>
+__device__ __forceinline__ void orbit_product_lds(C<R>* yv, const C<R>* xv, const C<R>* Ul, int ox, int OXs) {
+    if constexpr (E < 60) {
+        orbit_apply<R, E, 0>(yv, xv, Ul[E * OXs + ox]);
+        orbit_product_lds<R, E + 1>(yv, xv, Ul, ox, OXs);
+    }
+}
+
+template <typename R, int N>
+__global__ void __launch_bounds__(kP3SmallThreads) k_p3_pref(C<R>* __restrict__ A, const C<R>* __restrict__ U,
+                                                             P3Params p, const C<R>* __restrict__ tw) {
+    constexpr int NT = kP3SmallThreads;
+    constexpr int OX = N / 2 + 1;
+    constexpr int UN = 60 * OX;
+    constexpr int UPT = (UN + NT - 1) / NT;   // operator values per thread
+    extern __shared__ unsigned char smem_raw[];
+    C<R>* twl = reinterpret_cast<C<R>*>(smem_raw);
+    C<R>* Ul = twl + N;
+    C<R>* buf = Ul + UN;
+    const int tid = threadIdx.x;
+    const int K = 4 * p.nrhs;
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+    const int row = (q / K) * 8 + xcd;
+    if (row >= p.Oy * p.Oz) return;       // padding rows, uniform over the workgroup
+    const int kk = q - (q / K) * K;
+    const int r = kk >> 2, sib = kk & 3;
+    const int oz = row / p.Oy, oy = row - oz * p.Oy;
+    const int ny_sib = (oy == 0 || 2 * oy == p.My) ? 1 : 2;
+    const int nz_sib = (oz == 0 || 2 * oz == p.Mz) ? 1 : 2;
+    if (sib >= ny_sib * nz_sib) return;   // uniform over the workgroup
+    const int sz = sib / ny_sib, sy = sib - sz * ny_sib;
+    const int z = sz ? p.Mz - oz : oz;
+    const int y = sy ? p.My - oy : oy;
+    C<R>* base = A + (long long)r * p.s_r + (long long)z * p.s_z + (long long)y * p.s_y;
+    const C<R>* Ur = U + (long long)row * UN;
+    C<R> upre[UPT];
+#pragma unroll
+    for (int i = 0; i < UPT; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < UN) upre[i] = Ur[idx];
+    }
+    for (int m = tid; m < N; m += NT) twl[m] = tw[m];
+    const int tot = 12 * p.Nx;
+    for (int b0 = 0; b0 < tot; b0 += 4 * NT) {
+        C<R> v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = b0 + tid + i * NT;
+            if (e < tot) {
+                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
+                v[i] = base[(long long)c * p.s_c + k];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = b0 + tid + i * NT;
+            if (e < tot) {
+                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
+                buf[lds_pad(c * N + k)] = v[i];
+            }
+        }
+    }
+    for (int e = tid; e < 12 * N; e += NT) {
+        const int c = e / N, k = e - c * N;
+        if (k >= p.Nx) buf[lds_pad(e)] = mk<R>(0, 0);
+    }
+    __syncthreads();
+    ct_passes<R, true, N, 0, 1, NT, 12>(buf, twl, 12, N, tid);
+#pragma unroll
+    for (int i = 0; i < UPT; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < UN) Ul[idx] = upre[i];
+    }
+    __syncthreads();
+    for (int xi = tid; xi < N; xi += NT) {
+        const int fx = 2 * xi > N;
+        const int ox = fx ? N - xi : xi;
+        const unsigned mask = fold_mask(fx, sy, sz);
+        C<R> xv[12], yv[12];
+#pragma unroll
+        for (int a = 0; a < 12; ++a) {
+            C<R> v = buf[lds_pad(a * N + xi)];
+            if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+            xv[a] = v;
+            yv[a] = mk<R>(0, 0);
+        }
+        orbit_product_lds<R, 0>(yv, xv, Ul, ox, OX);
+#pragma unroll
+        for (int a = 0; a < 12; ++a) {
+            C<R> v = yv[a];
+            if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+            buf[lds_pad(a * N + xi)] = v;
+        }
+    }
+    __syncthreads();
+    ct_passes<R, false, N, 0, 1, NT, 12>(buf, twl, 12, N, tid);
+    for (int b0 = 0; b0 < tot; b0 += 4 * NT) {
+        C<R> v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = b0 + tid + i * NT;
+            if (e < tot) {
+                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
+                v[i] = buf[lds_pad(c * N + k)];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = b0 + tid + i * NT;
+            if (e < tot) {
+                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
+                base[(long long)c * p.s_c + k] = v[i];
+            }
+        }
+    }
+}
+
+// Sibling-sharing variant of the x pass: one workgroup of 256 threads per
+// (octant row, right-hand side) holding the up to four sibling pencil groups
+// (+-xi_y, +-xi_z) of the row in LDS.  The block product runs one work item
+// per (frequency, z sibling) that serves both y siblings at once: each of the
+// 60 unique operator values is read once and applied to the two vectors, so
+// a row's operator values are read half as often as with one workgroup per
+// sibling, and every thread has a column to work on.
+template <typename R, int E, int K>
+__device__ __forceinline__ void orbit_apply2(C<R>* y0, C<R>* y1, const C<R>* x0, const C<R>* x1, C<R> u) {
+    constexpr Orbits o = make_orbits();
+    if constexpr (K < o.cnt[E]) {
+        constexpr int a = o.m[E][K].a, b = o.m[E][K].b, sg = o.m[E][K].s;
+        const C<R> us = sg > 0 ? u : mk<R>(-u.x, -u.y);
+        cfma(y0[a], us, x0[b]);
+        cfma(y1[a], us, x1[b]);
+        orbit_apply2<R, E, K + 1>(y0, y1, x0, x1, u);
+    }
+}
+
+template <typename R, int E>
+__device__ __forceinline__ void orbit_product2(C<R>* y0, C<R>* y1, const C<R>* x0, const C<R>* x1,
+                                               const C<R>* __restrict__ Ur, int ox, int OXs) {
+    if constexpr (E < 60) {
+        orbit_apply2<R, E, 0>(y0, y1, x0, x1, Ur[E * OXs + ox]);
+        orbit_product2<R, E + 1>(y0, y1, x0, x1, Ur, ox, OXs);
+    }
+}
+
+constexpr int kP3QuadThreads = 256;
+
+template <typename R, int N>
+__global__ void __launch_bounds__(kP3QuadThreads) k_p3_quad(C<R>* __restrict__ A, const C<R>* __restrict__ U,
+                                                            P3Params p, const C<R>* __restrict__ tw) {
+    constexpr int NT = kP3QuadThreads;
+    constexpr int OX = N / 2 + 1;
+    extern __shared__ unsigned char smem_raw[];
+    C<R>* twl = reinterpret_cast<C<R>*>(smem_raw);
+    C<R>* buf = twl + N;
+    const int tid = threadIdx.x;
+    // block -> (octant row, right-hand side); the nrhs workgroups of one row
+    // get indices congruent modulo 8, so they run on one XCD and share its L2
+    const int K = p.nrhs;
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+    const int row = (q / K) * 8 + xcd;
+    if (row >= p.Oy * p.Oz) return;   // padding rows, uniform over the workgroup
+    const int r = q - (q / K) * K;
+    const int oz = row / p.Oy, oy = row - oz * p.Oy;
+    const int ny_sib = (oy == 0 || 2 * oy == p.My) ? 1 : 2;
+    const int nz_sib = (oz == 0 || 2 * oz == p.Mz) ? 1 : 2;
+    const int nrows = 12 * ny_sib * nz_sib;   // LDS row s * 12 + c, sibling s = sz * ny_sib + sy
+    C<R>* base = A + (long long)r * p.s_r;
+    for (int m = tid; m < N; m += NT) twl[m] = tw[m];
+    const int tot = nrows * p.Nx;
+    for (int b0 = 0; b0 < tot; b0 += 4 * NT) {
+        C<R> v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = b0 + tid + i * NT;
+            if (e < tot) {
+                const int rr = fast_div((unsigned)e, p.magic_nx), k = e - rr * p.Nx;
+                const int sb = rr / 12, c = rr - 12 * sb;
+                const int sz = sb >= ny_sib, sy = sb - sz * ny_sib;
+                const int z = sz ? p.Mz - oz : oz, y = sy ? p.My - oy : oy;
+                v[i] = base[(long long)z * p.s_z + (long long)y * p.s_y + (long long)c * p.s_c + k];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = b0 + tid + i * NT;
+            if (e < tot) {
+                const int rr = fast_div((unsigned)e, p.magic_nx), k = e - rr * p.Nx;
+                buf[lds_pad(rr * N + k)] = v[i];
+            }
+        }
+    }
+    for (int e = tid; e < nrows * N; e += NT) {
+        const int rr = e / N, k = e - rr * N;
+        if (k >= p.Nx) buf[lds_pad(e)] = mk<R>(0, 0);
+    }
+    __syncthreads();
+    ct_passes<R, true, N, 0, 1, NT, 48>(buf, twl, nrows, N, tid);
+    {
+        const C<R>* Ur = U + (long long)row * 60 * OX;
+        for (int w = tid; w < nz_sib * N; w += NT) {
+            const int sz = w >= N, xi = w - sz * N;
+            const int fx = 2 * xi > N;
+            const int ox = fx ? N - xi : xi;
+            const int s0 = sz * ny_sib;
+            if (ny_sib == 2) {
+                const unsigned m0 = fold_mask(fx, 0, sz), m1 = fold_mask(fx, 1, sz);
+                C<R> x0[12], x1[12], y0[12], y1[12];
+#pragma unroll
+                for (int a = 0; a < 12; ++a) {
+                    C<R> v = buf[lds_pad((s0 * 12 + a) * N + xi)];
+                    if (m0 & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                    x0[a] = v;
+                    v = buf[lds_pad(((s0 + 1) * 12 + a) * N + xi)];
+                    if (m1 & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                    x1[a] = v;
+                    y0[a] = mk<R>(0, 0);
+                    y1[a] = mk<R>(0, 0);
+                }
+                orbit_product2<R, 0>(y0, y1, x0, x1, Ur, ox, OX);
+#pragma unroll
+                for (int a = 0; a < 12; ++a) {
+                    C<R> v = y0[a];
+                    if (m0 & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                    buf[lds_pad((s0 * 12 + a) * N + xi)] = v;
+                    v = y1[a];
+                    if (m1 & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                    buf[lds_pad(((s0 + 1) * 12 + a) * N + xi)] = v;
+                }
+            } else {
+                const unsigned m0 = fold_mask(fx, 0, sz);
+                C<R> x0[12], y0[12];
+#pragma unroll
+                for (int a = 0; a < 12; ++a) {
+                    C<R> v = buf[lds_pad((s0 * 12 + a) * N + xi)];
+                    if (m0 & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                    x0[a] = v;
+                    y0[a] = mk<R>(0, 0);
+                }
+                orbit_product<R, 0>(y0, x0, Ur, ox, OX);
+#pragma unroll
+                for (int a = 0; a < 12; ++a) {
+                    C<R> v = y0[a];
+                    if (m0 & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                    buf[lds_pad((s0 * 12 + a) * N + xi)] = v;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    ct_passes<R, false, N, 0, 1, NT, 48>(buf, twl, nrows, N, tid);
+    for (int b0 = 0; b0 < tot; b0 += 4 * NT) {
+        C<R> v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = b0 + tid + i * NT;
+            if (e < tot) {
+                const int rr = fast_div((unsigned)e, p.magic_nx), k = e - rr * p.Nx;
+                v[i] = buf[lds_pad(rr * N + k)];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = b0 + tid + i * NT;
+            if (e < tot) {
+                const int rr = fast_div((unsigned)e, p.magic_nx), k = e - rr * p.Nx;
+                const int sb = rr / 12, c = rr - 12 * sb;
+                const int sz = sb >= ny_sib, sy = sb - sz * ny_sib;
+                const int z = sz ? p.Mz - oz : oz, y = sy ? p.My - oy : oy;
+                base[(long long)z * p.s_z + (long long)y * p.s_y + (long long)c * p.s_c + k] = v[i];
+            }
+        }
+    }
+}
+
 // lengths with a compile-time kernel
 #define VIE_P3_LENGTHS(X) X(8) X(16) X(32) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
 
@@ -492,14 +871,64 @@ bool p3_ct_supported(int n) {
 
 int p3_ct_groups(int es, int n) { return p3_gmax(es, n, 512); }
 
-template <typename R, int N>
+template <typename R, int N, int SPLIT>
 static void launch_p3_small_n(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
     const size_t lds = ((size_t)N + lds_pad(12 * N) + 2) * sizeof(C<R>);
     const long long rows8 = ((long long)p.Oy * p.Oz + 7) / 8 * 8;
     const long long nblk = rows8 * 4LL * p.nrhs;
     VIE_REQUIRE(nblk < (1LL << 31), -1, "x pass: too many workgroups");
-    hipLaunchKernelGGL((k_p3_small<R, N>), dim3((unsigned)nblk), dim3(kP3SmallThreads), lds, s, A, U, p, tw);
+    hipLaunchKernelGGL((k_p3_small<R, N, SPLIT>), dim3((unsigned)nblk), dim3(kP3SmallThreads), lds, s, A, U, p, tw);
     VIE_HIP(hipGetLastError());
+}
+
+template <typename R, int N>
+static void launch_p3_quad_n(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
+    const size_t lds = ((size_t)N + lds_pad(48 * N) + 2) * sizeof(C<R>);
+    const long long rows8 = ((long long)p.Oy * p.Oz + 7) / 8 * 8;
+    const long long nblk = rows8 * p.nrhs;
+    VIE_REQUIRE(nblk < (1LL << 31), -1, "x pass: too many workgroups");
+    VIE_REQUIRE(lds <= 160 * 1024, -1, "x pass: sibling variant does not fit LDS");
+    static std::once_flag once;
+    std::call_once(once, [&] {
+        (void)hipFuncSetAttribute((const void*)k_p3_quad<R, N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    });
+    hipLaunchKernelGGL((k_p3_quad<R, N>), dim3((unsigned)nblk), dim3(kP3QuadThreads), lds, s, A, U, p, tw);
+    VIE_HIP(hipGetLastError());
+}
+
+template <typename R, int N>
+static void launch_p3_pref(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
+    if constexpr (N <= 128) {
+        const size_t lds = ((size_t)N + 60 * (N / 2 + 1) + lds_pad(12 * N) + 2) * sizeof(C<R>);
+        const long long rows8 = ((long long)p.Oy * p.Oz + 7) / 8 * 8;
+        const long long nblk = rows8 * 4LL * p.nrhs;
+        VIE_REQUIRE(nblk < (1LL << 31), -1, "x pass: too many workgroups");
+        static std::once_flag once;
+        std::call_once(once, [&] {
+            (void)hipFuncSetAttribute((const void*)k_p3_pref<R, N>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds);
+            (void)hipGetLastError();
+        });
+        hipLaunchKernelGGL((k_p3_pref<R, N>), dim3((unsigned)nblk), dim3(kP3SmallThreads), lds, s, A, U, p, tw);
+        VIE_HIP(hipGetLastError());
+    } else {
+        throw Error(-1, "x pass: prefetching variant needs an fft length <= 128");
+    }
+}
+
+bool p3_pref_fits(int n) { return p3_ct_supported(n) && n <= 128; }
+
+// the sibling variant is built for complex64 only (its two-vector product
+// would not fit the registers in complex128)
+template <typename R, int N>
+static void launch_p3_quad(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
+    if constexpr (sizeof(R) == 4) launch_p3_quad_n<R, N>(A, U, p, tw, s);
+    else throw Error(-1, "x pass: sibling variant is complex64 only");
+}
+
+bool p3_quad_fits(int es, int n) {
+    return es == 8 && p3_ct_supported(n) && ((size_t)n + lds_pad(48 * n) + 2) * es <= 160 * 1024;
 }
 
 template <typename R, int N>
@@ -564,10 +993,75 @@ static void launch_strided_t(const C<R>* in, C<R>* out, const StridedPass& p, lo
     VIE_HIP(hipGetLastError());
 }
 
+template <typename R, bool FWD, bool EPI, int N, int T>
+static void launch_strided_ct_nt(const C<R>* in, C<R>* out, const StridedPass& p, long long n_o2, long long n_o1,
+                                 const C<R>* tw, const Epilogue<R>& ep, hipStream_t s) {
+    const size_t lds = ((size_t)N + lds_pad(N * T) + 2) * sizeof(C<R>);
+    static std::once_flag once;
+    std::call_once(once, [&] {
+        (void)hipFuncSetAttribute((const void*)k_strided_ct<R, FWD, EPI, N, T>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    });
+    dim3 grid((p.n_inner + T - 1) / T, (unsigned)n_o2, (unsigned)n_o1);
+    hipLaunchKernelGGL((k_strided_ct<R, FWD, EPI, N, T>), grid, dim3(256), lds, s, in, out, p, tw, ep);
+    VIE_HIP(hipGetLastError());
+}
+
+template <typename R, bool FWD, bool EPI, int N>
+static void launch_strided_ct_n(const C<R>* in, C<R>* out, const StridedPass& p, long long n_o2, long long n_o1,
+                                const C<R>* tw, const Epilogue<R>& ep, hipStream_t s) {
+    if (p.tile == 16) launch_strided_ct_nt<R, FWD, EPI, N, 16>(in, out, p, n_o2, n_o1, tw, ep, s);
+    else launch_strided_ct_nt<R, FWD, EPI, N, 32>(in, out, p, n_o2, n_o1, tw, ep, s);
+}
+
+// compiled strided lengths (tiles of 16 or 32 pencils)
+#define VIE_STRIDED_LENGTHS(X) X(8) X(16) X(32) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
+
+bool strided_ct_fits(int es, int n, int tile) {
+    if (tile != 16 && tile != 32) return false;
+    switch (n) {
+#define CASE(n_) case n_:
+        VIE_STRIDED_LENGTHS(CASE)
+#undef CASE
+        return ((size_t)n + lds_pad(n * tile) + 2) * es <= 160 * 1024;
+        default: return false;
+    }
+}
+
+// a tile the strided pass can run: 16 or 32 pencils with a compiled length,
+// or 4, 8, 16 pencils in the generic kernel (two buffers within 96 KiB)
+bool strided_tile_ok(int es, int n, int tile) {
+    if (strided_ct_fits(es, n, tile)) return true;
+    return (tile == 4 || tile == 8 || tile == 16) && 2LL * tile * n * es <= 96 * 1024;
+}
+
+template <typename R, bool FWD, bool EPI>
+static bool launch_strided_ct(const C<R>* in, C<R>* out, const StridedPass& p, long long n_o2, long long n_o1,
+                              const C<R>* tw, const Epilogue<R>& ep, hipStream_t s) {
+    if (!strided_ct_fits((int)sizeof(C<R>), p.plan.n, p.tile)) return false;
+    switch (p.plan.n) {
+#define CASE(n_)                                                                   \
+    case n_:                                                                      \
+        launch_strided_ct_n<R, FWD, EPI, n_>(in, out, p, n_o2, n_o1, tw, ep, s); \
+        return true;
+        VIE_STRIDED_LENGTHS(CASE)
+#undef CASE
+        default: return false;
+    }
+}
+
 template <typename R>
 void launch_strided(bool fwd, const C<R>* in, C<R>* out, const StridedPass& p, long long n_o2, long long n_o1,
                     const C<R>* tw, const Epilogue<R>* ep, hipStream_t s) {
     Epilogue<R> none{};
+    if (ep && !fwd) {
+        if (launch_strided_ct<R, false, true>(in, out, p, n_o2, n_o1, tw, *ep, s)) return;
+    } else if (!ep && fwd) {
+        if (launch_strided_ct<R, true, false>(in, out, p, n_o2, n_o1, tw, none, s)) return;
+    } else if (!ep) {
+        if (launch_strided_ct<R, false, false>(in, out, p, n_o2, n_o1, tw, none, s)) return;
+    }
     if (ep) {
         if (fwd) throw Error(-1, "epilogue only on the inverse pass");
         launch_strided_t<R, false, true>(in, out, p, n_o2, n_o1, tw, *ep, s);
@@ -583,7 +1077,10 @@ void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStr
     switch (p.plan.n) {
 #define CASE(n_)                                                                          \
     case n_:                                                                             \
-        if (p.variant == 1) launch_p3_small_n<R, n_>(A, U, p, tw, s);                    \
+        if (p.variant == 1) launch_p3_small_n<R, n_, 1>(A, U, p, tw, s);                 \
+        else if (p.variant == 4) launch_p3_small_n<R, n_, 2>(A, U, p, tw, s);            \
+        else if (p.variant == 2) launch_p3_quad<R, n_>(A, U, p, tw, s);                  \
+        else if (p.variant == 3) launch_p3_pref<R, n_>(A, U, p, tw, s);                  \
         else launch_p3_ct_n<R, n_>(A, U, p, tw, s);                                      \
         return;
         VIE_P3_LENGTHS(CASE)

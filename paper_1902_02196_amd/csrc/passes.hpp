@@ -52,7 +52,8 @@ struct P3Params {
     unsigned magic_nx;         // fast division by Nx
     unsigned magic_ox;         // fast division by Ox
     int sib_blocks;            // workgroups sharing one octant row (1, 2, 4)
-    int variant;               // 0: staged operator row, 1: one pencil group per workgroup
+    int variant;               // 0: staged operator row, 1: one pencil group per workgroup,
+                               // 2: the sibling pencil groups of a row per workgroup (complex64)
 };
 
 // workgroup size of the x pass: complex64 1024 threads (128 VGPRs each),

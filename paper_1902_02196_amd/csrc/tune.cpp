@@ -1,8 +1,8 @@
 // Autotuner for the launch shapes of the operator product: times each
 // candidate with HIP events on the context stream and keeps the fastest per
 // (precision, nrhs).  The candidates only change the work distribution; the
-// two x-pass variants add the terms of the block product in different
-// orders, so their results agree to rounding.
+// staged x-pass variant adds the terms of the block product in another order
+// than the other two, so results agree to rounding.
 #include <vector>
 
 #include "ctx.hpp"
@@ -36,18 +36,19 @@ static Tune tune_t(Ctx& c, int nrhs, double* best_ms) {
     VIE_HIP(hipMemsetAsync(x, 0, n * sizeof(C<R>), c.stream));
     const int key0 = sizeof(R) == 4 ? 0 : 1;
     std::vector<Tune> cands;
-    for (int var = 0; var <= 1; ++var)
+    for (int var = 0; var <= 4; ++var)
         for (int sb : {1, 2, 4}) {
-            if (var == 1 && sb != 1) continue;
-            for (int tz : {8, 16})
-                for (int ty : {8, 16}) {
+            if (var >= 1 && sb != 1) continue;
+            if (var == 2 && !p3_quad_fits((int)sizeof(C<R>), c.M[0])) continue;
+            if (var == 3 && !p3_pref_fits(c.M[0])) continue;
+            for (int tz : {8, 16, 32})
+                for (int ty : {8, 16, 32}) {
                     Tune t;
                     t.p3_variant = var;
                     t.p3_sib_blocks = sb;
                     t.tile_z = tz;
                     t.tile_y = ty;
-                    // keep the two-buffer tile within 96 KiB of LDS
-                    if (2LL * tz * c.M[2] * sizeof(C<R>) > 96 * 1024 || 2LL * ty * c.M[1] * sizeof(C<R>) > 96 * 1024)
+                    if (!strided_tile_ok((int)sizeof(C<R>), c.M[2], tz) || !strided_tile_ok((int)sizeof(C<R>), c.M[1], ty))
                         continue;
                     cands.push_back(t);
                 }

@@ -262,3 +262,36 @@ def test_autotuned_shapes_keep_results(vie, torch):
         y1 = torch.empty_like(xd)
         c.apply(xd, y1, op=vie.OP_PREC)
         assert float((y1 - y0).abs().max() / y0.abs().max()) < tol
+
+
+@pytest.mark.parametrize("N", [(16, 12, 10), (24, 20, 12), (5, 3, 6)])
+def test_every_launch_shape_matches_oracle(vie, torch, N):
+    """Each x-pass variant and strided-pass tile, installed explicitly, gives
+    the oracle's FFT product (complex64; complex128 where the variant exists)."""
+    D = (0.005, 0.004, 0.006)
+    c = _ctx(vie, torch, N, D)
+    T = toeplitz.toeplitz_full(N, D, K)
+    c.set_toeplitz(unique_from_full(T))
+    xs = [vi.complex_normal(40 + r, (12,) + N) for r in range(3)]
+    Ch = matvec.circulant_spectrum(T, tuple(2 * n for n in N))
+    ref = [matvec.fft_N(Ch, x) for x in xs]
+    x = torch.from_numpy(np.stack([vec_to_lib(v) for v in xs]))
+    shapes = [dict(variant=v, sib_blocks=sb, tile_z=tz, tile_y=ty) for v, sb in ((0, 1), (0, 2), (0, 4), (1, 1), (2, 1), (3, 1), (4, 1))
+              for tz in (8, 16, 32) for ty in (8, 16, 32)]
+    ran = 0
+    for dtype, prec, tol in ((torch.complex64, vie.C64, 1e-5), (torch.complex128, vie.C128, 1e-11)):
+        xd = x.to("cuda", dtype)
+        for sh in shapes:
+            try:
+                c.set_tuning(sh, prec, 3)
+            except vie.VieError:
+                continue   # shape not available for this grid or precision
+            y = torch.empty_like(xd)
+            c.apply(xd, y, op=vie.OP_N)
+            for r in range(3):
+                err = relerr(_from_dev(y[r:r + 1]), ref[r])
+                assert err < tol, (dtype, sh, r, err)
+            ran += 1
+    _say("  %d shapes checked" % ran)
+    assert ran >= 8
+
