@@ -231,8 +231,10 @@ enum {
     VIE_K_COUNT = 7
 };
 
-/* enable = 1 clears the records and starts timing every launch of the
- * classes above with HIP events on the context stream; enable = 0 stops. */
+/* enable = k > 0 clears the records and starts timing launches of the
+ * classes above with HIP events on the context stream, one launch in k of
+ * each class (k = 1: every launch; a larger k keeps the event overhead out of
+ * the timed work); enable = 0 stops. */
 int vie_profile(vie_ctx* ctx, int enable);
 
 /* Sum over the recorded launches of one class: device time (ms, from HIP

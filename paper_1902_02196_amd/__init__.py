@@ -291,8 +291,9 @@ class Context:
                                 int(choice["tile_y"]))
         _check(_lib.vie_set_tuning(self._h, precision, nrhs, ch))
 
-    def profile(self, enable=True):
-        _check(_lib.vie_profile(self._h, 1 if enable else 0))
+    def profile(self, enable=True, every=1):
+        """Time launches by class with HIP events (one launch in `every`)."""
+        _check(_lib.vie_profile(self._h, int(every) if enable else 0))
 
     def profile_read(self):
         """{kernel class: (total ms, launches, algorithmic bytes)}"""

@@ -39,6 +39,9 @@ Ctx::~Ctx() {
     small.release();
     basis.release();
     vecs.release();
+    hpin.release();
+    for (auto& e : col_ev)
+        if (e) (void)hipEventDestroy(e);
     if (flag) (void)hipFree(flag);
 }
 
@@ -466,9 +469,12 @@ int vie_profile(vie_ctx* ctx, int enable) {
         check_ctx(ctx);
         Ctx& c = ctx->c;
         set_device(c);
+        VIE_REQUIRE(enable >= 0, VIE_EINVAL, "enable must be >= 0");
         VIE_HIP(hipStreamSynchronize(c.stream));
         if (enable) c.prof.clear();
         c.prof.on = enable != 0;
+        c.prof.every = enable > 0 ? enable : 1;
+        for (auto& t : c.prof.tick) t = 0;
     });
 }
 
@@ -517,7 +523,7 @@ int vie_footprint_bytes(int nx, int ny, int nz, int nrhs, int mode, int restart,
         const size_t fft = 6 * n * nrhs * s;
         const size_t fft128 = 6 * n * nrhs * 16;   // refinement residual in complex128
         b += (mode == VIE_SOLVE_FP32_IR) ? std::max(fft, fft128) : fft;
-        b += (size_t)(restart + 1) * n * nrhs * s;  // Krylov basis
+        b += (size_t)(restart + 1) * (n * nrhs * s + 4352);  // Krylov basis (staggered)
         b += 2 * n * nrhs * 16;                      // residual and right-hand side (complex128)
         *out = b;
     });

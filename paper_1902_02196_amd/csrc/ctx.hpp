@@ -39,10 +39,34 @@ struct Scratch {
     }
 };
 
+// page-locked host buffer that only grows (asynchronous device-to-host copies)
+struct PinnedScratch {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void* get(size_t need) {
+        if (need > bytes) {
+            if (p) VIE_HIP(hipHostFree(p));
+            p = nullptr;
+            bytes = 0;
+            VIE_HIP(hipHostMalloc(&p, need, hipHostMallocDefault));
+            bytes = need;
+        }
+        return p;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
 // HIP-event timing of kernel launches, by class
 struct Profiler {
     struct Rec { int kind; hipEvent_t a, b; double bytes; };
     bool on = false;
+    int every = 1;                 // record one launch in `every` per class
+    unsigned long long tick[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    bool sample(int kind) { return (tick[kind & 7]++ % (unsigned long long)every) == 0; }
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     hipEvent_t take() {
@@ -69,7 +93,7 @@ struct ProfScope {
     double bytes;
     hipEvent_t a = nullptr;
     ProfScope(Profiler& p_, hipStream_t s_, int k, double b) : p(p_), s(s_), kind(k), bytes(b) {
-        if (p.on) { a = p.take(); VIE_HIP(hipEventRecord(a, s)); }
+        if (p.on && p.sample(k)) { a = p.take(); VIE_HIP(hipEventRecord(a, s)); }
     }
     ~ProfScope() {
         if (p.on && a) {
@@ -116,6 +140,8 @@ struct Ctx {
 
     // solver scratch
     Scratch basis, vecs;
+    PinnedScratch hpin;           // Hessenberg columns on their way to the host
+    hipEvent_t col_ev[2] = {nullptr, nullptr};
 
     Profiler prof;
     std::map<std::pair<int, int>, Tune> tune;   // (precision, nrhs) -> shapes

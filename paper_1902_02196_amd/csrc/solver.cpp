@@ -50,7 +50,11 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
     const int m = o.restart;
     const bool ir = (sizeof(R) == 4);
     const int nb = blocks_for(n);
-    C<R>* Vb = static_cast<C<R>*>(c.basis.get((size_t)(m + 1) * nrhs * n * sizeof(C<R>)));
+    // consecutive basis vectors are staggered by a little over 4 KiB, so that
+    // the j + 1 streams the Gram-Schmidt kernels read side by side do not
+    // start at equal offsets modulo large powers of two
+    const long long vpad = 4352 / (long long)sizeof(C<R>);
+    C<R>* Vb = static_cast<C<R>*>(c.basis.get((size_t)(m + 1) * (nrhs * n + vpad) * sizeof(C<R>)));
     std::vector<int> conv(nrhs, 0);
     std::vector<double> rnorm;
     std::vector<double> last_rel(nrhs, 1.0);
@@ -79,7 +83,7 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
         }
         if (cycle == o.max_outer) break;
         const int na = (int)active.size();
-        const long long ldv = (long long)na * n;
+        const long long ldv = (long long)na * n + vpad;
         // V_0 = r / ||r|| for the active right-hand sides (compacted)
         std::vector<double> inv(na);
         for (int s = 0; s < na; ++s) inv[s] = 1.0 / rnorm[active[s]];
@@ -103,45 +107,28 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
             const double need = o.tol * bnorm[active[s]] / rnorm[active[s]];
             target[s] = ir ? std::max(o.inner_tol, need) : need;
         }
+        // The Arnoldi steps do not depend on the Givens rotations, so the
+        // host lags the device by one step: it enqueues step j, then waits
+        // for the Hessenberg column of step j - 1 (copied into page-locked
+        // memory behind it on the stream) and updates the rotations and the
+        // residual estimate.  A convergence found at step j - 1 leaves step j
+        // computed but unused.
         int jdone = 0;
-        std::vector<double2> h1((size_t)na * (m + 1)), h2((size_t)na * (m + 1));
-        std::vector<double> nrm(na);
-        for (int j = 0; j < m; ++j) {
-            C<R>* vj = Vb + (long long)j * ldv;
-            C<R>* w = Vb + (long long)(j + 1) * ldv;
-            apply_op<R>(c, OP_PREC, na, vj, w, nullptr);
+        const size_t colsz = (size_t)na * (m + 1);
+        double* pin = static_cast<double*>(c.hpin.get(2 * (2 * colsz * sizeof(double2) + na * sizeof(double))));
+        auto slot_h1 = [&](int sl) { return reinterpret_cast<double2*>(pin) + (size_t)sl * 2 * colsz; };
+        auto slot_h2 = [&](int sl) { return slot_h1(sl) + colsz; };
+        auto slot_nrm = [&](int sl) { return pin + (size_t)2 * 2 * colsz * 2 + (size_t)sl * na; };
+        for (auto& e : c.col_ev)
+            if (!e) VIE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        // Givens update for column j; true when every slot has converged
+        auto process = [&](int j) -> int {
+            const int sl = j & 1;
+            VIE_HIP(hipEventSynchronize(c.col_ev[sl]));
             const int nvec = j + 1;
-            // Gram-Schmidt, per pass: the dot kernel reads the j + 1 basis
-            // vectors and w (w once per group of 16 basis vectors); the
-            // update reads them again and writes w; normalising reads and
-            // writes w once more
-            const double vb = (double)na * n * sizeof(C<R>);
-            const double dot_bytes = vb * (nvec + (nvec + 15) / 16);
-            const double upd_bytes = vb * (nvec + 2);
-            for (int pass = 0; pass < (o.reorth ? 2 : 1); ++pass) {
-                double2* hp = pass ? L.h2 : L.h1;
-                {
-                    ProfScope ps(c.prof, c.stream, VIE_K_GS_DOT, dot_bytes);
-                    launch_multidot<R>(L.partial, Vb, ldv, nvec, w, n, n, n, na, nb, c.stream);
-                    launch_reduce_partials(hp, L.partial, nvec, nb, na, c.stream);
-                }
-                {
-                    ProfScope ps(c.prof, c.stream, VIE_K_GS_UPDATE, upd_bytes + (pass == (o.reorth ? 1 : 0) ? 2 * vb : 0));
-                    launch_update<R>(w, Vb, ldv, nvec, hp, n, n, n, L.npart, na, nb, c.stream);
-                    if (pass == (o.reorth ? 1 : 0)) {
-                        launch_reduce_norm(L.nrm, L.npart, nb, na, c.stream);
-                        launch_scale_into<R>(w, w, L.nrm, n, n, n, na, c.stream);
-                    }
-                }
-            }
-            VIE_HIP(hipMemcpyAsync(h1.data(), L.h1, (size_t)na * nvec * sizeof(double2), hipMemcpyDeviceToHost,
-                                   c.stream));
-            if (o.reorth)
-                VIE_HIP(hipMemcpyAsync(h2.data(), L.h2, (size_t)na * nvec * sizeof(double2), hipMemcpyDeviceToHost,
-                                       c.stream));
-            VIE_HIP(hipMemcpyAsync(nrm.data(), L.nrm, na * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-            VIE_HIP(hipStreamSynchronize(c.stream));
-            jdone = j + 1;
+            const double2* h1 = slot_h1(sl);
+            const double2* h2 = slot_h2(sl);
+            const double* nrm = slot_nrm(sl);
             bool all = true;
             for (int s = 0; s < na; ++s) {
                 cd* Hc = &H[s][(size_t)j * (m + 1)];   // column j, rows 0..j+1
@@ -173,10 +160,62 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
                     if (ir) st[active[s]].matvecs_c64 += 1;
                     else st[active[s]].matvecs_c128 += 1;
                 }
+                if (!std::isfinite(est)) return -1;
                 if (!(est <= target[s]) && nrm[s] > 0.0) all = false;
-                if (!std::isfinite(est)) return VIE_ENAN;
             }
-            if (all) break;
+            return all ? 1 : 0;
+        };
+        int launched = 0, stop = 0;
+        for (int j = 0; j < m && !stop; ++j) {
+            C<R>* vj = Vb + (long long)j * ldv;
+            C<R>* w = Vb + (long long)(j + 1) * ldv;
+            apply_op<R>(c, OP_PREC, na, vj, w, nullptr);
+            const int nvec = j + 1;
+            // Gram-Schmidt, per pass: the dot kernel reads the j + 1 basis
+            // vectors and w (w once per group of 16 basis vectors); the
+            // update reads them again and writes w; normalising reads and
+            // writes w once more
+            const double vb = (double)na * n * sizeof(C<R>);
+            const double dot_bytes = vb * (nvec + (nvec + 15) / 16);
+            const double upd_bytes = vb * (nvec + 2);
+            for (int pass = 0; pass < (o.reorth ? 2 : 1); ++pass) {
+                double2* hp = pass ? L.h2 : L.h1;
+                {
+                    ProfScope ps(c.prof, c.stream, VIE_K_GS_DOT, dot_bytes);
+                    launch_multidot<R>(L.partial, Vb, ldv, nvec, w, n, n, n, na, nb, c.stream);
+                    launch_reduce_partials(hp, L.partial, nvec, nb, na, c.stream);
+                }
+                {
+                    ProfScope ps(c.prof, c.stream, VIE_K_GS_UPDATE, upd_bytes + (pass == (o.reorth ? 1 : 0) ? 2 * vb : 0));
+                    launch_update<R>(w, Vb, ldv, nvec, hp, n, n, n, L.npart, na, nb, c.stream);
+                    if (pass == (o.reorth ? 1 : 0)) {
+                        launch_reduce_norm(L.nrm, L.npart, nb, na, c.stream);
+                        launch_scale_into<R>(w, w, L.nrm, n, n, n, na, c.stream);
+                    }
+                }
+            }
+            // the column's slot was last read by the host for step j - 2,
+            // which process() finished before this step was enqueued
+            const int sl = j & 1;
+            VIE_HIP(hipMemcpyAsync(slot_h1(sl), L.h1, (size_t)na * nvec * sizeof(double2), hipMemcpyDeviceToHost,
+                                   c.stream));
+            if (o.reorth)
+                VIE_HIP(hipMemcpyAsync(slot_h2(sl), L.h2, (size_t)na * nvec * sizeof(double2),
+                                       hipMemcpyDeviceToHost, c.stream));
+            VIE_HIP(hipMemcpyAsync(slot_nrm(sl), L.nrm, na * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            VIE_HIP(hipEventRecord(c.col_ev[sl], c.stream));
+            launched = j + 1;
+            if (j >= 1) {
+                const int rc = process(j - 1);
+                if (rc < 0) return VIE_ENAN;
+                jdone = j;
+                if (rc > 0) stop = 1;
+            }
+        }
+        if (!stop && launched > jdone) {
+            const int rc = process(launched - 1);
+            if (rc < 0) return VIE_ENAN;
+            jdone = launched;
         }
         // x += V y with y from the triangular system (FP64)
         std::vector<double2> yh((size_t)na * jdone);
