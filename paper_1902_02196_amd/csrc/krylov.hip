@@ -34,8 +34,53 @@ template <> struct Unit<double> {
     __device__ static void set(T& u, int, double2 v) { u = v; }
 };
 
-// partial[(r * nvec + i) * nblocks + block] = sum over the block's elements of conj(V_i) w
-// (vectors read in 16-byte units; n must be a multiple of the unit size)
+// One group of G basis vectors (G compile-time, so that the G + 1 loads of an
+// element are issued together with no guard between them): FP64 sums of
+// conj(V_i) w over this thread's elements, reduced over the workgroup and
+// written to partial[(r * nvec + i) * nblocks + block].
+template <typename R, int G>
+__device__ __forceinline__ void dot_group(double2* __restrict__ partial, const typename Unit<R>::T* __restrict__ V,
+                                          const typename Unit<R>::T* __restrict__ wr, long long ldu, long long nu,
+                                          int i0, int nvec, int r, double (*red)[2 * kGroup]) {
+    using U = Unit<R>;
+    using T = typename U::T;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long stride = (long long)gridDim.x * kTpb;
+    double ar[G], ai[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) ar[g] = ai[g] = 0.0;
+    for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < nu; k += stride) {
+        const T wu = wr[k];
+        T vu[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) vu[g] = V[(i0 + g) * ldu + k];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+#pragma unroll
+            for (int h = 0; h < U::per; ++h) {
+                const double2 v = U::get(vu[g], h), wv = U::get(wu, h);
+                ar[g] += v.x * wv.x + v.y * wv.y;
+                ai[g] += v.x * wv.y - v.y * wv.x;
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const double sr = wave_sum(ar[g]), si = wave_sum(ai[g]);
+        if (lane == 0) { red[wave][2 * g] = sr; red[wave][2 * g + 1] = si; }
+    }
+    __syncthreads();
+    if (threadIdx.x < G) {
+        const int g = threadIdx.x;
+        double sr = 0, si = 0;
+        for (int wv = 0; wv < kTpb / 64; ++wv) { sr += red[wv][2 * g]; si += red[wv][2 * g + 1]; }
+        partial[((long long)r * nvec + i0 + g) * gridDim.x + blockIdx.x] = make_double2(sr, si);
+    }
+    __syncthreads();
+}
+
+// partial sums of conj(V_i) w for i < nvec, groups of kGroup vectors and one
+// remainder group (vectors read in 16-byte units; n a multiple of the unit)
 template <typename R>
 __global__ void __launch_bounds__(kTpb) k_multidot(double2* __restrict__ partial, const C<R>* __restrict__ Vb,
                                                    long long ldv, int nvec, const C<R>* __restrict__ w, long long n,
@@ -47,41 +92,16 @@ __global__ void __launch_bounds__(kTpb) k_multidot(double2* __restrict__ partial
     const T* V = reinterpret_cast<const T*>(Vb + r * rsv);
     const T* wr = reinterpret_cast<const T*>(w + r * rsw);
     const long long nu = n / U::per, ldu = ldv / U::per;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long long stride = (long long)gridDim.x * kTpb;
-    for (int i0 = 0; i0 < nvec; i0 += kGroup) {
-        const int ng = min(kGroup, nvec - i0);
-        double ar[kGroup], ai[kGroup];
-#pragma unroll
-        for (int g = 0; g < kGroup; ++g) ar[g] = ai[g] = 0.0;
-        for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < nu; k += stride) {
-            const T wu = wr[k];
-#pragma unroll
-            for (int g = 0; g < kGroup; ++g) {
-                if (g < ng) {
-                    const T vu = V[(i0 + g) * ldu + k];
-#pragma unroll
-                    for (int h = 0; h < U::per; ++h) {
-                        const double2 v = U::get(vu, h), wv = U::get(wu, h);
-                        ar[g] += v.x * wv.x + v.y * wv.y;
-                        ai[g] += v.x * wv.y - v.y * wv.x;
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int g = 0; g < kGroup; ++g) {
-            const double sr = wave_sum(ar[g]), si = wave_sum(ai[g]);
-            if (lane == 0) { red[wave][2 * g] = sr; red[wave][2 * g + 1] = si; }
-        }
-        __syncthreads();
-        if (threadIdx.x < ng) {
-            const int g = threadIdx.x;
-            double sr = 0, si = 0;
-            for (int wv = 0; wv < kTpb / 64; ++wv) { sr += red[wv][2 * g]; si += red[wv][2 * g + 1]; }
-            partial[((long long)r * nvec + i0 + g) * gridDim.x + blockIdx.x] = make_double2(sr, si);
-        }
-        __syncthreads();
+    int i0 = 0;
+    for (; i0 + kGroup <= nvec; i0 += kGroup) dot_group<R, kGroup>(partial, V, wr, ldu, nu, i0, nvec, r, red);
+    switch (nvec - i0) {
+#define VIE_DOT_REM(g_) \
+    case g_: dot_group<R, g_>(partial, V, wr, ldu, nu, i0, nvec, r, red); break;
+        VIE_DOT_REM(1) VIE_DOT_REM(2) VIE_DOT_REM(3) VIE_DOT_REM(4) VIE_DOT_REM(5) VIE_DOT_REM(6)
+        VIE_DOT_REM(7) VIE_DOT_REM(8) VIE_DOT_REM(9) VIE_DOT_REM(10) VIE_DOT_REM(11) VIE_DOT_REM(12)
+        VIE_DOT_REM(13) VIE_DOT_REM(14) VIE_DOT_REM(15)
+#undef VIE_DOT_REM
+        default: break;
     }
 }
 
@@ -127,7 +147,25 @@ __global__ void __launch_bounds__(kTpb) k_update(C<R>* __restrict__ w, const C<R
         double2 wv[U::per];
 #pragma unroll
         for (int q = 0; q < U::per; ++q) wv[q] = U::get(wu, q);
-        for (int i = 0; i < nvec; ++i) {
+        // the basis vectors in blocks of 8 (their loads issued together),
+        // then one at a time
+        int i = 0;
+        for (; i + 8 <= nvec; i += 8) {
+            T vu[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) vu[u] = V[(i + u) * ldu + k];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double2 hi = hr[i + u];
+#pragma unroll
+                for (int q = 0; q < U::per; ++q) {
+                    const double2 v = U::get(vu[u], q);
+                    wv[q].x -= hi.x * v.x - hi.y * v.y;
+                    wv[q].y -= hi.x * v.y + hi.y * v.x;
+                }
+            }
+        }
+        for (; i < nvec; ++i) {
             const T vu = V[i * ldu + k];
             const double2 hi = hr[i];
 #pragma unroll
