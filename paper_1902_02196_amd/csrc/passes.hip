@@ -407,6 +407,50 @@ __global__ void __launch_bounds__(p3_threads<R>()) k_p3_ct(C<R>* __restrict__ A,
     }
 }
 
+// Row copies between global memory and LDS for the x pass: one wavefront per
+// row (the row address is uniform over the wave), four rows in flight per
+// wave.  Row i holds Nx contiguous elements at rowp(i); in LDS it is padded
+// with zeros to N.
+template <typename R, int N, int NT, typename RowPtr>
+__device__ __forceinline__ void rows_to_lds(C<R>* buf, int nrows, int Nx, RowPtr rowp) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int i0 = wave; i0 < nrows; i0 += 4 * NW) {
+        const C<R>* src[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) src[u] = rowp(min(i0 + u * NW, nrows - 1));
+        for (int k = lane; k < N; k += 64) {
+            C<R> v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = (i0 + u * NW < nrows && k < Nx) ? src[u][k] : mk<R>(0, 0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (i0 + u * NW < nrows) buf[lds_pad((i0 + u * NW) * N + k)] = v[u];
+        }
+    }
+}
+
+template <typename R, int N, int NT, typename RowPtr>
+__device__ __forceinline__ void lds_to_rows(const C<R>* buf, int nrows, int Nx, RowPtr rowp) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int i0 = wave; i0 < nrows; i0 += 4 * NW) {
+        C<R>* dst[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) dst[u] = rowp(min(i0 + u * NW, nrows - 1));
+        for (int k = lane; k < Nx; k += 64) {
+            C<R> v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = buf[lds_pad(min(i0 + u * NW, nrows - 1) * N + k)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (i0 + u * NW < nrows) dst[u][k] = v[u];
+        }
+    }
+}
+
 // Light variant of the x pass: one workgroup of 256 threads per pencil group
 // (one right-hand side, one of the up to four sibling pencils of an octant
 // row), 12 rows of N in LDS and nothing else, so that many workgroups share a
@@ -462,32 +506,10 @@ __global__ void __launch_bounds__(kP3SmallThreads) k_p3_small(C<R>* __restrict__
     const int z = sz ? p.Mz - oz : oz;
     const int y = sy ? p.My - oy : oy;
     C<R>* base = A + (long long)r * p.s_r + (long long)z * p.s_z + (long long)y * p.s_y;   // 12 rows of Nx, stride s_c
+    const long long s_c = p.s_c;
+    auto rowp = [=](int c) { return base + c * s_c; };
     for (int m = tid; m < N; m += NT) twl[m] = tw[m];
-    // gather (the 12 rows are one contiguous block when s_c == Nx)
-    const int tot = 12 * p.Nx;
-    for (int b0 = 0; b0 < tot; b0 += 4 * NT) {
-        C<R> v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = b0 + tid + i * NT;
-            if (e < tot) {
-                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
-                v[i] = base[(long long)c * p.s_c + k];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = b0 + tid + i * NT;
-            if (e < tot) {
-                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
-                buf[lds_pad(c * N + k)] = v[i];
-            }
-        }
-    }
-    for (int e = tid; e < 12 * N; e += NT) {
-        const int c = e / N, k = e - c * N;
-        if (k >= p.Nx) buf[lds_pad(e)] = mk<R>(0, 0);
-    }
+    rows_to_lds<R, N, NT>(buf, 12, p.Nx, rowp);
     __syncthreads();
     ct_passes<R, true, N, 0, 1, NT, 12>(buf, twl, 12, N, tid);
     const C<R>* Ur = U + (long long)row * 60 * OX;
@@ -555,25 +577,7 @@ __global__ void __launch_bounds__(kP3SmallThreads) k_p3_small(C<R>* __restrict__
     }
     __syncthreads();
     ct_passes<R, false, N, 0, 1, NT, 12>(buf, twl, 12, N, tid);
-    for (int b0 = 0; b0 < tot; b0 += 4 * NT) {
-        C<R> v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = b0 + tid + i * NT;
-            if (e < tot) {
-                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
-                v[i] = buf[lds_pad(c * N + k)];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = b0 + tid + i * NT;
-            if (e < tot) {
-                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
-                base[(long long)c * p.s_c + k] = v[i];
-            }
-        }
-    }
+    lds_to_rows<R, N, NT>(buf, 12, p.Nx, rowp);
 }
 
 // Prefetching variant of the light x pass (fft lengths up to 128): as the
@@ -615,6 +619,8 @@ __global__ void __launch_bounds__(kP3SmallThreads) k_p3_pref(C<R>* __restrict__ 
     const int z = sz ? p.Mz - oz : oz;
     const int y = sy ? p.My - oy : oy;
     C<R>* base = A + (long long)r * p.s_r + (long long)z * p.s_z + (long long)y * p.s_y;
+    const long long s_c = p.s_c;
+    auto rowp = [=](int c) { return base + c * s_c; };
     const C<R>* Ur = U + (long long)row * UN;
     C<R> upre[UPT];
 #pragma unroll
@@ -623,30 +629,7 @@ __global__ void __launch_bounds__(kP3SmallThreads) k_p3_pref(C<R>* __restrict__ 
         if (idx < UN) upre[i] = Ur[idx];
     }
     for (int m = tid; m < N; m += NT) twl[m] = tw[m];
-    const int tot = 12 * p.Nx;
-    for (int b0 = 0; b0 < tot; b0 += 4 * NT) {
-        C<R> v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = b0 + tid + i * NT;
-            if (e < tot) {
-                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
-                v[i] = base[(long long)c * p.s_c + k];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = b0 + tid + i * NT;
-            if (e < tot) {
-                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
-                buf[lds_pad(c * N + k)] = v[i];
-            }
-        }
-    }
-    for (int e = tid; e < 12 * N; e += NT) {
-        const int c = e / N, k = e - c * N;
-        if (k >= p.Nx) buf[lds_pad(e)] = mk<R>(0, 0);
-    }
+    rows_to_lds<R, N, NT>(buf, 12, p.Nx, rowp);
     __syncthreads();
     ct_passes<R, true, N, 0, 1, NT, 12>(buf, twl, 12, N, tid);
 #pragma unroll
@@ -677,25 +660,7 @@ __global__ void __launch_bounds__(kP3SmallThreads) k_p3_pref(C<R>* __restrict__ 
     }
     __syncthreads();
     ct_passes<R, false, N, 0, 1, NT, 12>(buf, twl, 12, N, tid);
-    for (int b0 = 0; b0 < tot; b0 += 4 * NT) {
-        C<R> v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = b0 + tid + i * NT;
-            if (e < tot) {
-                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
-                v[i] = buf[lds_pad(c * N + k)];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = b0 + tid + i * NT;
-            if (e < tot) {
-                const int c = fast_div((unsigned)e, p.magic_nx), k = e - c * p.Nx;
-                base[(long long)c * p.s_c + k] = v[i];
-            }
-        }
-    }
+    lds_to_rows<R, N, NT>(buf, 12, p.Nx, rowp);
 }
 
 // Sibling-sharing variant of the x pass: one workgroup of 256 threads per
@@ -749,34 +714,16 @@ __global__ void __launch_bounds__(kP3QuadThreads) k_p3_quad(C<R>* __restrict__ A
     const int nz_sib = (oz == 0 || 2 * oz == p.Mz) ? 1 : 2;
     const int nrows = 12 * ny_sib * nz_sib;   // LDS row s * 12 + c, sibling s = sz * ny_sib + sy
     C<R>* base = A + (long long)r * p.s_r;
+    const long long s_c = p.s_c, s_y = p.s_y, s_z = p.s_z;
+    const int Mz = p.Mz, My = p.My;
+    auto rowp = [=](int rr) {
+        const int sb = rr / 12, c = rr - 12 * sb;
+        const int sz = sb >= ny_sib, sy = sb - sz * ny_sib;
+        const int z = sz ? Mz - oz : oz, y = sy ? My - oy : oy;
+        return base + z * s_z + y * s_y + c * s_c;
+    };
     for (int m = tid; m < N; m += NT) twl[m] = tw[m];
-    const int tot = nrows * p.Nx;
-    for (int b0 = 0; b0 < tot; b0 += 4 * NT) {
-        C<R> v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = b0 + tid + i * NT;
-            if (e < tot) {
-                const int rr = fast_div((unsigned)e, p.magic_nx), k = e - rr * p.Nx;
-                const int sb = rr / 12, c = rr - 12 * sb;
-                const int sz = sb >= ny_sib, sy = sb - sz * ny_sib;
-                const int z = sz ? p.Mz - oz : oz, y = sy ? p.My - oy : oy;
-                v[i] = base[(long long)z * p.s_z + (long long)y * p.s_y + (long long)c * p.s_c + k];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = b0 + tid + i * NT;
-            if (e < tot) {
-                const int rr = fast_div((unsigned)e, p.magic_nx), k = e - rr * p.Nx;
-                buf[lds_pad(rr * N + k)] = v[i];
-            }
-        }
-    }
-    for (int e = tid; e < nrows * N; e += NT) {
-        const int rr = e / N, k = e - rr * N;
-        if (k >= p.Nx) buf[lds_pad(e)] = mk<R>(0, 0);
-    }
+    rows_to_lds<R, N, NT>(buf, nrows, p.Nx, rowp);
     __syncthreads();
     ct_passes<R, true, N, 0, 1, NT, 48>(buf, twl, nrows, N, tid);
     {
@@ -832,28 +779,7 @@ __global__ void __launch_bounds__(kP3QuadThreads) k_p3_quad(C<R>* __restrict__ A
     }
     __syncthreads();
     ct_passes<R, false, N, 0, 1, NT, 48>(buf, twl, nrows, N, tid);
-    for (int b0 = 0; b0 < tot; b0 += 4 * NT) {
-        C<R> v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = b0 + tid + i * NT;
-            if (e < tot) {
-                const int rr = fast_div((unsigned)e, p.magic_nx), k = e - rr * p.Nx;
-                v[i] = buf[lds_pad(rr * N + k)];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = b0 + tid + i * NT;
-            if (e < tot) {
-                const int rr = fast_div((unsigned)e, p.magic_nx), k = e - rr * p.Nx;
-                const int sb = rr / 12, c = rr - 12 * sb;
-                const int sz = sb >= ny_sib, sy = sb - sz * ny_sib;
-                const int z = sz ? p.Mz - oz : oz, y = sy ? p.My - oy : oy;
-                base[(long long)z * p.s_z + (long long)y * p.s_y + (long long)c * p.s_c + k] = v[i];
-            }
-        }
-    }
+    lds_to_rows<R, N, NT>(buf, nrows, p.Nx, rowp);
 }
 
 // lengths with a compile-time kernel
