@@ -1,0 +1,158 @@
+"""Parity at the benchmark sizes, in the launch shapes the benchmark uses
+(autotuned), on outputs the oracle can compute one by one.
+
+* A unit current at one voxel and component a makes the operator product's
+  output at voxel m equal to column a of the block T(m - n0) (eq. 42-43): the
+  device's whole FFT path (embedding, transforms, octant product, crop) is
+  checked at sampled m against the oracle's blocks at those offsets.
+* The Galerkin operator is complex symmetric (x2^T N x1 = x1^T N x2 for the
+  reciprocal kernel): checked for random vectors at full size.
+* The preconditioned solves reach the requested residual, and the FP32 +
+  refinement solution matches the FP64 one.
+
+Grids: 64 x 64 x 64 at 3 mm, 298 MHz (single right-hand side) and
+96 x 128 x 128 at 2 mm, 298 MHz with 16 right-hand sides in one batch.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import vie_inputs as vi
+from oracle import physics, toeplitz
+
+pytestmark = pytest.mark.gpu
+
+F = 298e6
+K = physics.k0(F)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def vie(torch):
+    import paper_1902_02196_amd as v
+    return v
+
+
+def _samples(N, n0, g, count):
+    """Output voxels: the source itself, its neighbours, the far corners and
+    random ones."""
+    Nx, Ny, Nz = N
+    pts = {tuple(n0)}
+    for d in ((1, 0, 0), (0, 1, 0), (0, 0, 1), (-1, -1, 0), (2, 0, -1)):
+        m = tuple(int(np.clip(n0[i] + d[i], 0, N[i] - 1)) for i in range(3))
+        pts.add(m)
+    for c in ((0, 0, 0), (Nx - 1, Ny - 1, Nz - 1), (Nx - 1, 0, Nz - 1), (0, Ny - 1, 0)):
+        pts.add(c)
+    while len(pts) < count:
+        pts.add(tuple(int(g.integers(0, N[i])) for i in range(3)))
+    return sorted(pts)
+
+
+def _check_delta_columns(vie, torch, c, N, D, sources, dtype, tol, tag):
+    """sources: list of (n0 (ix, iy, iz), component a), one per right-hand side."""
+    nrhs = len(sources)
+    x = torch.zeros((nrhs, 12, N[2], N[1], N[0]), dtype=dtype, device="cuda")
+    for r, (n0, a) in enumerate(sources):
+        x[r, a, n0[2], n0[1], n0[0]] = 1.0
+    y = torch.empty_like(x)
+    c.apply(x, y, op=vie.OP_N)
+    g = vi.rng(7001)
+    worst = 0.0
+    for r, (n0, a) in enumerate(sources):
+        ms = _samples(N, n0, g, 14)
+        offs = np.array([[m[i] - n0[i] for i in range(3)] for m in ms])
+        ref = toeplitz.galerkin_blocks(offs, D, K)[:, :, a]          # [S, 12]
+        got = np.stack([y[r, :, m[2], m[1], m[0]].cpu().numpy() for m in ms])
+        scale = np.abs(ref).max()
+        err = float(np.abs(got - ref).max() / scale)
+        worst = max(worst, err)
+        assert err < tol, (tag, r, n0, a, err)
+    _say("  %s: worst sampled error %.3e over %d sources" % (tag, worst, nrhs))
+
+
+def test_delta_columns_phantom64(vie, torch):
+    N, D = (64, 64, 64), (0.003,) * 3
+    c = vie.Context(0)
+    c.set_grid(N, D, F)
+    sources = [((0, 0, 0), 0), ((31, 32, 30), 5), ((63, 17, 40), 11), ((10, 63, 63), 2)]
+    for prec, dtype, tol in ((vie.C128, torch.complex128, 1e-10), (vie.C64, torch.complex64, 1e-5)):
+        choice, ms = c.autotune(prec, len(sources))
+        _say("  autotune %s: %s %.3f ms" % (dtype, choice, ms))
+        _check_delta_columns(vie, torch, c, N, D, sources, dtype, tol, "64^3 %s" % dtype)
+
+
+def test_delta_columns_head_batch16(vie, torch):
+    N, D = (96, 128, 128), (0.002,) * 3
+    c = vie.Context(0)
+    c.set_grid(N, D, F)
+    g = vi.rng(7002)
+    sources = [(tuple(int(g.integers(0, N[i])) for i in range(3)), int(g.integers(0, 12))) for _ in range(16)]
+    choice, ms = c.autotune(vie.C64, 16)
+    _say("  autotune c64 x16: %s %.3f ms" % (choice, ms))
+    _check_delta_columns(vie, torch, c, N, D, sources, torch.complex64, 1e-5, "head c64 x16")
+    _check_delta_columns(vie, torch, c, N, D, sources[:4], torch.complex128, 1e-10, "head c128 x4")
+
+
+def test_complex_symmetry_full_size(vie, torch):
+    N, D = (64, 64, 64), (0.003,) * 3
+    c = vie.Context(0)
+    c.set_grid(N, D, F)
+    c.autotune(vie.C128, 1)
+    x1 = torch.from_numpy(vi.complex_normal(81, (1, 12, N[2], N[1], N[0]))).cuda()
+    x2 = torch.from_numpy(vi.complex_normal(82, (1, 12, N[2], N[1], N[0]))).cuda()
+    y1, y2 = torch.empty_like(x1), torch.empty_like(x2)
+    c.apply(x1, y1, op=vie.OP_N)
+    c.apply(x2, y2, op=vie.OP_N)
+    a = complex((x2 * y1).sum().item())
+    b = complex((x1 * y2).sum().item())
+    bound = float(torch.linalg.vector_norm(x2) * torch.linalg.vector_norm(y1))
+    _say("  x2^T N x1 = %s, x1^T N x2 = %s, |diff| / (|x2| |N x1|) = %.3e" % (a, b, abs(a - b) / bound))
+    assert abs(a - b) <= 1e-12 * bound
+
+
+def test_solves_at_full_size(vie, torch):
+    """64^3 phantom, plane wave: both solver modes reach 1e-6 (the library's
+    complex128 residual recomputed here), and the refined FP32 solution's
+    fields agree with the FP64 one within 1e-5."""
+    N, D = (64, 64, 64), (0.003,) * 3
+    c = vie.Context(0)
+    c.set_grid(N, D, F)
+    c.autotune(vie.C64, 1)
+    e, s = vi.ellipsoid_phantom(N, D, 190202196 + 1)
+    c.set_contrast(np.ascontiguousarray(e.transpose(2, 1, 0)), np.ascontiguousarray(s.transpose(2, 1, 0)))
+    et = torch.empty(c.vec_shape(1), dtype=torch.complex128, device="cuda")
+    c.incident_planewave(et)
+    b = torch.empty_like(et)
+    c.rhs_prec(et, b)
+    out = {}
+    for mode in (vie.SOLVE_FP32_IR, vie.SOLVE_FP64):
+        x = torch.empty_like(et)
+        code, st = c.solve(et, x, mode=mode, tol=1e-6)
+        assert code == vie.VIE_OK and st[0]["converged"]
+        ax = torch.empty_like(x)
+        c.apply(x, ax, op=vie.OP_PREC)
+        rel = float(torch.linalg.vector_norm(b - ax) / torch.linalg.vector_norm(b))
+        _say("  mode %d: %d iterations, residual %.3e (solver %.3e)" % (mode, st[0]["iterations"], rel,
+                                                                         st[0]["rel_residual"]))
+        assert rel <= 1.05e-6
+        fields = torch.empty_like(x)
+        c.fields(x, fields)
+        out[mode] = (fields, c.absorbed_power(x)[0])
+    (f32, p32), (f64, p64) = out[vie.SOLVE_FP32_IR], out[vie.SOLVE_FP64]
+    ferr = float(torch.linalg.vector_norm(f32 - f64) / torch.linalg.vector_norm(f64))
+    _say("  fields IR vs FP64: %.3e, power %.3e" % (ferr, abs(p32 - p64) / abs(p64)))
+    assert ferr < 1e-5
+    assert abs(p32 - p64) / abs(p64) < 1e-5
