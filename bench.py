@@ -28,8 +28,9 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_EVERY = 8
 
 # sources whose change invalidates counter measurements of the kernels
-KERNEL_SOURCES = ["paper_1902_02196_amd/csrc/passes.hip", "paper_1902_02196_amd/csrc/fft.hpp",
-                  "paper_1902_02196_amd/csrc/fft_ct.hpp", "paper_1902_02196_amd/csrc/passes.hpp",
+KERNEL_SOURCES = ["paper_1902_02196_amd/csrc/passes.hip", "paper_1902_02196_amd/csrc/strided.hip",
+                  "paper_1902_02196_amd/csrc/fft.hpp", "paper_1902_02196_amd/csrc/fft_ct.hpp",
+                  "paper_1902_02196_amd/csrc/passes.hpp", "paper_1902_02196_amd/csrc/common.hpp",
                   "paper_1902_02196_amd/csrc/krylov.hip", "paper_1902_02196_amd/csrc/apply.cpp"]
 
 
@@ -66,6 +67,10 @@ WORKLOADS = {
     # head-sized box, 16 Hertzian dipoles on a 15 cm cylinder, one batched solve
     "batched16": dict(N=(96, 128, 128), h=0.002, f=298e6, seed=190202196 + 3, nrhs=16, cyl=0.15,
                       fp64_rhs=4),
+    # whole-body box, 10-class layered phantom, 8 dipoles on a ring, solved
+    # in groups of right-hand sides that fit HBM
+    "body8": dict(N=(128, 256, 384), h=0.005, f=128e6, seed=190202196 + 5, nrhs=8, ring=(0.30, 0.56), group=2,
+                  fp64_rhs=1, layered=True),
 }
 
 
@@ -241,12 +246,14 @@ def main():
     torch.cuda.synchronize()
     t_grid = time.perf_counter() - t0
     t0 = time.perf_counter()
-    tune64 = ctx.autotune(vie.C64, W.get("nrhs", 1))
+    tune64 = ctx.autotune(vie.C64, W.get("group", W.get("nrhs", 1)))
     tune128 = ctx.autotune(vie.C128, 1)
     t_tune = time.perf_counter() - t0
     log("autotune %.2f s: c64 %s, c128 %s" % (t_tune, tune64, tune128))
     if W["seed"] is None:
         e, s = vi.sphere(N, D, 0.03, 50.0, 0.7)
+    elif W.get("layered"):
+        e, s = vi.layered_phantom(N, D, W["seed"])
     else:
         e, s = vi.ellipsoid_phantom(N, D, W["seed"])
     ctx.set_contrast(np.ascontiguousarray(e.transpose(2, 1, 0)), np.ascontiguousarray(s.transpose(2, 1, 0)))
@@ -255,10 +262,33 @@ def main():
     if nrhs == 1:
         ctx.incident_planewave(et)
         excitation = "x-polarised plane wave"
+    elif "ring" in W:
+        pos, mom = vi.dipole_ring(nrhs, *W["ring"])
+        ctx.incident_dipoles(et, pos, mom)
+        excitation = ("%d z-directed Hertzian dipoles on a %.0f x %.0f cm ring, solved in groups of %d"
+                      % (nrhs, 200 * W["ring"][0], 200 * W["ring"][1], W["group"]))
     else:
         pos, mom = vi.dipoles_on_cylinder(W["seed"] + 1, nrhs, W["cyl"], N[2] * h)
         ctx.incident_dipoles(et, pos, mom)
         excitation = "%d z-directed Hertzian dipoles on a %.0f cm cylinder, one batched solve" % (nrhs, W["cyl"] * 100)
+    group = W.get("group", nrhs)
+
+    def solve_all(opts):
+        """Solve every right-hand side, `group` at a time; returns the status
+        and per-right-hand-side statistics."""
+        code, stl = vie.VIE_OK, []
+        for g0 in range(0, nrhs, group):
+            if group == nrhs:
+                c_, s_ = ctx.solve(et, x, opts)
+            else:
+                xg = torch.empty_like(et[g0:g0 + group])
+                c_, s_ = ctx.solve(et[g0:g0 + group].contiguous(), xg, opts)
+                x[g0:g0 + group].copy_(xg)
+                del xg
+                log("  right-hand sides %d-%d: %s" % (g0, g0 + group - 1, max(s_, key=lambda d: d["iterations"])))
+            code = code if code != vie.VIE_OK else c_
+            stl += s_
+        return code, stl
     x = torch.empty_like(et)
     log("setup: grid+operator %.2f s" % t_grid)
 
@@ -266,7 +296,7 @@ def main():
                                reorth=args.reorth)
     opts_64 = vie.default_opts(mode=vie.SOLVE_FP64, tol=1e-6, restart=args.restart, reorth=args.reorth)
     for i in range(args.warmup):
-        code, st = ctx.solve(et, x, opts_ir)
+        code, st = solve_all(opts_ir)
         log("warmup %d: %s" % (i, st[0]))
 
     # timed region: K full solves; one launch in PROFILE_EVERY of each kernel
@@ -276,7 +306,7 @@ def main():
     t0 = time.perf_counter()
     stats = []
     for i in range(args.steps):
-        code, st = ctx.solve(et, x, opts_ir)
+        code, st = solve_all(opts_ir)
         stats.append(max(st, key=lambda d: d["iterations"]))
         log("step %d: %s" % (i, stats[-1]))
     torch.cuda.synchronize()
@@ -284,11 +314,11 @@ def main():
     prof = ctx.profile_read()
     ctx.profile(False)
     assert code == vie.VIE_OK, "IR solve did not converge: %s" % stats[-1]
-    x_ir = x.clone()
+    n64 = min(nrhs, W.get("fp64_rhs", nrhs))
+    x_ir = x[:n64].clone()
 
     # FP64 path for comparison (same timing discipline, one solve; on the
     # first right-hand sides only when all of them would not fit in HBM)
-    n64 = min(nrhs, W.get("fp64_rhs", nrhs))
     et64 = et[:n64].contiguous()
     x64 = torch.empty_like(et64)
     torch.cuda.synchronize()
@@ -310,7 +340,7 @@ def main():
     del e_ir, e_64, xi, et64
 
     # operator product alone (complex64, preconditioned), for GB/s
-    xv = torch.randn(ctx.vec_shape(nrhs), dtype=torch.complex64, device=dev)
+    xv = torch.randn(ctx.vec_shape(group), dtype=torch.complex64, device=dev)
     yv = torch.empty_like(xv)
     for _ in range(3):
         ctx.apply(xv, yv, op=vie.OP_PREC)
@@ -362,7 +392,8 @@ def main():
         "config": {"workload": "%s: %dx%dx%d voxels at %.0f mm, %.0f MHz, %s, %s, "
                                "GMRES(%d) to 1e-6, complex64 + FP64 refinement"
                                % (args.workload, N[0], N[1], N[2], h * 1e3, f / 1e6,
-                                  "6-class ellipsoid phantom" if W["seed"] else "eps 50 sigma 0.7 sphere r=3 cm",
+                                  ("10-class layered phantom" if W.get("layered") else "6-class ellipsoid phantom")
+                                  if W["seed"] else "eps 50 sigma 0.7 sphere r=3 cm",
                                   excitation, args.restart), "nrhs": nrhs},
         "fp64_solves_per_s": round(n64 / t_64, 4),
         "fp64_rhs": n64,

@@ -26,12 +26,7 @@ template <typename R> static const C<R>* opspec(const Ctx& c);
 template <> const C<float>* opspec<float>(const Ctx& c) { return c.U64; }
 template <> const C<double>* opspec<double>(const Ctx& c) { return c.U128; }
 
-static int pick_tile(int n, size_t elem) {
-    // two LDS buffers of tile x n elements within 96 KiB; 4..16 pencils
-    int t = 16;
-    while (t > 4 && 2 * (size_t)t * n * elem > 96 * 1024) t /= 2;
-    return t;
-}
+static int pick_tile(int n, size_t elem) { return strided_tile_for((int)elem, n, 16); }
 
 template <typename R>
 void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs) {
@@ -138,6 +133,7 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
             // operator row among all siblings and right-hand sides of a
             // workgroup
             p3.variant = tn.p3_variant >= 0 ? tn.p3_variant : 1;
+            if (p3.variant == 0 && !p3_ct_fits((int)es, Mx)) p3.variant = 1;   // staged row would not fit LDS
             p3.sib_blocks = tn.p3_sib_blocks ? tn.p3_sib_blocks : 1;
             g = std::min(p3_ct_groups((int)es, Mx), (4 / p3.sib_blocks) * nrhs);
             g = std::max(g, 1);

@@ -14,10 +14,17 @@ template <typename R>
 void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s);
 bool p3_ct_supported(int n);
 int p3_ct_groups(int es, int n);
+bool p3_ct_fits(int es, int n);
 bool p3_quad_fits(int es, int n);
 bool p3_pref_fits(int n);
+// strided.hip: compiled-length strided passes; false when (length, tile)
+// has no compiled kernel
+template <typename R>
+bool launch_strided_compiled(bool fwd, bool epi, const C<R>* in, C<R>* out, const StridedPass& p, long long n_o2,
+                             long long n_o1, const C<R>* tw, const Epilogue<R>& ep, hipStream_t s);
 bool strided_ct_fits(int es, int n, int tile);
 bool strided_tile_ok(int es, int n, int tile);
+int strided_tile_for(int es, int n, int preferred);
 template <typename R>
 void launch_rows(bool fwd, C<R>* data, long long nrows, const FftPlan& plan, const C<R>* tw, hipStream_t s);
 

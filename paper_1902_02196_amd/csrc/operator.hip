@@ -657,8 +657,8 @@ void embed_and_transform(double2* U128, float2* U64, const double2* T, double2* 
         pz.plan = plans[2];
         pz.n_in = pz.n_out = Mz;
         pz.n_inner = Mx;
-        pz.tile = 16;
-        pz.pitch = 16;
+        pz.tile = strided_tile_for((int)sizeof(double2), Mz, 16);
+        pz.pitch = pz.tile;
         pz.in_s1 = pz.out_s1 = 0;
         pz.in_sc = pz.out_sc = 0;
         pz.in_s2 = pz.out_s2 = Mx;          // o2 = y
@@ -668,8 +668,8 @@ void embed_and_transform(double2* U128, float2* U64, const double2* T, double2* 
         py.plan = plans[1];
         py.n_in = py.n_out = My;
         py.n_inner = Mx;
-        py.tile = 16;
-        py.pitch = 16;
+        py.tile = strided_tile_for((int)sizeof(double2), My, 16);
+        py.pitch = py.tile;
         py.in_s1 = py.out_s1 = 0;
         py.in_sc = py.out_sc = 0;
         py.in_s2 = py.out_s2 = (long long)Mx * My;   // o2 = z

@@ -56,65 +56,6 @@ __global__ void __launch_bounds__(256) k_strided(const C<R>* in, C<R>* out,
     }
 }
 
-// Compile-time-length strided pass: the tile's T pencils are held as T rows
-// of N in LDS (one buffer, padded) and transformed in place by the unrolled
-// Stockham passes; loads and stores run along t, T consecutive elements.
-template <typename R, bool FWD, bool EPI, int N, int T>
-__global__ void __launch_bounds__(256) k_strided_ct(const C<R>* in, C<R>* out, StridedPass p,
-                                                    const C<R>* __restrict__ tw, Epilogue<R> ep) {
-    constexpr int NT = 256;
-    extern __shared__ unsigned char smem_raw[];
-    C<R>* twl = reinterpret_cast<C<R>*>(smem_raw);
-    C<R>* buf = twl + N;
-    const int tid = threadIdx.x;
-    const int t0 = blockIdx.x * T;
-    const long long o2 = blockIdx.y;
-    const int o1 = blockIdx.z, rr = o1 / 12, cc = o1 - 12 * rr;
-    const int tw_n = min(T, p.n_inner - t0);
-    const C<R>* src = in + rr * p.in_s1 + cc * p.in_sc + o2 * p.in_s2 + t0;
-    for (int m = tid; m < N; m += NT) twl[m] = tw[m];
-    constexpr int LN = N * T;
-    constexpr int LPT = (LN + NT - 1) / NT;
-#pragma unroll
-    for (int i = 0; i < LPT; ++i) {
-        const int idx = tid + i * NT;
-        if (LN % NT == 0 || idx < LN) {
-            const int k = idx / T, t = idx - k * T;
-            C<R> v = mk<R>(0, 0);
-            if (k < p.n_in && t < tw_n) v = src[k * p.in_sk + t];
-            buf[lds_pad(t * N + k)] = v;
-        }
-    }
-    __syncthreads();
-    ct_passes<R, FWD, N, 0, 1, NT, T>(buf, twl, T, N, tid);
-    const long long obase = rr * p.out_s1 + cc * p.out_sc;
-    C<R>* dst = out + obase + o2 * p.out_s2 + t0;
-    const int l = cc & 3;
-#pragma unroll
-    for (int i = 0; i < LPT; ++i) {
-        const int idx = tid + i * NT;
-        if (LN % NT == 0 || idx < LN) {
-            const int k = idx / T, t = idx - k * T;
-            if (k < p.n_out && t < tw_n) {
-                C<R> w = buf[lds_pad(t * N + k)];
-                if (EPI) {
-                    const long long v = o2 * p.out_s2 + k * p.out_sk + t0 + t;   // voxel
-                    const long long e = obase + v;                                  // element
-                    C<R> bv = ep.b ? ep.b[v] : mk<R>(ep.b_const, 0);
-                    C<R> y = cscale(cmul(bv, w), ep.gb[l]);
-                    if (ep.a || ep.a_const != R(0)) {
-                        C<R> av = ep.a ? ep.a[v] : mk<R>(ep.a_const, 0);
-                        y = cadd(y, cscale(cmul(av, ep.x[e]), ep.ga[l]));
-                    }
-                    if (ep.rhs) y = cadd(y, ep.rhs[e]);
-                    w = y;
-                }
-                dst[k * p.out_sk + t] = w;
-            }
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // fused x pass
 // ---------------------------------------------------------------------------
@@ -797,6 +738,9 @@ bool p3_ct_supported(int n) {
 
 int p3_ct_groups(int es, int n) { return p3_gmax(es, n, 512); }
 
+// the staged variant holds the operator row and at least one pencil group
+bool p3_ct_fits(int es, int n) { return p3_ct_supported(n) && p3_lds_bytes(es, n, 1) <= 160 * 1024; }
+
 template <typename R, int N, int SPLIT>
 static void launch_p3_small_n(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
     const size_t lds = ((size_t)N + lds_pad(12 * N) + 2) * sizeof(C<R>);
@@ -863,6 +807,7 @@ static void launch_p3_ct_n(C<R>* A, const C<R>* U, const P3Params& p, const C<R>
     constexpr int GMAX = p3_gmax(sizeof(C<R>), N, NT);
     VIE_REQUIRE(p.groups >= 1 && p.groups <= GMAX && p.Ox == N / 2 + 1, -1, "x pass: bad group count");
     const size_t lds = (size_t)p3_lds_bytes(sizeof(C<R>), N, p.groups);
+    VIE_REQUIRE(lds <= 160 * 1024, -1, "x pass: staged variant does not fit LDS for this length");
     // allow more than the default 64 KiB of dynamic LDS (once per process;
     // the size is fixed per instantiation); a refusal shows up as a launch
     // error below, so clear the status here
@@ -919,74 +864,16 @@ static void launch_strided_t(const C<R>* in, C<R>* out, const StridedPass& p, lo
     VIE_HIP(hipGetLastError());
 }
 
-template <typename R, bool FWD, bool EPI, int N, int T>
-static void launch_strided_ct_nt(const C<R>* in, C<R>* out, const StridedPass& p, long long n_o2, long long n_o1,
-                                 const C<R>* tw, const Epilogue<R>& ep, hipStream_t s) {
-    const size_t lds = ((size_t)N + lds_pad(N * T) + 2) * sizeof(C<R>);
-    static std::once_flag once;
-    std::call_once(once, [&] {
-        (void)hipFuncSetAttribute((const void*)k_strided_ct<R, FWD, EPI, N, T>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        (void)hipGetLastError();
-    });
-    dim3 grid((p.n_inner + T - 1) / T, (unsigned)n_o2, (unsigned)n_o1);
-    hipLaunchKernelGGL((k_strided_ct<R, FWD, EPI, N, T>), grid, dim3(256), lds, s, in, out, p, tw, ep);
-    VIE_HIP(hipGetLastError());
-}
-
-template <typename R, bool FWD, bool EPI, int N>
-static void launch_strided_ct_n(const C<R>* in, C<R>* out, const StridedPass& p, long long n_o2, long long n_o1,
-                                const C<R>* tw, const Epilogue<R>& ep, hipStream_t s) {
-    if (p.tile == 16) launch_strided_ct_nt<R, FWD, EPI, N, 16>(in, out, p, n_o2, n_o1, tw, ep, s);
-    else launch_strided_ct_nt<R, FWD, EPI, N, 32>(in, out, p, n_o2, n_o1, tw, ep, s);
-}
-
-// compiled strided lengths (tiles of 16 or 32 pencils)
-#define VIE_STRIDED_LENGTHS(X) X(8) X(16) X(32) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
-
-bool strided_ct_fits(int es, int n, int tile) {
-    if (tile != 16 && tile != 32) return false;
-    switch (n) {
-#define CASE(n_) case n_:
-        VIE_STRIDED_LENGTHS(CASE)
-#undef CASE
-        return ((size_t)n + lds_pad(n * tile) + 2) * es <= 160 * 1024;
-        default: return false;
-    }
-}
-
-// a tile the strided pass can run: 16 or 32 pencils with a compiled length,
-// or 4, 8, 16 pencils in the generic kernel (two buffers within 96 KiB)
-bool strided_tile_ok(int es, int n, int tile) {
-    if (strided_ct_fits(es, n, tile)) return true;
-    return (tile == 4 || tile == 8 || tile == 16) && 2LL * tile * n * es <= 96 * 1024;
-}
-
-template <typename R, bool FWD, bool EPI>
-static bool launch_strided_ct(const C<R>* in, C<R>* out, const StridedPass& p, long long n_o2, long long n_o1,
-                              const C<R>* tw, const Epilogue<R>& ep, hipStream_t s) {
-    if (!strided_ct_fits((int)sizeof(C<R>), p.plan.n, p.tile)) return false;
-    switch (p.plan.n) {
-#define CASE(n_)                                                                   \
-    case n_:                                                                      \
-        launch_strided_ct_n<R, FWD, EPI, n_>(in, out, p, n_o2, n_o1, tw, ep, s); \
-        return true;
-        VIE_STRIDED_LENGTHS(CASE)
-#undef CASE
-        default: return false;
-    }
-}
-
 template <typename R>
 void launch_strided(bool fwd, const C<R>* in, C<R>* out, const StridedPass& p, long long n_o2, long long n_o1,
                     const C<R>* tw, const Epilogue<R>* ep, hipStream_t s) {
     Epilogue<R> none{};
     if (ep && !fwd) {
-        if (launch_strided_ct<R, false, true>(in, out, p, n_o2, n_o1, tw, *ep, s)) return;
+        if (launch_strided_compiled<R>(false, true, in, out, p, n_o2, n_o1, tw, *ep, s)) return;
     } else if (!ep && fwd) {
-        if (launch_strided_ct<R, true, false>(in, out, p, n_o2, n_o1, tw, none, s)) return;
+        if (launch_strided_compiled<R>(true, false, in, out, p, n_o2, n_o1, tw, none, s)) return;
     } else if (!ep) {
-        if (launch_strided_ct<R, false, false>(in, out, p, n_o2, n_o1, tw, none, s)) return;
+        if (launch_strided_compiled<R>(false, false, in, out, p, n_o2, n_o1, tw, none, s)) return;
     }
     if (ep) {
         if (fwd) throw Error(-1, "epilogue only on the inverse pass");

@@ -39,10 +39,11 @@ static Tune tune_t(Ctx& c, int nrhs, double* best_ms) {
     for (int var = 0; var <= 4; ++var)
         for (int sb : {1, 2, 4}) {
             if (var >= 1 && sb != 1) continue;
+            if (var == 0 && p3_ct_supported(c.M[0]) && !p3_ct_fits((int)sizeof(C<R>), c.M[0])) continue;
             if (var == 2 && !p3_quad_fits((int)sizeof(C<R>), c.M[0])) continue;
             if (var == 3 && !p3_pref_fits(c.M[0])) continue;
-            for (int tz : {8, 16, 32})
-                for (int ty : {8, 16, 32}) {
+            for (int tz : {4, 8, 16, 32})
+                for (int ty : {4, 8, 16, 32}) {
                     Tune t;
                     t.p3_variant = var;
                     t.p3_sib_blocks = sb;
