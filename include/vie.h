@@ -125,6 +125,16 @@ int vie_set_toeplitz(vie_ctx* ctx, const double* T_host);
  * host buffer of 60 * Nz * Ny * Nx complex128. */
 int vie_get_toeplitz(vie_ctx* ctx, double* T_host);
 
+/* Make dst use src's grid and operator (the same device buffers, read-only,
+ * freed with the last context that uses them) instead of assembling its own;
+ * dst's launch-shape choices are copied from src and its contrast cleared.
+ * For many solves on one grid from several contexts or streams.  Waits for
+ * src's stream.  vie_set_toeplitz refuses a shared operator. */
+int vie_share_grid(vie_ctx* dst, const vie_ctx* src);
+
+/* FFT grid size {M_x, M_y, M_z} chosen by vie_set_grid (host int[3]). */
+int vie_fft_size(vie_ctx* ctx, int* m3);
+
 /* -- materials and excitation (eq. 2, 7, 17, 27, 30-31) --------------------- */
 
 /* Per-voxel relative permittivity eps' and conductivity sigma (S/m), FP64
@@ -278,6 +288,7 @@ typedef struct {
     int iterations;      /* most GMRES iterations over its right-hand sides   */
     double rel_residual; /* largest final relative residual                   */
     char message[192];   /* error text when status != VIE_OK                  */
+    int operator_cached; /* 1 when the grid's operator came from the cache    */
 } vie_request_info;
 
 typedef struct {
@@ -285,13 +296,23 @@ typedef struct {
     double p50_s, p99_s, mean_s; /* latency = completion - arrival            */
     double makespan_s;           /* first arrival to last completion          */
     size_t peak_bytes;           /* largest sum of admitted footprints         */
+    long long operator_hits;     /* requests that reused a cached operator     */
+    long long operator_misses;   /* requests that assembled their operator     */
+    size_t operator_cache_bytes; /* device bytes held by the operator cache    */
 } vie_serving_stats;
 
 /* Create a server on HIP device `device` that admits requests while the sum
  * of their footprints (vie_footprint_bytes plus the request vectors) stays
  * within hbm_budget bytes and at most max_slots run at once.  Each admitted
- * request runs on its own worker thread, context and stream. */
+ * request runs on its own worker thread, context and stream.  Operators of
+ * recently used grids stay resident for later requests on the same grid
+ * (extents, voxel size, frequency), in a cache of hbm_budget / 8 bytes by
+ * default, held outside the budget (see vie_server_set_operator_cache). */
 int vie_server_create(vie_server** out, int device, size_t hbm_budget, int max_slots);
+
+/* Bytes the operator cache may hold (0 disables it); least recently used
+ * operators are dropped to fit. */
+int vie_server_set_operator_cache(vie_server* s, size_t bytes);
 
 /* Queue a request (returns at once); *id identifies it.  VIE_ENOMEM when its
  * footprint exceeds the whole budget, VIE_EINVAL on bad arguments. */

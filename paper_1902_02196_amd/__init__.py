@@ -57,12 +57,14 @@ class Request(ctypes.Structure):
 class RequestInfo(ctypes.Structure):
     _fields_ = [("done", _i), ("status", _i), ("t_arrival", _d), ("t_start", _d), ("t_end", _d),
                 ("footprint", ctypes.c_size_t), ("iterations", _i), ("rel_residual", _d),
-                ("message", ctypes.c_char * 192)]
+                ("message", ctypes.c_char * 192), ("operator_cached", _i)]
 
 
 class ServingStats(ctypes.Structure):
     _fields_ = [("completed", _i), ("queued", _i), ("running", _i), ("peak_running", _i), ("p50_s", _d),
-                ("p99_s", _d), ("mean_s", _d), ("makespan_s", _d), ("peak_bytes", ctypes.c_size_t)]
+                ("p99_s", _d), ("mean_s", _d), ("makespan_s", _d), ("peak_bytes", ctypes.c_size_t),
+                ("operator_hits", ctypes.c_longlong), ("operator_misses", ctypes.c_longlong),
+                ("operator_cache_bytes", ctypes.c_size_t)]
 
 
 _sig = {
@@ -86,6 +88,8 @@ _sig = {
     "vie_copy": (_i, [_vp, _vp, _vp, ctypes.c_longlong]),
     "vie_autotune": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _dp]),
     "vie_set_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(_i)]),
+    "vie_fft_size": (_i, [_vp, ctypes.POINTER(_i)]),
+    "vie_share_grid": (_i, [_vp, _vp]),
     "vie_profile": (_i, [_vp, _i]),
     "vie_profile_read": (_i, [_vp, _i, _dp, ctypes.POINTER(_i), _dp]),
     "vie_server_create": (_i, [ctypes.POINTER(_vp), _i, ctypes.c_size_t, _i]),
@@ -94,6 +98,7 @@ _sig = {
     "vie_server_wait": (_i, [_vp]),
     "vie_server_stats": (_i, [_vp, ctypes.c_longlong, ctypes.POINTER(ServingStats)]),
     "vie_server_destroy": (None, [_vp]),
+    "vie_server_set_operator_cache": (_i, [_vp, ctypes.c_size_t]),
     "vie_unknowns_bytes_paper": (ctypes.c_size_t, [_i, _i, _i]),
     "vie_footprint_bytes": (_i, [_i, _i, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_size_t)]),
 }
@@ -189,6 +194,18 @@ class Context:
         _check(_lib.vie_set_grid(self._h, nx, ny, nz, float(Delta[0]), float(Delta[1]), float(Delta[2]),
                                  float(freq_hz), fs))
         self.N = (nx, ny, nz)
+
+    def share_grid(self, other):
+        """Use other's grid and operator (shared device buffers)."""
+        _check(_lib.vie_share_grid(self._h, other._h))
+        self.N = other.N
+
+    @property
+    def fft_size(self):
+        """(M_x, M_y, M_z) of the padded FFT grid."""
+        m = (ctypes.c_int * 3)()
+        _check(_lib.vie_fft_size(self._h, m))
+        return tuple(m)
 
     @property
     def V(self):
@@ -376,6 +393,10 @@ class Server:
 
     def wait(self):
         _check(_lib.vie_server_wait(self._h))
+
+    def set_operator_cache(self, nbytes):
+        """Device bytes kept for operators of recently used grids (0: off)."""
+        _check(_lib.vie_server_set_operator_cache(self._h, int(nbytes)))
 
     def stats(self, first_id=0):
         st = ServingStats()

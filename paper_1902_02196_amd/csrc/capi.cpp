@@ -46,15 +46,8 @@ Ctx::~Ctx() {
 }
 
 void Ctx::free_grid() {
-    for (auto& a : ax) {
-        if (a.tw128) (void)hipFree(a.tw128);
-        if (a.tw64) (void)hipFree(a.tw64);
-        a.tw128 = nullptr;
-        a.tw64 = nullptr;
-    }
-    if (T) (void)hipFree(T);
-    if (U128) (void)hipFree(U128);
-    if (U64) (void)hipFree(U64);
+    op.reset();   // frees the operator unless another context shares it
+    for (auto& a : ax) a = FftAxis{};
     T = nullptr;
     U128 = nullptr;
     U64 = nullptr;
@@ -154,20 +147,28 @@ int vie_set_grid(vie_ctx* ctx, int nx, int ny, int nz, double dx, double dy, dou
         c.k0 = c.omega * std::sqrt(kMu0 * kEps0);
         c.V = (long long)nx * ny * nz;
         c.Osz = (long long)c.O[0] * c.O[1] * c.O[2];
+        auto opd = std::make_shared<OperatorData>();
         for (int i = 0; i < 3; ++i) {
-            c.ax[i].plan = make_plan(M[i]);
+            opd->ax[i].plan = make_plan(M[i]);
             std::vector<double2> tw;
             make_twiddles(M[i], tw);
             std::vector<float2> tw32(M[i]);
             for (int k = 0; k < M[i]; ++k) tw32[k] = make_float2((float)tw[k].x, (float)tw[k].y);
-            VIE_HIP(hipMalloc(&c.ax[i].tw128, M[i] * sizeof(double2)));
-            VIE_HIP(hipMalloc(&c.ax[i].tw64, M[i] * sizeof(float2)));
-            VIE_HIP(hipMemcpy(c.ax[i].tw128, tw.data(), M[i] * sizeof(double2), hipMemcpyHostToDevice));
-            VIE_HIP(hipMemcpy(c.ax[i].tw64, tw32.data(), M[i] * sizeof(float2), hipMemcpyHostToDevice));
+            VIE_HIP(hipMalloc(&opd->ax[i].tw128, M[i] * sizeof(double2)));
+            VIE_HIP(hipMalloc(&opd->ax[i].tw64, M[i] * sizeof(float2)));
+            VIE_HIP(hipMemcpy(opd->ax[i].tw128, tw.data(), M[i] * sizeof(double2), hipMemcpyHostToDevice));
+            VIE_HIP(hipMemcpy(opd->ax[i].tw64, tw32.data(), M[i] * sizeof(float2), hipMemcpyHostToDevice));
+            opd->bytes += M[i] * (sizeof(double2) + sizeof(float2));
         }
-        VIE_HIP(hipMalloc(&c.T, 60 * c.V * sizeof(double2)));
-        VIE_HIP(hipMalloc(&c.U128, 60 * c.Osz * sizeof(double2)));
-        VIE_HIP(hipMalloc(&c.U64, 60 * c.Osz * sizeof(float2)));
+        VIE_HIP(hipMalloc(&opd->T, 60 * c.V * sizeof(double2)));
+        VIE_HIP(hipMalloc(&opd->U128, 60 * c.Osz * sizeof(double2)));
+        VIE_HIP(hipMalloc(&opd->U64, 60 * c.Osz * sizeof(float2)));
+        opd->bytes += 60 * c.V * sizeof(double2) + 60 * c.Osz * (sizeof(double2) + sizeof(float2));
+        c.op = opd;
+        for (int i = 0; i < 3; ++i) c.ax[i] = opd->ax[i];
+        c.T = opd->T;
+        c.U128 = opd->U128;
+        c.U64 = opd->U64;
         AssemblyTables tab = build_assembly_tables(c.D, c.k0);
         assemble_blocks(c.T, tab, nx, ny, nz, c.stream);
         c.has_grid = true;
@@ -181,12 +182,48 @@ int vie_set_grid(vie_ctx* ctx, int nx, int ny, int nz, double dx, double dy, dou
     });
 }
 
+int vie_share_grid(vie_ctx* dst, const vie_ctx* src) {
+    return guarded([&] {
+        check_ctx(dst);
+        VIE_REQUIRE(src != nullptr && src != dst, VIE_EINVAL, "bad source context");
+        const Ctx& s = src->c;
+        Ctx& c = dst->c;
+        VIE_REQUIRE(s.has_grid, VIE_ESTATE, "source context has no grid");
+        VIE_REQUIRE(s.device == c.device, VIE_EINVAL, "contexts on different devices");
+        set_device(c);
+        if (s.stream) VIE_HIP(hipStreamSynchronize(s.stream));   // operator complete
+        if (c.stream) VIE_HIP(hipStreamSynchronize(c.stream));
+        std::shared_ptr<OperatorData> keep = s.op;                // src may equal a context sharing dst's op
+        c.free_grid();
+        c.free_contrast();
+        for (int i = 0; i < 3; ++i) {
+            c.N[i] = s.N[i];
+            c.M[i] = s.M[i];
+            c.O[i] = s.O[i];
+            c.D[i] = s.D[i];
+            c.ax[i] = s.ax[i];
+        }
+        c.freq = s.freq;
+        c.omega = s.omega;
+        c.k0 = s.k0;
+        c.V = s.V;
+        c.Osz = s.Osz;
+        c.op = keep;
+        c.T = s.T;
+        c.U128 = s.U128;
+        c.U64 = s.U64;
+        c.tune = s.tune;
+        c.has_grid = true;
+    });
+}
+
 int vie_set_toeplitz(vie_ctx* ctx, const double* T_host) {
     return guarded([&] {
         check_ctx(ctx);
         Ctx& c = ctx->c;
         set_device(c);
         VIE_REQUIRE(c.has_grid, VIE_ESTATE, "vie_set_toeplitz before vie_set_grid");
+        VIE_REQUIRE(c.op.use_count() == 1, VIE_ESTATE, "the operator is shared with another context");
         VIE_REQUIRE(T_host != nullptr, VIE_EINVAL, "T_host is null");
         VIE_HIP(hipMemcpyAsync(c.T, T_host, 60 * c.V * sizeof(double2), hipMemcpyHostToDevice, c.stream));
         const long long Mt = (long long)c.M[0] * c.M[1] * c.M[2];
@@ -433,6 +470,16 @@ int vie_autotune(vie_ctx* ctx, int precision, int nrhs, int* choice, double* bes
             choice[2] = t.tile_z;
             choice[3] = t.tile_y;
         }
+    });
+}
+
+int vie_fft_size(vie_ctx* ctx, int* m3) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        VIE_REQUIRE(c.has_grid, VIE_ESTATE, "no grid set");
+        VIE_REQUIRE(m3 != nullptr, VIE_EINVAL, "null output");
+        for (int i = 0; i < 3; ++i) m3[i] = c.M[i];
     });
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <map>
+#include <memory>
 #include <vector>
 
 #include "vie.h"
@@ -16,6 +17,26 @@ struct FftAxis {
     FftPlan plan{};
     double2* tw128 = nullptr;
     float2* tw64 = nullptr;
+};
+
+// Device operator of one grid: block tensors, octant spectra and twiddles.
+// Contexts on the same grid (extents, voxel size, frequency, fft size) may
+// share one read-only copy; the last owner frees it.
+struct OperatorData {
+    FftAxis ax[3];
+    double2* T = nullptr;
+    double2* U128 = nullptr;
+    float2* U64 = nullptr;
+    size_t bytes = 0;
+    ~OperatorData() {
+        for (auto& a : ax) {
+            if (a.tw128) (void)hipFree(a.tw128);
+            if (a.tw64) (void)hipFree(a.tw64);
+        }
+        if (T) (void)hipFree(T);
+        if (U128) (void)hipFree(U128);
+        if (U64) (void)hipFree(U64);
+    }
 };
 
 // device buffer that only grows
@@ -126,6 +147,7 @@ struct Ctx {
     long long V = 0, Osz = 0;
     FftAxis ax[3];
 
+    std::shared_ptr<OperatorData> op;   // owner of the buffers below
     double2* T = nullptr;      // [60][V] unique block tensors, d >= 0
     double2* U128 = nullptr;   // [60][Osz] octant spectra
     float2* U64 = nullptr;

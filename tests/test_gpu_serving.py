@@ -67,13 +67,20 @@ def test_same_result_alone_and_in_mix(vie):
     reqs = _requests()
     alone = []
     srv = vie.Server(0, hbm_budget=8 << 30, max_slots=1)
+    cached = []
     for q in reqs:
         rid = _submit(srv, q)
         srv.wait()
         info, p, x = srv.result(rid)
         _check_done(info)
-        _say("alone %d: iters %d res %.2e p %s" % (rid, info["iterations"], info["rel_residual"], p))
+        _say("alone %d: iters %d res %.2e p %s cached %d" % (rid, info["iterations"], info["rel_residual"], p,
+                                                           info["operator_cached"]))
         alone.append((p.copy(), x.copy()))
+        cached.append(info["operator_cached"])
+    # the last request repeats the first one's grid: its operator is reused
+    assert cached == [0, 0, 0, 0, 1]
+    st = srv.stats()
+    assert st["operator_hits"] == 1 and st["operator_misses"] == 4 and st["operator_cache_bytes"] > 0
     srv.close()
 
     srv = vie.Server(0, hbm_budget=8 << 30, max_slots=4)
@@ -110,6 +117,30 @@ def test_served_solution_matches_oracle(vie):
     assert err < 1e-9
     pref = post.absorbed_power(xref, chi, D, f)
     assert abs(p[0] - pref) / abs(pref) < 1e-8
+
+
+def test_operator_cache_off_gives_same_result(vie):
+    """With the operator cache disabled every request assembles its own
+    operator, and the solution is bitwise the one obtained through the cache."""
+    reqs = _requests()
+    out = {}
+    for cache in (True, False):
+        srv = vie.Server(0, hbm_budget=4 << 30, max_slots=2)
+        if not cache:
+            srv.set_operator_cache(0)
+        ids = [_submit(srv, reqs[0]), _submit(srv, reqs[0])]
+        srv.wait()
+        res = [srv.result(i) for i in ids]
+        for info, _, _ in res:
+            _check_done(info)
+        st = srv.stats()
+        _say("cache %s: hits %d misses %d" % (cache, st["operator_hits"], st["operator_misses"]))
+        if not cache:
+            assert st["operator_hits"] == 0 and st["operator_cache_bytes"] == 0
+        out[cache] = [r[2].copy() for r in res]
+        srv.close()
+    for a, b in zip(out[True], out[False]):
+        assert np.array_equal(a, b)
 
 
 def test_admission_limits_and_errors(vie):
