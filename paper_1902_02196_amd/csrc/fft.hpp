@@ -129,6 +129,75 @@ __device__ __forceinline__ void dft16(C<R>* v) {
 }
 
 template <typename R, bool FWD, int RAD>
+__device__ __forceinline__ void dft_r(C<R>* v);
+
+// Length-4 DFT of (a0, a1, 0, 0): the zero half of a zero-padded input is
+// not added in.
+template <typename R, bool FWD>
+__device__ __forceinline__ void dft4z(C<R>& a0, C<R>& a1, C<R>& a2, C<R>& a3) {
+    const C<R> d13 = mul_mi<FWD>(a1);
+    const C<R> s = cadd(a0, a1), d = csub(a0, a1);
+    a2 = d;
+    a3 = csub(a0, d13);
+    a1 = cadd(a0, d13);
+    a0 = s;
+}
+
+// DFT of a length-RAD butterfly whose upper half of inputs is zero (the
+// first forward pass over zero-padded data); same outputs as dft_r.
+template <typename R, bool FWD, int RAD>
+__device__ __forceinline__ void dft_r_halfin(C<R>* v) {
+    if constexpr (RAD == 2) {
+        v[1] = v[0];
+    } else if constexpr (RAD == 4) {
+        dft4z<R, FWD>(v[0], v[1], v[2], v[3]);
+    } else if constexpr (RAD == 8) {
+        C<R> e0 = v[0], e1 = v[2], e2, e3;
+        C<R> o0 = v[1], o1 = v[3], o2, o3;
+        dft4z<R, FWD>(e0, e1, e2, e3);
+        dft4z<R, FWD>(o0, o1, o2, o3);
+        const R h = R(0.70710678118654752440);
+        C<R> w1o1 = FWD ? mk<R>(h * (o1.x + o1.y), h * (o1.y - o1.x)) : mk<R>(h * (o1.x - o1.y), h * (o1.y + o1.x));
+        C<R> w2o2 = mul_mi<FWD>(o2);
+        C<R> w3o3 = FWD ? mk<R>(h * (-o3.x + o3.y), h * (-o3.y - o3.x)) : mk<R>(h * (-o3.x - o3.y), h * (-o3.y + o3.x));
+        v[0] = cadd(e0, o0);
+        v[4] = csub(e0, o0);
+        v[1] = cadd(e1, w1o1);
+        v[5] = csub(e1, w1o1);
+        v[2] = cadd(e2, w2o2);
+        v[6] = csub(e2, w2o2);
+        v[3] = cadd(e3, w3o3);
+        v[7] = csub(e3, w3o3);
+    } else if constexpr (RAD == 16) {
+        // as dft16, whose first stage combines v[q], v[4+q], v[8+q], v[12+q]:
+        // the last two are zero
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dft4z<R, FWD>(v[q], v[4 + q], v[8 + q], v[12 + q]);
+        const R c1 = R(0.92387953251128675613), s1 = R(0.38268343236508977173);
+        const R c2 = R(0.70710678118654752440);
+        const R sg = FWD ? R(-1) : R(1);
+        const C<R> w[10] = {mk<R>(1, 0),  mk<R>(c1, sg * s1),  mk<R>(c2, sg * c2),  mk<R>(s1, sg * c1),
+                            mk<R>(0, sg), mk<R>(-s1, sg * c1), mk<R>(-c2, sg * c2), mk<R>(-c1, sg * s1),
+                            mk<R>(-1, 0), mk<R>(-c1, -sg * s1)};
+#pragma unroll
+        for (int q = 1; q < 4; ++q)
+#pragma unroll
+            for (int k1 = 1; k1 < 4; ++k1) v[q + 4 * k1] = cmul(v[q + 4 * k1], w[q * k1]);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) dft4<R, FWD>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+        C<R> t;
+        t = v[1]; v[1] = v[4]; v[4] = t;
+        t = v[2]; v[2] = v[8]; v[8] = t;
+        t = v[3]; v[3] = v[12]; v[12] = t;
+        t = v[6]; v[6] = v[9]; v[9] = t;
+        t = v[7]; v[7] = v[13]; v[13] = t;
+        t = v[11]; v[11] = v[14]; v[14] = t;
+    } else {
+        dft_r<R, FWD, RAD>(v);   // odd radices: no zero half
+    }
+}
+
+template <typename R, bool FWD, int RAD>
 __device__ __forceinline__ void dft_r(C<R>* v) {
     if constexpr (RAD == 2) dft2<R, FWD>(v[0], v[1]);
     else if constexpr (RAD == 3) dft3<R, FWD>(v);

@@ -24,8 +24,16 @@ __host__ __device__ constexpr int ct_radix(int n, int s) {
     return 0;
 }
 
-template <typename R, bool FWD, int N, int RAD, int NS, int NTHR, int MAXROWS>
+// HIN: the inputs of the upper half of each row are zero (a zero-padded
+// forward transform, first pass only): they are neither read nor added.
+// HOUT: only the lower half of each row is used afterwards (a cropped inverse
+// transform, last pass only): the upper half is neither stored nor, once the
+// compiler drops the dead arithmetic, computed.
+template <typename R, bool FWD, int N, int RAD, int NS, int NTHR, int MAXROWS, bool HIN = false,
+          bool HOUT = false>
 __device__ __forceinline__ void ct_pass(C<R>* buf, const C<R>* twl, int rows, int pitch, int tid) {
+    static_assert(!HIN || (NS == 1 && RAD % 2 == 0), "half-zero input only on an even first pass");
+    static_assert(!HOUT || (NS * RAD == N && RAD % 2 == 0), "half output only on an even last pass");
     constexpr int nb = N / RAD;
     constexpr int NB = (MAXROWS * nb + NTHR - 1) / NTHR;
     constexpr int twstep = N / (NS * RAD);
@@ -38,7 +46,7 @@ __device__ __forceinline__ void ct_pass(C<R>* buf, const C<R>* twl, int rows, in
             const int t = idx / nb, j = idx - t * nb;
             const int rb = t * pitch + j;
 #pragma unroll
-            for (int i = 0; i < RAD; ++i) v[q][i] = buf[lds_pad(rb + i * nb)];
+            for (int i = 0; i < (HIN ? RAD / 2 : RAD); ++i) v[q][i] = buf[lds_pad(rb + i * nb)];
         }
     }
     __syncthreads();
@@ -56,21 +64,28 @@ __device__ __forceinline__ void ct_pass(C<R>* buf, const C<R>* twl, int rows, in
                     v[q][i] = cmul(v[q][i], w);
                 }
             }
-            dft_r<R, FWD, RAD>(v[q]);
+            if constexpr (HIN) dft_r_halfin<R, FWD, RAD>(v[q]);
+            else dft_r<R, FWD, RAD>(v[q]);
             const int rb = t * pitch + (j - k) * RAD + k;
 #pragma unroll
-            for (int i = 0; i < RAD; ++i) buf[lds_pad(rb + i * NS)] = v[q][i];
+            for (int i = 0; i < (HOUT ? RAD / 2 : RAD); ++i) buf[lds_pad(rb + i * NS)] = v[q][i];
         }
     }
     __syncthreads();
 }
 
-template <typename R, bool FWD, int N, int S, int NS, int NTHR, int MAXROWS>
+// HIN: rows are zero beyond N / 2 (zero-padded forward transform); the
+// first pass then skips the zero half when its radix is even
+// HOUT: only positions below N / 2 are read after the transform (cropped
+// inverse); the last pass then stores the lower half when its radix is even
+template <typename R, bool FWD, int N, int S, int NS, int NTHR, int MAXROWS, bool HIN = false, bool HOUT = false>
 __device__ __forceinline__ void ct_passes(C<R>* buf, const C<R>* twl, int rows, int pitch, int tid) {
     constexpr int r = ct_radix(N, S);
     if constexpr (r > 0) {
-        ct_pass<R, FWD, N, r, NS, NTHR, MAXROWS>(buf, twl, rows, pitch, tid);
-        ct_passes<R, FWD, N, S + 1, NS * r, NTHR, MAXROWS>(buf, twl, rows, pitch, tid);
+        constexpr bool hin = HIN && S == 0 && r % 2 == 0;
+        constexpr bool hout = HOUT && ct_radix(N, S + 1) == 0 && r % 2 == 0;
+        ct_pass<R, FWD, N, r, NS, NTHR, MAXROWS, hin, hout>(buf, twl, rows, pitch, tid);
+        ct_passes<R, FWD, N, S + 1, NS * r, NTHR, MAXROWS, false, HOUT>(buf, twl, rows, pitch, tid);
     }
 }
 

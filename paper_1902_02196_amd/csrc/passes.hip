@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(p3_threads<R>()) k_p3_ct(C<R>* __restrict__ A,
             if (k >= p.Nx) buf[lds_pad(e)] = mk<R>(0, 0);
         }
         __syncthreads();
-        ct_passes<R, true, N, 0, 1, NT, MAXROWS>(buf, twl, rows, N, tid);
+        ct_passes<R, true, N, 0, 1, NT, MAXROWS, true>(buf, twl, rows, N, tid);   // Nx <= N / 2
         {
             const int ncol = G * N;
             const bool act = tid < SPLIT * ncol;
@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(p3_threads<R>()) k_p3_ct(C<R>* __restrict__ A,
             }
         }
         __syncthreads();
-        ct_passes<R, false, N, 0, 1, NT, MAXROWS>(buf, twl, rows, N, tid);
+        ct_passes<R, false, N, 0, 1, NT, MAXROWS, false, true>(buf, twl, rows, N, tid);   // crop to Nx
         for (int b0 = 0; b0 < tot; b0 += 8 * NT) {
             C<R> v[8];
 #pragma unroll
@@ -452,7 +452,7 @@ __global__ void __launch_bounds__(kP3SmallThreads) k_p3_small(C<R>* __restrict__
     for (int m = tid; m < N; m += NT) twl[m] = tw[m];
     rows_to_lds<R, N, NT>(buf, 12, p.Nx, rowp);
     __syncthreads();
-    ct_passes<R, true, N, 0, 1, NT, 12>(buf, twl, 12, N, tid);
+    ct_passes<R, true, N, 0, 1, NT, 12, true>(buf, twl, 12, N, tid);   // Nx <= N / 2
     const C<R>* Ur = U + (long long)row * 60 * OX;
     if constexpr (SPLIT == 1) {
         for (int xi = tid; xi < N; xi += NT) {
@@ -517,7 +517,7 @@ __global__ void __launch_bounds__(kP3SmallThreads) k_p3_small(C<R>* __restrict__
         }
     }
     __syncthreads();
-    ct_passes<R, false, N, 0, 1, NT, 12>(buf, twl, 12, N, tid);
+    ct_passes<R, false, N, 0, 1, NT, 12, false, true>(buf, twl, 12, N, tid);   // crop to Nx
     lds_to_rows<R, N, NT>(buf, 12, p.Nx, rowp);
 }
 
@@ -572,7 +572,7 @@ __global__ void __launch_bounds__(kP3SmallThreads) k_p3_pref(C<R>* __restrict__ 
     for (int m = tid; m < N; m += NT) twl[m] = tw[m];
     rows_to_lds<R, N, NT>(buf, 12, p.Nx, rowp);
     __syncthreads();
-    ct_passes<R, true, N, 0, 1, NT, 12>(buf, twl, 12, N, tid);
+    ct_passes<R, true, N, 0, 1, NT, 12, true>(buf, twl, 12, N, tid);   // Nx <= N / 2
 #pragma unroll
     for (int i = 0; i < UPT; ++i) {
         const int idx = tid + i * NT;
@@ -600,7 +600,7 @@ __global__ void __launch_bounds__(kP3SmallThreads) k_p3_pref(C<R>* __restrict__ 
         }
     }
     __syncthreads();
-    ct_passes<R, false, N, 0, 1, NT, 12>(buf, twl, 12, N, tid);
+    ct_passes<R, false, N, 0, 1, NT, 12, false, true>(buf, twl, 12, N, tid);   // crop to Nx
     lds_to_rows<R, N, NT>(buf, 12, p.Nx, rowp);
 }
 
@@ -666,7 +666,7 @@ __global__ void __launch_bounds__(kP3QuadThreads) k_p3_quad(C<R>* __restrict__ A
     for (int m = tid; m < N; m += NT) twl[m] = tw[m];
     rows_to_lds<R, N, NT>(buf, nrows, p.Nx, rowp);
     __syncthreads();
-    ct_passes<R, true, N, 0, 1, NT, 48>(buf, twl, nrows, N, tid);
+    ct_passes<R, true, N, 0, 1, NT, 48, true>(buf, twl, nrows, N, tid);   // Nx <= N / 2
     {
         const C<R>* Ur = U + (long long)row * 60 * OX;
         for (int w = tid; w < nz_sib * N; w += NT) {
@@ -719,7 +719,7 @@ __global__ void __launch_bounds__(kP3QuadThreads) k_p3_quad(C<R>* __restrict__ A
         }
     }
     __syncthreads();
-    ct_passes<R, false, N, 0, 1, NT, 48>(buf, twl, nrows, N, tid);
+    ct_passes<R, false, N, 0, 1, NT, 48, false, true>(buf, twl, nrows, N, tid);   // crop to Nx
     lds_to_rows<R, N, NT>(buf, nrows, p.Nx, rowp);
 }
 
@@ -887,6 +887,8 @@ void launch_strided(bool fwd, const C<R>* in, C<R>* out, const StridedPass& p, l
 
 template <typename R>
 void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
+    // the compiled kernels skip the zero upper half of each padded row
+    VIE_REQUIRE(2 * p.Nx <= p.plan.n, -1, "x pass: fft length below 2 Nx");
     switch (p.plan.n) {
 #define CASE(n_)                                                                          \
     case n_:                                                                             \

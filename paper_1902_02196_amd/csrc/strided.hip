@@ -39,7 +39,9 @@ __global__ void __launch_bounds__(256) k_strided_ct(const C<R>* in, C<R>* out, S
         }
     }
     __syncthreads();
-    ct_passes<R, FWD, N, 0, 1, NT, T>(buf, twl, T, N, tid);
+    if (FWD && 2 * p.n_in <= N) ct_passes<R, FWD, N, 0, 1, NT, T, FWD, false>(buf, twl, T, N, tid);   // zero-padded
+    else if (!FWD && 2 * p.n_out <= N) ct_passes<R, FWD, N, 0, 1, NT, T, false, !FWD>(buf, twl, T, N, tid);   // cropped
+    else ct_passes<R, FWD, N, 0, 1, NT, T>(buf, twl, T, N, tid);
     const long long obase = rr * p.out_s1 + cc * p.out_sc;
     C<R>* dst = out + obase + o2 * p.out_s2 + t0;
     const int l = cc & 3;
