@@ -73,7 +73,7 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     p1.out_sk = pl1;
     const double bV = (double)B * V * es, bA1 = (double)B * Mz * Ny * Nx * es, bA2 = (double)B * Mz * My * Nx * es;
     {
-        ProfScope ps(c.prof, s, VIE_K_FFT_Z_FWD, bV + bA1);
+        KernelTiming kt(c.prof, VIE_K_FFT_Z_FWD, bV + bA1);
         launch_strided<R>(true, x, A1, p1, Ny, B, twid<R>(c.ax[2]), nullptr, s);
     }
 
@@ -94,7 +94,7 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     p2.out_s2 = pl2;
     p2.out_sk = row;
     {
-        ProfScope ps(c.prof, s, VIE_K_FFT_Y_FWD, bA1 + bA2);
+        KernelTiming kt(c.prof, VIE_K_FFT_Y_FWD, bA1 + bA2);
         launch_strided<R>(true, A1, A2, p2, Mz, B, twid<R>(c.ax[1]), nullptr, s);
     }
 
@@ -146,7 +146,7 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
         p3.magic_ox = magic_for((unsigned)c.O[0]);
     }
     {
-        ProfScope ps(c.prof, s, VIE_K_BLOCK, 2 * bA2 + 60.0 * c.Osz * es);
+        KernelTiming kt(c.prof, VIE_K_BLOCK, 2 * bA2 + 60.0 * c.Osz * es);
         launch_p3<R>(A2, opspec<R>(c), p3, twid<R>(c.ax[0]), s);
     }
 
@@ -163,7 +163,7 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     p4.out_s2 = pl1;
     p4.out_sk = row;
     {
-        ProfScope ps(c.prof, s, VIE_K_FFT_Y_INV, bA2 + bA1);
+        KernelTiming kt(c.prof, VIE_K_FFT_Y_INV, bA2 + bA1);
         launch_strided<R>(false, A2, A1, p4, Mz, B, twid<R>(c.ax[1]), nullptr, s);
     }
 
@@ -233,7 +233,7 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
         if (ep.rhs) extra += bV;
         if (ep.a) extra += (double)V * es;
         if (ep.b) extra += (double)V * es;
-        ProfScope ps(c.prof, s, VIE_K_FFT_Z_INV, bA1 + bV + extra);
+        KernelTiming kt(c.prof, VIE_K_FFT_Z_INV, bA1 + bV + extra);
         launch_strided<R>(false, A1, y, p5, Ny, B, twid<R>(c.ax[2]), &ep, s);
     }
 }

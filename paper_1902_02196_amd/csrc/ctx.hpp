@@ -125,6 +125,32 @@ struct ProfScope {
     }
 };
 
+// records one kernel launch of a class by its own dispatch timestamps (the
+// launch must go through timed_launch) when profiling samples it
+struct KernelTiming {
+    Profiler& p;
+    int kind;
+    double bytes;
+    hipEvent_t a = nullptr, b = nullptr;
+    KernelTiming(Profiler& p_, int k, double by) : p(p_), kind(k), bytes(by) {
+        if (p.on && p.sample(k)) {
+            a = p.take();
+            b = p.take();
+            g_launch_timing = LaunchTiming{a, b};
+        }
+    }
+    ~KernelTiming() {
+        if (!a) return;
+        if (g_launch_timing.start == a) {   // no launch took the events (an error came first)
+            g_launch_timing = LaunchTiming{};
+            p.pool.push_back(a);
+            p.pool.push_back(b);
+            return;
+        }
+        p.recs.push_back(Profiler::Rec{kind, a, b, bytes});
+    }
+};
+
 // launch shapes of the operator product, chosen per (precision, nrhs) by
 // the autotuner; zeros mean the built-in defaults
 struct Tune {

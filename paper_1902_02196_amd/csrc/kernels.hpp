@@ -1,10 +1,28 @@
 // Host-side launchers of the device kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "assembly.hpp"
 #include "passes.hpp"
 
 namespace vie {
+
+// Start / stop events for the next kernel launch of the operator passes:
+// hipExtLaunchKernelGGL stamps them from the kernel's own dispatch, so the
+// time between them is the kernel's duration without event packets around
+// it.  Set by the launch profiler, consumed (and cleared) by one launch.
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchTiming g_launch_timing;
+
+template <typename F, typename... Args>
+inline void timed_launch(F kernel, const dim3& grid, const dim3& block, unsigned lds, hipStream_t s, Args... args) {
+    const LaunchTiming t = g_launch_timing;
+    g_launch_timing = LaunchTiming{};
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, s, t.start, t.stop, 0, args...);
+}
 
 // passes.hip
 template <typename R>

@@ -8,6 +8,8 @@
 
 namespace vie {
 
+thread_local LaunchTiming g_launch_timing;
+
 // ---------------------------------------------------------------------------
 // strided pass
 // ---------------------------------------------------------------------------
@@ -747,7 +749,7 @@ static void launch_p3_small_n(C<R>* A, const C<R>* U, const P3Params& p, const C
     const long long rows8 = ((long long)p.Oy * p.Oz + 7) / 8 * 8;
     const long long nblk = rows8 * 4LL * p.nrhs;
     VIE_REQUIRE(nblk < (1LL << 31), -1, "x pass: too many workgroups");
-    hipLaunchKernelGGL((k_p3_small<R, N, SPLIT>), dim3((unsigned)nblk), dim3(kP3SmallThreads), lds, s, A, U, p, tw);
+    timed_launch(k_p3_small<R, N, SPLIT>, dim3((unsigned)nblk), dim3(kP3SmallThreads), (unsigned)lds, s, A, U, p, tw);
     VIE_HIP(hipGetLastError());
 }
 
@@ -763,7 +765,7 @@ static void launch_p3_quad_n(C<R>* A, const C<R>* U, const P3Params& p, const C<
         (void)hipFuncSetAttribute((const void*)k_p3_quad<R, N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)hipGetLastError();
     });
-    hipLaunchKernelGGL((k_p3_quad<R, N>), dim3((unsigned)nblk), dim3(kP3QuadThreads), lds, s, A, U, p, tw);
+    timed_launch(k_p3_quad<R, N>, dim3((unsigned)nblk), dim3(kP3QuadThreads), (unsigned)lds, s, A, U, p, tw);
     VIE_HIP(hipGetLastError());
 }
 
@@ -780,7 +782,7 @@ static void launch_p3_pref(C<R>* A, const C<R>* U, const P3Params& p, const C<R>
                                       (int)lds);
             (void)hipGetLastError();
         });
-        hipLaunchKernelGGL((k_p3_pref<R, N>), dim3((unsigned)nblk), dim3(kP3SmallThreads), lds, s, A, U, p, tw);
+        timed_launch(k_p3_pref<R, N>, dim3((unsigned)nblk), dim3(kP3SmallThreads), (unsigned)lds, s, A, U, p, tw);
         VIE_HIP(hipGetLastError());
     } else {
         throw Error(-1, "x pass: prefetching variant needs an fft length <= 128");
@@ -817,7 +819,7 @@ static void launch_p3_ct_n(C<R>* A, const C<R>* U, const P3Params& p, const C<R>
         (void)hipGetLastError();
     });
     VIE_REQUIRE(p.sib_blocks == 1 || p.sib_blocks == 2 || p.sib_blocks == 4, -1, "x pass: bad sibling split");
-    hipLaunchKernelGGL((k_p3_ct<R, N>), dim3(p.Oy * p.Oz * p.sib_blocks), dim3(NT), lds, s, A, U, p, tw);
+    timed_launch(k_p3_ct<R, N>, dim3(p.Oy * p.Oz * p.sib_blocks), dim3(NT), (unsigned)lds, s, A, U, p, tw);
     VIE_HIP(hipGetLastError());
 }
 
@@ -860,7 +862,7 @@ static void launch_strided_t(const C<R>* in, C<R>* out, const StridedPass& p, lo
                                   96 * 1024);
         (void)hipGetLastError();
     });
-    hipLaunchKernelGGL((k_strided<R, FWD, EPI>), grid, dim3(256), lds, s, in, out, p, tw, ep);
+    timed_launch(k_strided<R, FWD, EPI>, grid, dim3(256), (unsigned)lds, s, in, out, p, tw, ep);
     VIE_HIP(hipGetLastError());
 }
 
@@ -913,8 +915,8 @@ void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStr
         (void)hipFuncSetAttribute((const void*)k_p3<R, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
         (void)hipGetLastError();
     });
-    if (split4) hipLaunchKernelGGL((k_p3<R, 4>), dim3(p.Oy * p.Oz), dim3(nt), lds, s, A, U, p, tw);
-    else hipLaunchKernelGGL((k_p3<R, 2>), dim3(p.Oy * p.Oz), dim3(nt), lds, s, A, U, p, tw);
+    if (split4) timed_launch(k_p3<R, 4>, dim3(p.Oy * p.Oz), dim3(nt), (unsigned)lds, s, A, U, p, tw);
+    else timed_launch(k_p3<R, 2>, dim3(p.Oy * p.Oz), dim3(nt), (unsigned)lds, s, A, U, p, tw);
     VIE_HIP(hipGetLastError());
 }
 

@@ -81,7 +81,7 @@ static void launch_strided_ct_nt(const C<R>* in, C<R>* out, const StridedPass& p
         (void)hipGetLastError();
     });
     dim3 grid((p.n_inner + T - 1) / T, (unsigned)n_o2, (unsigned)n_o1);
-    hipLaunchKernelGGL((k_strided_ct<R, FWD, EPI, N, T>), grid, dim3(256), lds, s, in, out, p, tw, ep);
+    timed_launch(k_strided_ct<R, FWD, EPI, N, T>, grid, dim3(256), (unsigned)lds, s, in, out, p, tw, ep);
     VIE_HIP(hipGetLastError());
 }
 
