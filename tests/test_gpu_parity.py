@@ -295,3 +295,26 @@ def test_every_launch_shape_matches_oracle(vie, torch, N):
     _say("  %d shapes checked" % ran)
     assert ran >= 8
 
+
+def test_shared_grid_matches_own_assembly(vie, torch):
+    """A context sharing another's operator (vie_share_grid) computes the same
+    products bitwise as one that assembled its own, keeps working after the
+    source context is gone, and refuses to overwrite the shared blocks."""
+    N, D = (6, 5, 7), (0.005, 0.004, 0.006)
+    a = _ctx(vie, torch, N, D)
+    b = vie.Context(0)
+    b.share_grid(a)
+    assert b.fft_size == a.fft_size
+    own = _ctx(vie, torch, N, D)
+    e, s = vi.ellipsoid_phantom(N, D, 21)
+    for c in (b, own):
+        c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    x = torch.from_numpy(vec_to_lib(vi.complex_normal(22, (12,) + N))[None]).cuda()
+    yb, yo = torch.empty_like(x), torch.empty_like(x)
+    with pytest.raises(vie.VieError):
+        b.set_toeplitz(np.zeros((60, N[2], N[1], N[0]), dtype=np.complex128))
+    a.close()
+    b.apply(x, yb, op=vie.OP_PREC)
+    own.apply(x, yo, op=vie.OP_PREC)
+    assert torch.equal(yb, yo)
+

@@ -143,6 +143,26 @@ def test_operator_cache_off_gives_same_result(vie):
         assert np.array_equal(a, b)
 
 
+def test_operator_cache_eviction(vie):
+    """With room for one operator only, alternating grids evict each other
+    (no hits); with room for both, the repeats hit."""
+    reqs = _requests()
+    a, b = reqs[0], reqs[3]   # (4,4,4) and (5,7,6) grids
+    for cap, want_hits in ((900 << 10, 0), (256 << 20, 2)):   # operators of 242016 and 746832 bytes
+        srv = vie.Server(0, hbm_budget=8 << 30, max_slots=1)
+        srv.set_operator_cache(cap)
+        for q in (a, b, a, b):
+            rid = _submit(srv, q)
+            srv.wait()
+            _check_done(srv.poll(rid))
+        st = srv.stats()
+        _say("cache %d B: hits %d misses %d bytes %d" % (cap, st["operator_hits"], st["operator_misses"],
+                                                       st["operator_cache_bytes"]))
+        assert st["operator_hits"] == want_hits
+        assert st["operator_cache_bytes"] <= cap
+        srv.close()
+
+
 def test_admission_limits_and_errors(vie):
     N, D = (6, 6, 6), (0.005,) * 3
     e, s = vi.sphere(N, D, 0.012, 50.0, 0.7)
