@@ -7,7 +7,7 @@
 namespace vie {
 
 constexpr int kTpb = 256;
-constexpr int kGroup = 16;  // basis vectors per sweep of the dot kernel
+constexpr int kGroup = 8;   // basis vectors per sweep of the dot kernel
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -92,14 +92,14 @@ __global__ void __launch_bounds__(kTpb) k_multidot(double2* __restrict__ partial
     const T* V = reinterpret_cast<const T*>(Vb + r * rsv);
     const T* wr = reinterpret_cast<const T*>(w + r * rsw);
     const long long nu = n / U::per, ldu = ldv / U::per;
+    static_assert(kGroup == 8, "the remainder cases below cover groups of 8");
     int i0 = 0;
     for (; i0 + kGroup <= nvec; i0 += kGroup) dot_group<R, kGroup>(partial, V, wr, ldu, nu, i0, nvec, r, red);
     switch (nvec - i0) {
 #define VIE_DOT_REM(g_) \
     case g_: dot_group<R, g_>(partial, V, wr, ldu, nu, i0, nvec, r, red); break;
         VIE_DOT_REM(1) VIE_DOT_REM(2) VIE_DOT_REM(3) VIE_DOT_REM(4) VIE_DOT_REM(5) VIE_DOT_REM(6)
-        VIE_DOT_REM(7) VIE_DOT_REM(8) VIE_DOT_REM(9) VIE_DOT_REM(10) VIE_DOT_REM(11) VIE_DOT_REM(12)
-        VIE_DOT_REM(13) VIE_DOT_REM(14) VIE_DOT_REM(15)
+        VIE_DOT_REM(7)
 #undef VIE_DOT_REM
         default: break;
     }

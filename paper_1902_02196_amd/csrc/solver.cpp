@@ -172,11 +172,11 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
             apply_op<R>(c, OP_PREC, na, vj, w, nullptr);
             const int nvec = j + 1;
             // Gram-Schmidt, per pass: the dot kernel reads the j + 1 basis
-            // vectors and w (w once per group of 16 basis vectors); the
+            // vectors and w (w once per group of 8 basis vectors); the
             // update reads them again and writes w; normalising reads and
             // writes w once more
             const double vb = (double)na * n * sizeof(C<R>);
-            const double dot_bytes = vb * (nvec + (nvec + 15) / 16);
+            const double dot_bytes = vb * (nvec + (nvec + 7) / 8);
             const double upd_bytes = vb * (nvec + 2);
             for (int pass = 0; pass < (o.reorth ? 2 : 1); ++pass) {
                 double2* hp = pass ? L.h2 : L.h1;
