@@ -200,7 +200,8 @@ def serving_main(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 (FP64 refinement)",
+        "dtype": "c64",
+        "refinement": "FP64 residuals, updates, inner products and Givens",
         "data": "synthetic",
         "config": {"workload": "serving: %d requests, Poisson arrivals at %.0f req/s, edge in %s voxels at %.0f mm, "
                                "1-%d dipoles, %s MHz, 6-class ellipsoid phantoms, GMRES(%d) to 1e-6, "
@@ -417,7 +418,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 (FP64 refinement)",
+        "dtype": "c64",
+        "refinement": "FP64 residuals, updates, inner products and Givens",
         "data": "synthetic",
         "config": {"workload": "%s: %dx%dx%d voxels at %.0f mm, %.0f MHz, %s, %s, "
                                "GMRES(%d) to 1e-6, complex64 + FP64 refinement"
