@@ -318,3 +318,37 @@ def test_shared_grid_matches_own_assembly(vie, torch):
     own.apply(x, yo, op=vie.OP_PREC)
     assert torch.equal(yb, yo)
 
+
+
+def test_degenerate_cases(vie, torch):
+    """Edge cases of the method: a single voxel (fft length 2, generic
+    kernels) against the oracle's direct sum; no contrast, where P^-1 A is the
+    identity and a zero right-hand side solves to zero at once; zero right-hand
+    side counts are refused."""
+    N, D = (1, 1, 1), (0.004, 0.005, 0.006)
+    T = _full_blocks(N, D)
+    c = _ctx(vie, torch, N, D, T)
+    assert c.fft_size == (2, 2, 2)
+    x = vi.complex_normal(51, (12,) + N)
+    ref = matvec.direct_N(T, x)
+    for dtype, tol in ((torch.complex128, 1e-12), (torch.complex64, 1e-6)):
+        xd = _to_dev(torch, x, dtype)
+        yd = torch.empty_like(xd)
+        c.apply(xd, yd, op=vie.OP_N)
+        assert relerr(_from_dev(yd), ref) < tol
+
+    N, D = (6, 5, 4), (0.005,) * 3
+    c = _ctx(vie, torch, N, D)
+    c.set_contrast(np.ones((N[2], N[1], N[0])), np.zeros((N[2], N[1], N[0])))   # air: chi = 0
+    x = torch.from_numpy(vec_to_lib(vi.complex_normal(52, (12,) + N))[None]).cuda()
+    y = torch.empty_like(x)
+    c.apply(x, y, op=vie.OP_PREC)
+    assert torch.equal(x, y)
+    et = torch.zeros_like(x)
+    xs = torch.full_like(x, 1.0)
+    code, st = c.solve(et, xs, mode=vie.SOLVE_FP32_IR)
+    assert code == vie.VIE_OK and st[0]["iterations"] == 0
+    assert not bool(xs.abs().max())
+    with pytest.raises(vie.VieError) as ei:
+        c.apply(x[:0], y[:0], op=vie.OP_PREC)
+    assert ei.value.code == vie.VIE_EINVAL
