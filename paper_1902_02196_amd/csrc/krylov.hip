@@ -7,6 +7,17 @@
 namespace vie {
 
 constexpr int kTpb = 256;
+
+// Basis vectors are streamed once per Gram-Schmidt pass and a whole basis is
+// larger than the caches, so their loads are marked non-temporal (streaming
+// cache policy); a 16-byte unit is loaded as four 32-bit words and bit-cast.
+typedef unsigned int vie_u4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ T stream_load(const T* p) {
+    static_assert(sizeof(T) == 16, "16-byte units");
+    const vie_u4 v = __builtin_nontemporal_load(reinterpret_cast<const vie_u4*>(p));
+    return __builtin_bit_cast(T, v);
+}
 constexpr int kGroup = 8;   // basis vectors per sweep of the dot kernel
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -53,7 +64,7 @@ __device__ __forceinline__ void dot_group(double2* __restrict__ partial, const t
         const T wu = wr[k];
         T vu[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) vu[g] = V[(i0 + g) * ldu + k];
+        for (int g = 0; g < G; ++g) vu[g] = stream_load(&V[(i0 + g) * ldu + k]);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
 #pragma unroll
@@ -153,7 +164,7 @@ __global__ void __launch_bounds__(kTpb) k_update(C<R>* __restrict__ w, const C<R
         for (; i + 8 <= nvec; i += 8) {
             T vu[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) vu[u] = V[(i + u) * ldu + k];
+            for (int u = 0; u < 8; ++u) vu[u] = stream_load(&V[(i + u) * ldu + k]);
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const double2 hi = hr[i + u];
@@ -166,7 +177,7 @@ __global__ void __launch_bounds__(kTpb) k_update(C<R>* __restrict__ w, const C<R
             }
         }
         for (; i < nvec; ++i) {
-            const T vu = V[i * ldu + k];
+            const T vu = stream_load(&V[i * ldu + k]);
             const double2 hi = hr[i];
 #pragma unroll
             for (int q = 0; q < U::per; ++q) {
