@@ -48,6 +48,21 @@ template <bool FWD, typename T> __host__ __device__ __forceinline__ T mul_mi(T a
     return r;
 }
 // acc += a * b
+// Load marked non-temporal (streaming cache policy) for data read once: it
+// keeps the caches, including the 256 MB Infinity Cache, for data that is
+// read again (the operator octant, the next pass's intermediates).
+template <typename T>
+__device__ __forceinline__ T stream_load(const T* p) {
+    static_assert(sizeof(T) == 8 || sizeof(T) == 16, "8- or 16-byte elements");
+    if constexpr (sizeof(T) == 8) {
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const u2*>(p)));
+    } else {
+        typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+        return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const u4*>(p)));
+    }
+}
+
 __host__ __device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
 __host__ __device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
 

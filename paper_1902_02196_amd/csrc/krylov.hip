@@ -9,15 +9,7 @@ namespace vie {
 constexpr int kTpb = 256;
 
 // Basis vectors are streamed once per Gram-Schmidt pass and a whole basis is
-// larger than the caches, so their loads are marked non-temporal (streaming
-// cache policy); a 16-byte unit is loaded as four 32-bit words and bit-cast.
-typedef unsigned int vie_u4 __attribute__((ext_vector_type(4)));
-template <typename T>
-__device__ __forceinline__ T stream_load(const T* p) {
-    static_assert(sizeof(T) == 16, "16-byte units");
-    const vie_u4 v = __builtin_nontemporal_load(reinterpret_cast<const vie_u4*>(p));
-    return __builtin_bit_cast(T, v);
-}
+// larger than the caches, so their loads are non-temporal (stream_load).
 constexpr int kGroup = 8;   // basis vectors per sweep of the dot kernel
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(256) k_strided(const C<R>* in, C<R>* out,
     for (int idx = tid; idx < n * p.tile; idx += nthr) {
         const int k = idx / p.tile, t = idx - k * p.tile;
         C<R> v = mk<R>(0, 0);
-        if (k < p.n_in && t < tw_n) v = src[k * p.in_sk + t];
+        if (k < p.n_in && t < tw_n) v = stream_load(&src[k * p.in_sk + t]);
         buf0[k * p.pitch + t] = v;
     }
     __syncthreads();

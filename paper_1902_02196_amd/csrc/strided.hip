@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(256) k_strided_ct(const C<R>* in, C<R>* out, S
         if (LN % NT == 0 || idx < LN) {
             const int k = idx / T, t = idx - k * T;
             C<R> v = mk<R>(0, 0);
-            if (k < p.n_in && t < tw_n) v = src[k * p.in_sk + t];
+            if (k < p.n_in && t < tw_n) v = stream_load(&src[k * p.in_sk + t]);   // last read of the input
             buf[lds_pad(t * N + k)] = v;
         }
     }
