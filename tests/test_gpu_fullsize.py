@@ -9,6 +9,8 @@
   reciprocal kernel): checked for random vectors at full size.
 * The preconditioned solves reach the requested residual, and the FP32 +
   refinement solution matches the FP64 one.
+* The 16^3 sphere is solved whole on both sides (device GMRES vs the
+  oracle's GMRES on its own FFT product) and compared element by element.
 
 Grids: 64 x 64 x 64 at 3 mm, 298 MHz (single right-hand side) and
 96 x 128 x 128 at 2 mm, 298 MHz with 16 right-hand sides in one batch.
@@ -20,6 +22,7 @@ import pytest
 
 import vie_inputs as vi
 from oracle import physics, toeplitz
+from tests.layout import relerr, vec_from_lib, vox_to_lib
 
 pytestmark = pytest.mark.gpu
 
@@ -156,3 +159,44 @@ def test_solves_at_full_size(vie, torch):
     _say("  fields IR vs FP64: %.3e, power %.3e" % (ferr, abs(p32 - p64) / abs(p64)))
     assert ferr < 1e-5
     assert abs(p32 - p64) / abs(p64) < 1e-5
+
+
+
+def test_sphere16_solution_matches_oracle(vie, torch):
+    """16^3 sphere (r = 3 cm, eps' 50, sigma 0.7 S/m, 5 mm, 298 MHz, plane
+    wave; 49k unknowns), the whole device path (incident field, right-hand
+    side, GMRES in both modes, absorbed power) against the oracle's own FP64
+    GMRES on its own blocks and FFT product, element by element; and the
+    oracle's absorbed power against the Mie series of the volume-equivalent
+    sphere, the discretisation check of the staircased body."""
+    from oracle import incident, matvec, mie, post, solve
+    N, D = (16, 16, 16), (0.005,) * 3
+    e, s = vi.sphere(N, D, 0.03, 50.0, 0.7)
+    tau, chi = physics.tau(e, s, F), physics.chi(e, s, F)
+    T = toeplitz.toeplitz_full(N, D, K)
+    Ch = matvec.circulant_spectrum(T, tuple(2 * n for n in N))
+    b = matvec.rhs_prec(incident.planewave_tested(N, D, K), tau, D, F)
+    xref, info = solve.gmres(lambda v: matvec.apply_prec(T, v, tau, D, Nx_fn=lambda _t, u: matvec.fft_N(Ch, u)),
+                             b, restart=50, tol=1e-11)
+    assert info["converged"]
+    p_ref = post.absorbed_power(xref, chi, D, F)
+    _say("  oracle GMRES: %d iterations, P_abs %.6e W" % (info["iters"], p_ref))
+    c = vie.Context(0)
+    c.set_grid(N, D, F)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    et = torch.empty(c.vec_shape(1), dtype=torch.complex128, device="cuda")
+    c.incident_planewave(et)
+    for mode in (vie.SOLVE_FP64, vie.SOLVE_FP32_IR):
+        x = torch.empty_like(et)
+        code, st = c.solve(et, x, mode=mode, tol=1e-10)
+        assert code == vie.VIE_OK and st[0]["converged"]
+        err = relerr(vec_from_lib(x[0].cpu().numpy()), xref)
+        p = c.absorbed_power(x)[0]
+        _say("  mode %d: %d iterations, solution vs oracle %.3e, P_abs vs oracle %.3e" % (
+            mode, st[0]["iterations"], err, abs(p - p_ref) / p_ref))
+        assert err < 1e-8
+        assert abs(p - p_ref) / p_ref < 1e-8
+    req = (np.count_nonzero(chi) * D[0] * D[1] * D[2] * 3 / (4 * np.pi)) ** (1 / 3)
+    pm = mie.absorbed_power(req, 50.0, 0.7, F)
+    _say("  oracle P_abs vs Mie (r_eq %.4f m): %.3e" % (req, abs(p_ref - pm) / pm))
+    assert abs(p_ref - pm) / pm < 0.02
