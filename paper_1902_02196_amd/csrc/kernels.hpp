@@ -81,12 +81,17 @@ void launch_power_density(double* p, const double2* e, const double* sigma, long
 template <typename R>
 void launch_multidot(double2* partial, const C<R>* Vb, long long ldv, int nvec, const C<R>* w, long long n,
                      long long rstride_v, long long rstride_w, int nrhs, int nblocks, hipStream_t s);
-void launch_reduce_partials(double2* out, const double2* partial, int nvec, int nblocks, int nrhs, hipStream_t s);
+// the basis is stored unnormalised, v_i = u_i * ivn[i] (ivn at stride ivn_ld
+// per right-hand side); jw names the vector the operator was applied to
+// (w = A u_jw), or jw < 0 for a second pass
+void launch_reduce_partials(double2* h, double2* coef, const double2* partial, int nvec, int nblocks, int nrhs,
+                            const double* ivn, long long ivn_ld, int jw, hipStream_t s);
 template <typename R>
-void launch_update(C<R>* w, const C<R>* Vb, long long ldv, int nvec, const double2* h, long long n,
-                   long long rstride_v, long long rstride_w, double* norm_partial, int nrhs, int nblocks,
-                   hipStream_t s);
-void launch_reduce_norm(double* out, const double* partial, int nblocks, int nrhs, hipStream_t s);
+void launch_update(C<R>* w, const C<R>* Vb, long long ldv, int nvec, const double2* coef, long long n,
+                   long long rstride_v, long long rstride_w, double* norm_partial, const double* ivn,
+                   long long ivn_ld, int jw, int nrhs, int nblocks, hipStream_t s);
+void launch_reduce_norm(double* out, const double* partial, int nblocks, int nrhs, hipStream_t s,
+                        double* inv = nullptr, long long inv_ld = 0);
 template <typename R>
 void launch_scale_into(C<R>* dst, const C<R>* src, const double* norms, long long n, long long rstride_dst,
                        long long rstride_src, int nrhs, hipStream_t s);

@@ -115,27 +115,45 @@ void launch_multidot(double2* partial, const C<R>* Vb, long long ldv, int nvec, 
     VIE_HIP(hipGetLastError());
 }
 
-__global__ void k_reduce_partials(double2* __restrict__ out, const double2* __restrict__ partial, int nblocks) {
-    // one wave per (r, i); fixed summation order
+// The basis is stored unnormalised: slot i holds u_i with v_i = u_i * ivn[i]
+// (ivn = 1 / ||u_i||, 0 for a zero vector).  From the partial sums of
+// conj(u_i) w this forms the Hessenberg entries h_i = conj(v_i) (sw w), with
+// sw = ivn[jw] (w = the operator applied to u_jw; jw < 0: sw = 1), and the
+// update coefficients c_i = h_i ivn[i], so that sw w - sum_i h_i v_i =
+// sw w - sum_i c_i u_i.
+__global__ void k_reduce_partials(double2* __restrict__ h, double2* __restrict__ coef,
+                                  const double2* __restrict__ partial, int nblocks, int nvec,
+                                  const double* __restrict__ ivn, long long ivn_ld, int jw) {
     const long long row = blockIdx.x;
+    const int r = (int)(row / nvec), i = (int)(row % nvec);
     const double2* p = partial + row * nblocks;
     double sr = 0, si = 0;
     for (int b = threadIdx.x; b < nblocks; b += 64) { sr += p[b].x; si += p[b].y; }
     sr = wave_sum(sr);
     si = wave_sum(si);
-    if (threadIdx.x == 0) out[row] = make_double2(sr, si);
+    if (threadIdx.x == 0) {
+        const double sw = jw >= 0 ? ivn[r * ivn_ld + jw] : 1.0;
+        const double iv = ivn[r * ivn_ld + i];
+        const double2 hv = make_double2(sr * sw * iv, si * sw * iv);
+        h[row] = hv;
+        coef[row] = make_double2(hv.x * iv, hv.y * iv);
+    }
 }
 
-void launch_reduce_partials(double2* out, const double2* partial, int nvec, int nblocks, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nvec * nrhs), dim3(64), 0, s, out, partial, nblocks);
+void launch_reduce_partials(double2* h, double2* coef, const double2* partial, int nvec, int nblocks, int nrhs,
+                            const double* ivn, long long ivn_ld, int jw, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nvec * nrhs), dim3(64), 0, s, h, coef, partial, nblocks, nvec, ivn,
+                       ivn_ld, jw);
     VIE_HIP(hipGetLastError());
 }
 
-// w -= sum_i h_i V_i (FP64 arithmetic), and partial sums of |w|^2
+// w = sw w - sum_i c_i u_i (FP64 arithmetic; sw = ivn[jw], or 1 for jw < 0),
+// and partial sums of |w|^2 of the stored values
 template <typename R>
 __global__ void __launch_bounds__(kTpb) k_update(C<R>* __restrict__ w, const C<R>* __restrict__ Vb, long long ldv,
                                                  int nvec, const double2* __restrict__ h, long long n, long long rsv,
-                                                 long long rsw, double* __restrict__ norm_partial) {
+                                                 long long rsw, double* __restrict__ norm_partial,
+                                                 const double* __restrict__ ivn, long long ivn_ld, int jw) {
     using U = Unit<R>;
     using T = typename U::T;
     __shared__ double red[kTpb / 64];
@@ -144,12 +162,17 @@ __global__ void __launch_bounds__(kTpb) k_update(C<R>* __restrict__ w, const C<R
     T* wr = reinterpret_cast<T*>(w + r * rsw);
     const long long nu = n / U::per, ldu = ldv / U::per;
     const double2* hr = h + (long long)r * nvec;
+    const double sw = jw >= 0 ? ivn[r * ivn_ld + jw] : 1.0;
     double acc = 0.0;
     for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < nu; k += (long long)gridDim.x * kTpb) {
         T wu = wr[k];
         double2 wv[U::per];
 #pragma unroll
-        for (int q = 0; q < U::per; ++q) wv[q] = U::get(wu, q);
+        for (int q = 0; q < U::per; ++q) {
+            wv[q] = U::get(wu, q);
+            wv[q].x *= sw;
+            wv[q].y *= sw;
+        }
         // the basis vectors in blocks of 8 (their loads issued together),
         // then one at a time
         int i = 0;
@@ -199,22 +222,31 @@ __global__ void __launch_bounds__(kTpb) k_update(C<R>* __restrict__ w, const C<R
 
 template <typename R>
 void launch_update(C<R>* w, const C<R>* Vb, long long ldv, int nvec, const double2* h, long long n, long long rsv,
-                   long long rsw, double* norm_partial, int nrhs, int nblocks, hipStream_t s) {
+                   long long rsw, double* norm_partial, const double* ivn, long long ivn_ld, int jw, int nrhs,
+                   int nblocks, hipStream_t s) {
     hipLaunchKernelGGL(k_update<R>, dim3(nblocks, nrhs), dim3(kTpb), 0, s, w, Vb, ldv, nvec, h, n, rsv, rsw,
-                       norm_partial);
+                       norm_partial, ivn, ivn_ld, jw);
     VIE_HIP(hipGetLastError());
 }
 
-__global__ void k_reduce_norm(double* __restrict__ out, const double* __restrict__ partial, int nblocks) {
+// norms from partial sums of squares; with inv != nullptr also their
+// reciprocals (0 for a zero norm) at inv[r * inv_ld]
+__global__ void k_reduce_norm(double* __restrict__ out, const double* __restrict__ partial, int nblocks,
+                              double* __restrict__ inv, long long inv_ld) {
     const int r = blockIdx.x;
     double s = 0;
     for (int b = threadIdx.x; b < nblocks; b += 64) s += partial[(long long)r * nblocks + b];
     s = wave_sum(s);
-    if (threadIdx.x == 0) out[r] = sqrt(s);
+    if (threadIdx.x == 0) {
+        const double nv = sqrt(s);
+        out[r] = nv;
+        if (inv) inv[r * inv_ld] = nv > 0 ? 1.0 / nv : 0.0;
+    }
 }
 
-void launch_reduce_norm(double* out, const double* partial, int nblocks, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_norm, dim3(nrhs), dim3(64), 0, s, out, partial, nblocks);
+void launch_reduce_norm(double* out, const double* partial, int nblocks, int nrhs, hipStream_t s, double* inv,
+                        long long inv_ld) {
+    hipLaunchKernelGGL(k_reduce_norm, dim3(nrhs), dim3(64), 0, s, out, partial, nblocks, inv, inv_ld);
     VIE_HIP(hipGetLastError());
 }
 
@@ -357,7 +389,7 @@ void launch_nonfinite(int* flag, const double2* v, long long n, hipStream_t s) {
     template void launch_multidot<R>(double2*, const C<R>*, long long, int, const C<R>*, long long, long long,  \
                                      long long, int, int, hipStream_t);                                          \
     template void launch_update<R>(C<R>*, const C<R>*, long long, int, const double2*, long long, long long,   \
-                                   long long, double*, int, int, hipStream_t);                                   \
+                                   long long, double*, const double*, long long, int, int, int, hipStream_t);    \
     template void launch_scale_into<R>(C<R>*, const C<R>*, const double*, long long, long long, long long, int, \
                                        hipStream_t);                                                             \
     template void launch_combine<R>(double2*, const C<R>*, long long, int, const double2*, long long, long long, \

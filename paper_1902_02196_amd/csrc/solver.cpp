@@ -9,7 +9,10 @@
 // followed by x += ||r|| d in FP64.  Orthogonalisation is classical
 // Gram-Schmidt (optionally twice) with FP64 inner products; the Hessenberg
 // matrix, Givens rotations and the small triangular solve are FP64 on the
-// host.
+// host.  Basis vectors after the first are stored unnormalised, each with its
+// reciprocal norm beside it: the normalisation is folded into the
+// Gram-Schmidt coefficients and the solution update instead of taking a pass
+// over the vector of its own.
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -39,8 +42,8 @@ static void norms(Ctx& c, const C<R>* v, long long n, int nrhs, double* partial,
 }
 
 struct Layout {
-    double2 *rhs, *r, *partial, *h1, *h2, *y;
-    double *nrm, *npart, *inv, *bn, *rn;
+    double2 *rhs, *r, *partial, *h1, *h2, *coef, *y;
+    double *nrm, *npart, *inv, *bn, *rn, *ivn;
 };
 
 template <typename R>
@@ -96,6 +99,14 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
                 launch_scale_into<double>(reinterpret_cast<double2*>(Vb) + s * n, L.r + active[s] * n,
                                           L.rn + active[s], n, n, n, 1, c.stream);
         }
+        // reciprocal norms of the stored basis vectors: 1 for V_0, the rest
+        // written by the device after each step (and kept on the host for
+        // the solution update)
+        std::vector<double> ivn0((size_t)na * (m + 1), 0.0);
+        for (int s = 0; s < na; ++s) ivn0[(size_t)s * (m + 1)] = 1.0;
+        VIE_HIP(hipMemcpyAsync(L.ivn, ivn0.data(), ivn0.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        std::vector<std::vector<double>> ivh(na, std::vector<double>(m + 1, 0.0));
+        for (int s = 0; s < na; ++s) ivh[s][0] = 1.0;
         // per-slot Hessenberg / Givens state
         std::vector<std::vector<cd>> H(na, std::vector<cd>((size_t)(m + 1) * m));
         std::vector<std::vector<cd>> cs(na, std::vector<cd>(m)), sn(na, std::vector<cd>(m)),
@@ -137,6 +148,7 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
                     if (o.reorth) Hc[i] += cd(h2[(size_t)s * nvec + i].x, h2[(size_t)s * nvec + i].y);
                 }
                 Hc[j + 1] = nrm[s];
+                ivh[s][j + 1] = nrm[s] > 0 ? 1.0 / nrm[s] : 0.0;
                 for (int i = 0; i < j; ++i) {   // previous rotations
                     const cd t = cs[s][i] * Hc[i] + sn[s][i] * Hc[i + 1];
                     Hc[i + 1] = -std::conj(sn[s][i]) * Hc[i] + std::conj(cs[s][i]) * Hc[i + 1];
@@ -173,25 +185,25 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
             const int nvec = j + 1;
             // Gram-Schmidt, per pass: the dot kernel reads the j + 1 basis
             // vectors and w (w once per group of 8 basis vectors); the
-            // update reads them again and writes w; normalising reads and
-            // writes w once more
+            // update reads them again, reads and writes w, and leaves w
+            // unnormalised with its reciprocal norm in ivn[j + 1]
             const double vb = (double)na * n * sizeof(C<R>);
             const double dot_bytes = vb * (nvec + (nvec + 7) / 8);
             const double upd_bytes = vb * (nvec + 2);
+            const long long ivld = m + 1;
             for (int pass = 0; pass < (o.reorth ? 2 : 1); ++pass) {
                 double2* hp = pass ? L.h2 : L.h1;
+                const int jw = pass ? -1 : j;
                 {
                     ProfScope ps(c.prof, c.stream, VIE_K_GS_DOT, dot_bytes);
                     launch_multidot<R>(L.partial, Vb, ldv, nvec, w, n, n, n, na, nb, c.stream);
-                    launch_reduce_partials(hp, L.partial, nvec, nb, na, c.stream);
+                    launch_reduce_partials(hp, L.coef, L.partial, nvec, nb, na, L.ivn, ivld, jw, c.stream);
                 }
                 {
-                    ProfScope ps(c.prof, c.stream, VIE_K_GS_UPDATE, upd_bytes + (pass == (o.reorth ? 1 : 0) ? 2 * vb : 0));
-                    launch_update<R>(w, Vb, ldv, nvec, hp, n, n, n, L.npart, na, nb, c.stream);
-                    if (pass == (o.reorth ? 1 : 0)) {
-                        launch_reduce_norm(L.nrm, L.npart, nb, na, c.stream);
-                        launch_scale_into<R>(w, w, L.nrm, n, n, n, na, c.stream);
-                    }
+                    ProfScope ps(c.prof, c.stream, VIE_K_GS_UPDATE, upd_bytes);
+                    launch_update<R>(w, Vb, ldv, nvec, L.coef, n, n, n, L.npart, L.ivn, ivld, jw, na, nb, c.stream);
+                    if (pass == (o.reorth ? 1 : 0))
+                        launch_reduce_norm(L.nrm, L.npart, nb, na, c.stream, L.ivn + (j + 1), ivld);
                 }
             }
             // the column's slot was last read by the host for step j - 2,
@@ -227,7 +239,9 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
                 const cd d = H[s][(size_t)i * (m + 1) + i];
                 yv[i] = (d == 0.0) ? cd(0) : acc / d;
             }
-            for (int i = 0; i < jdone; ++i) yh[(size_t)s * jdone + i] = make_double2(yv[i].real(), yv[i].imag());
+            // V y = sum_i (y_i ivn_i) u_i over the stored vectors
+            for (int i = 0; i < jdone; ++i)
+                yh[(size_t)s * jdone + i] = make_double2(yv[i].real() * ivh[s][i], yv[i].imag() * ivh[s][i]);
         }
         VIE_HIP(hipMemcpyAsync(L.y, yh.data(), yh.size() * sizeof(double2), hipMemcpyHostToDevice, c.stream));
         for (int s = 0; s < na; ++s) {
@@ -263,6 +277,7 @@ int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2*
     const size_t o_rhs = take((size_t)nrhs * n * 16), o_r = take((size_t)nrhs * n * 16);
     const size_t o_part = take((size_t)nrhs * (m + 1) * nb * 16);
     const size_t o_h1 = take((size_t)nrhs * (m + 1) * 16), o_h2 = take((size_t)nrhs * (m + 1) * 16);
+    const size_t o_coef = take((size_t)nrhs * (m + 1) * 16), o_ivn = take((size_t)nrhs * (m + 1) * 8);
     const size_t o_y = take((size_t)nrhs * m * 16);
     const size_t o_nrm = take(nrhs * 8), o_np = take((size_t)nrhs * nb * 8), o_inv = take(nrhs * 8);
     const size_t o_bn = take(nrhs * 8), o_rn = take(nrhs * 8);
@@ -273,6 +288,8 @@ int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2*
     L.partial = reinterpret_cast<double2*>(base + o_part);
     L.h1 = reinterpret_cast<double2*>(base + o_h1);
     L.h2 = reinterpret_cast<double2*>(base + o_h2);
+    L.coef = reinterpret_cast<double2*>(base + o_coef);
+    L.ivn = reinterpret_cast<double*>(base + o_ivn);
     L.y = reinterpret_cast<double2*>(base + o_y);
     L.nrm = reinterpret_cast<double*>(base + o_nrm);
     L.npart = reinterpret_cast<double*>(base + o_np);
