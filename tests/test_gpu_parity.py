@@ -184,11 +184,13 @@ def test_dipole_rhs(vie, torch):
         assert relerr(vec_from_lib(et[r].cpu().numpy()), ref[r]) < 1e-12
 
 
-@pytest.mark.parametrize("mode,tol,bound", [(0, 1e-12, 1e-9), (1, 1e-10, 1e-7)])
-def test_solve_matches_dense(vie, torch, mode, tol, bound):
-    """GMRES on the device (FP64, and FP32 + FP64 refinement) vs the oracle's
-    exact discrete solution by dense LU (4 x 4 x 4 sphere, config-1 material)."""
-    _say("solve mode %d" % mode)
+@pytest.mark.parametrize("mode,tol,bound,reorth", [(0, 1e-12, 1e-9, 0), (1, 1e-10, 1e-7, 0), (0, 1e-12, 1e-9, 1),
+                                                   (1, 1e-10, 1e-7, 1)])
+def test_solve_matches_dense(vie, torch, mode, tol, bound, reorth):
+    """GMRES on the device (FP64, and FP32 + FP64 refinement; one or two
+    Gram-Schmidt passes) vs the oracle's exact discrete solution by dense LU
+    (4 x 4 x 4 sphere, config-1 material)."""
+    _say("solve mode %d reorth %d" % (mode, reorth))
     N, D = (4, 4, 4), (0.005,) * 3
     T = _full_blocks(N, D)
     c = _ctx(vie, torch, N, D)
@@ -199,7 +201,7 @@ def test_solve_matches_dense(vie, torch, mode, tol, bound):
     xref = solve.solve_dense(T, tau, D, matvec.rhs_prec(et, tau, D, F))
     etd = _to_dev(torch, et, torch.complex128)
     xd = torch.empty_like(etd)
-    code, st = c.solve(etd, xd, mode=mode, tol=tol, restart=20)
+    code, st = c.solve(etd, xd, mode=mode, tol=tol, restart=20, reorth=reorth)
     _say("  stats %s" % st[0])
     assert code == vie.VIE_OK and st[0]["converged"]
     err = relerr(_from_dev(xd), xref)
@@ -322,7 +324,8 @@ def test_shared_grid_matches_own_assembly(vie, torch):
 
 def test_degenerate_cases(vie, torch):
     """Edge cases of the method: a single voxel (fft length 2, generic
-    kernels) against the oracle's direct sum; no contrast, where P^-1 A is the
+    kernels) against the oracle's direct sum, and solved against dense LU with
+    a Krylov space used up within one cycle; no contrast, where P^-1 A is the
     identity and a zero right-hand side solves to zero at once; zero right-hand
     side counts are refused."""
     N, D = (1, 1, 1), (0.004, 0.005, 0.006)
@@ -349,6 +352,23 @@ def test_degenerate_cases(vie, torch):
     code, st = c.solve(et, xs, mode=vie.SOLVE_FP32_IR)
     assert code == vie.VIE_OK and st[0]["iterations"] == 0
     assert not bool(xs.abs().max())
+    # one voxel with contrast: the 12 unknowns use the Krylov space up within
+    # one restart cycle, so the last vectors vanish up to rounding
+    N1, D1 = (1, 1, 1), (0.004, 0.005, 0.006)
+    T1 = _full_blocks(N1, D1)
+    c1 = _ctx(vie, torch, N1, D1, T1)
+    e1, s1 = np.full(N1, 50.0), np.full(N1, 0.7)
+    c1.set_contrast(vox_to_lib(e1), vox_to_lib(s1))
+    tau1 = physics.tau(e1, s1, F)
+    et1 = incident.planewave_tested(N1, D1, K)
+    xref = solve.solve_dense(T1, tau1, D1, matvec.rhs_prec(et1, tau1, D1, F))
+    for mode, tol, bound in ((vie.SOLVE_FP64, 1e-13, 1e-10), (vie.SOLVE_FP32_IR, 1e-11, 1e-8)):
+        etd = _to_dev(torch, et1, torch.complex128)
+        xd = torch.empty_like(etd)
+        code, st = c1.solve(etd, xd, mode=mode, tol=tol, restart=20)
+        _say("  one voxel, mode %d: %s" % (mode, st[0]))
+        assert code == vie.VIE_OK and st[0]["converged"]
+        assert relerr(_from_dev(xd), xref) < bound
     with pytest.raises(vie.VieError) as ei:
         c.apply(x[:0], y[:0], op=vie.OP_PREC)
     assert ei.value.code == vie.VIE_EINVAL
