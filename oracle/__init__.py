@@ -22,6 +22,9 @@ Fields in MRI", IEEE TAP 2020):
 * ``post``      - fields, absorbed power, error metrics (Sec. IV-C, eq. 44,
                   Sec. V-C error definitions)
 * ``mie``       - Mie series absorbed power for a homogeneous sphere (Sec. V-A)
+* ``pwc``       - the piecewise-constant discretisation the paper compares
+                  against (Sec. V: 3 unknowns per voxel, 6 unique tensors),
+                  as the l = 1 restriction of the PWL system
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test except the
 absolute accuracy of the discretisation against Mie, which the paper only
