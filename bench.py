@@ -33,14 +33,15 @@ FP32_UNPACKED_PEAK_TFLOPS = 78.6
 PROFILE_EVERY = 8
 
 
-def block_flops(M, nrhs):
+def block_flops(M, nrhs, nc=12):
     """Algorithmic flops of one x-pass launch: forward and inverse FFT along x
-    of the 12 components (5 n log2 n each) and the 12 x 12 complex block
-    product (144 complex multiply-adds = 1152 flops) at every frequency."""
+    of the nc components (5 n log2 n each) and the nc x nc complex block
+    product (nc^2 complex multiply-adds of 8 flops) at every frequency:
+    1152 flops for the PWL basis (nc = 12), 72 for the PWC basis (nc = 3)."""
     import math
     Mx, My, Mz = M
     pts = Mx * My * Mz
-    return nrhs * (2 * 5 * 12 * pts * math.log2(Mx) + 1152 * pts)
+    return nrhs * (2 * 5 * nc * pts * math.log2(Mx) + 8 * nc * nc * pts)
 
 # sources whose change invalidates counter measurements of the kernels
 KERNEL_SOURCES = ["paper_1902_02196_amd/csrc/passes.hip", "paper_1902_02196_amd/csrc/strided.hip",
@@ -78,6 +79,9 @@ def measured_traffic(kernel_class, workload):
 
 WORKLOADS = {
     "phantom64": dict(N=(64, 64, 64), h=0.003, f=298e6, seed=190202196 + 1),
+    # the same body with the PWC basis the paper compares against (3 unknowns
+    # per voxel)
+    "phantom64_pwc": dict(N=(64, 64, 64), h=0.003, f=298e6, seed=190202196 + 1, basis=3),
     "sphere16": dict(N=(16, 16, 16), h=0.005, f=298e6, seed=None),
     # head-sized box, 16 Hertzian dipoles on a 15 cm cylinder, one batched solve
     "batched16": dict(N=(96, 128, 128), h=0.002, f=298e6, seed=190202196 + 3, nrhs=16, cyl=0.15,
@@ -93,35 +97,35 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(N, h, f, mv_per_solve, seconds_budget=25.0):
+def cpu_baseline(N, h, f, mv_per_solve, seconds_budget=25.0, nc=12):
     """The oracle's FFT operator product (FP64, scipy.fft) on this host's cores,
     timed on a bounded sample: a few products of the same grid; the solve rate
     is that time times the FP64 solver's operator products per solve.  The
     oracle's own block assembly is not included (random blocks of the right
     shape: values do not change the time)."""
-    import scipy.fft
-    from oracle import matvec
+    from oracle import matvec, pwc
     import vie_inputs as vi
     cores = min(16, os.cpu_count() or 1)
     Nx, Ny, Nz = N
-    T = vi.complex_normal(5, (12, 12, 2 * Nx - 1, 2 * Ny - 1, 2 * Nz - 1))
+    T = vi.complex_normal(5, (nc, nc, 2 * Nx - 1, 2 * Ny - 1, 2 * Nz - 1))
     M = (2 * Nx, 2 * Ny, 2 * Nz)
     t0 = time.perf_counter()
-    Ch = matvec.circulant_spectrum(T, M, workers=cores)
+    Ch = matvec.circulant_spectrum(T, M, workers=cores) if nc == 12 else pwc.spectrum(T, M, workers=cores)
     del T
     t_setup = time.perf_counter() - t0
-    x = vi.complex_normal(6, (12,) + tuple(N))
+    x = vi.complex_normal(6, (nc,) + tuple(N))
+    fft_N = matvec.fft_N if nc == 12 else pwc.fft_N
     times = []
     t_start = time.perf_counter()
     while len(times) < 3 and (time.perf_counter() - t_start) < seconds_budget:
         t0 = time.perf_counter()
-        matvec.fft_N(Ch, x, workers=cores)
+        fft_N(Ch, x, workers=cores)
         times.append(time.perf_counter() - t0)
     t_mv = float(np.median(times))
     return {"value": 1.0 / (t_mv * mv_per_solve), "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": "%d oracle FFT operator products (FP64, scipy.fft, %d workers) on the %dx%dx%d grid, "
-                      "%.2f s each, times %d products per FP64 solve; spectrum set-up %.1f s excluded"
-                      % (len(times), cores, Nx, Ny, Nz, t_mv, mv_per_solve, t_setup)}
+            "sample": "%d oracle FFT operator products (FP64, scipy.fft, %d workers, %d unknowns per voxel) on "
+                      "the %dx%dx%d grid, %.2f s each, times %d products per FP64 solve; spectrum set-up %.1f s "
+                      "excluded" % (len(times), cores, nc, Nx, Ny, Nz, t_mv, mv_per_solve, t_setup)}
 
 
 SERVING = dict(edges=(32, 48, 64, 96, 128), h=0.003, freqs=(128e6, 298e6), rate=20.0, max_rhs=8,
@@ -259,6 +263,9 @@ def main():
     t0 = time.perf_counter()
     ctx = vie.Context(0, stream)
     ctx.set_grid(N, D, f)
+    nc = W.get("basis", 12)
+    if nc != 12:
+        ctx.set_basis(nc)
     torch.cuda.synchronize()
     t_grid = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -391,7 +398,7 @@ def main():
     tr = measured_traffic(dom, args.workload)
     hbm_achieved = (by / nl) / avg_s / 1e9
     if dom == "block":
-        fl = block_flops(ctx.fft_size, group)
+        fl = block_flops(ctx.fft_size, group, nc)
         achieved = fl / avg_s / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": tr,
@@ -422,11 +429,13 @@ def main():
         "refinement": "FP64 residuals, updates, inner products and Givens",
         "data": "synthetic",
         "config": {"workload": "%s: %dx%dx%d voxels at %.0f mm, %.0f MHz, %s, %s, "
-                               "GMRES(%d) to 1e-6, complex64 + FP64 refinement"
+                               "GMRES(%d) to 1e-6, complex64 + FP64 refinement, %s basis"
                                % (args.workload, N[0], N[1], N[2], h * 1e3, f / 1e6,
                                   ("10-class layered phantom" if W.get("layered") else "6-class ellipsoid phantom")
                                   if W["seed"] else "eps 50 sigma 0.7 sphere r=3 cm",
-                                  excitation, args.restart), "nrhs": nrhs},
+                                  excitation, args.restart,
+                                  "PWL (12 unknowns per voxel)" if nc == 12 else "PWC (3 unknowns per voxel)"),
+                   "nrhs": nrhs},
         "fp64_solves_per_s": round(n64 / t_64, 4),
         "fp64_rhs": n64,
         "ir_vs_fp64_speedup": round(sps * t_64 / n64, 3),
@@ -446,7 +455,7 @@ def main():
     if not args.no_cpu and nrhs == 1:
         mv_per_solve = st64[0]["matvecs_c128"]
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(N, h, f, mv_per_solve)
+        out["cpu_baseline"] = cpu_baseline(N, h, f, mv_per_solve, nc=nc)
     print(json.dumps(out), flush=True)
 
 

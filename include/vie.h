@@ -16,9 +16,11 @@
  * ----------------------------------------
  * - Grid: Nx x Ny x Nz voxels of size dx x dy x dz (metres), box centred at
  *   the origin; voxel centres at (n_i - (N_i - 1)/2) * d_i.
- * - Vectors of unknowns ("x" layout): [nrhs][12][Nz][Ny][Nx], x fastest,
- *   interleaved complex (real, imag).  Unknown index a = 4 p + (l - 1),
- *   p in {x, y, z} -> 0..2, l = 1 (pulse), 2..4 (linear in x, y, z) (eq. 30).
+ * - Vectors of unknowns ("x" layout): [nrhs][nc][Nz][Ny][Nx], x fastest,
+ *   interleaved complex (real, imag).  PWL basis (nc = 12, the default):
+ *   unknown index a = 4 p + (l - 1), p in {x, y, z} -> 0..2, l = 1 (pulse),
+ *   2..4 (linear in x, y, z) (eq. 30).  PWC basis (nc = 3, vie_set_basis):
+ *   unknown index p, the pulse coefficients alone.
  * - Per-voxel arrays: [Nz][Ny][Nx].
  * - precision: VIE_C64 (complex64, FP32 arithmetic) or VIE_C128 (complex128).
  * - Time factor exp(+i w t); eps_r = eps' - i sigma / (w eps0) (eq. 2).
@@ -114,6 +116,17 @@ int vie_set_stream(vie_ctx* ctx, void* stream);
 int vie_set_grid(vie_ctx* ctx, int nx, int ny, int nz, double dx, double dy, double dz,
                  double freq_hz, const int* fft_size);
 
+/* Discretisation of later calls: ncomp = 12 selects the PWL basis (the
+ * default), ncomp = 3 the piecewise-constant (PWC) basis the paper compares
+ * against (Sec. I, Sec. V: 3 unknowns per voxel, 6 unique tensors).  The PWC
+ * basis is the pulse function of each voxel and component, i.e. the l = 1
+ * members of the PWL basis, so its Galerkin system is the PWL one restricted
+ * to a = 4 p: operator tensors u = 10 pq (ll = 11) of the same assembled
+ * operator, Gram dV.  Vectors of every later call hold ncomp unknowns per
+ * voxel.  Clears the launch-shape choices; may be called at any time.
+ * Returns VIE_EINVAL for other values. */
+int vie_set_basis(vie_ctx* ctx, int ncomp);
+
 /* Debug / parity entry: replace the operator by caller-supplied unique block
  * tensors T_host [60][Nz][Ny][Nx] complex128 (host memory), d >= 0 octant,
  * unique index u = 10 * pq + ll with pq over (xx, xy, xz, yy, yz, zz) and
@@ -145,14 +158,14 @@ int vie_set_contrast(vie_ctx* ctx, const double* eps_re, const double* sigma, in
 
 /* Tested incident field of a plane wave E0 pol exp(-i k0 dir . r) (eq. 30,
  * plane wave of Sec. V-A for pol = x, dir = z), into e_t (device,
- * [12][Nz][Ny][Nx] complex128).  pol and dir must be orthogonal unit vectors
+ * [nc][Nz][Ny][Nx] complex128).  pol and dir must be orthogonal unit vectors
  * along coordinate axes. */
 int vie_incident_planewave(vie_ctx* ctx, const double pol[3], const double dir[3], double amp,
                            void* e_t);
 
 /* Tested incident fields of nrhs Hertzian dipoles (current moment vectors in
  * A m at positions in m, host arrays [nrhs][3]) into e_t (device,
- * [nrhs][12][Nz][Ny][Nx] complex128), by nq^3-point Gauss quadrature per
+ * [nrhs][nc][Nz][Ny][Nx] complex128), by nq^3-point Gauss quadrature per
  * voxel on voxels with chi != 0 (others set to zero). */
 int vie_incident_dipoles(vie_ctx* ctx, int nrhs, const double* pos, const double* moment, int nq,
                          void* e_t);

@@ -77,6 +77,12 @@ def apply_prec(T3, x, tau, Delta, Nx_fn=direct_N):
     return x - tau[None] * Nx_fn(T3, x) / dv
 
 
+def apply_A(T3, x, epsr, chi, Delta, Nx_fn=direct_N):
+    """A x = M_eps dV x - M_chi N x (eq. 24a with G = dV I)."""
+    dv = Delta[0] * Delta[1] * Delta[2]
+    return epsr[None] * dv * x - chi[None] * Nx_fn(T3, x)
+
+
 def rhs_prec(e_t3, tau, Delta, freq_hz):
     """P^-1 b = c_e tau e_t / dV (eq. 24b, 31 with G = dV I)."""
     dv = Delta[0] * Delta[1] * Delta[2]

@@ -3,13 +3,15 @@
 Thin ctypes binding of the C ABI in include/vie.h: argument marshalling only,
 every step of the computation runs in the HIP library ``libvie.so``.  PyTorch
 supplies device memory and streams.  Importing fails loudly when the library
-has not been built (``python -m paper_1902_02196_amd.build``); there is no
+has not been built (``python paper_1902_02196_amd/build.py``); there is no
 CPU fallback.
 
 Array layout: vectors of unknowns are torch tensors of shape
-(nrhs, 12, Nz, Ny, Nx), complex64 or complex128, on the GPU; unknown index
-a = 4 p + (l - 1) with p the field component and l the scalar basis
-(1 pulse, 2..4 linear in x, y, z).  Per-voxel arrays are (Nz, Ny, Nx).
+(nrhs, nc, Nz, Ny, Nx), complex64 or complex128, on the GPU.  PWL basis
+(nc = 12, the default): unknown index a = 4 p + (l - 1) with p the field
+component and l the scalar basis (1 pulse, 2..4 linear in x, y, z).  PWC
+basis (nc = 3, ``Context.set_basis(3)``): unknown index p, the pulse
+coefficients alone.  Per-voxel arrays are (Nz, Ny, Nx).
 """
 import ctypes
 import os
@@ -26,7 +28,7 @@ SOLVE_FP64, SOLVE_FP32_IR = 0, 1
 KERNELS = ("fft_z_fwd", "fft_y_fwd", "block", "fft_y_inv", "fft_z_inv", "gs_dot", "gs_update")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libvie.so is not built; run `python -m paper_1902_02196_amd.build` (needs hipcc)")
+    raise ImportError("libvie.so is not built; run `python paper_1902_02196_amd/build.py` (needs hipcc)")
 _lib = ctypes.CDLL(LIB_PATH)
 
 _vp = ctypes.c_void_p
@@ -89,6 +91,7 @@ _sig = {
     "vie_autotune": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _dp]),
     "vie_set_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(_i)]),
     "vie_fft_size": (_i, [_vp, ctypes.POINTER(_i)]),
+    "vie_set_basis": (_i, [_vp, _i]),
     "vie_share_grid": (_i, [_vp, _vp]),
     "vie_profile": (_i, [_vp, _i]),
     "vie_profile_read": (_i, [_vp, _i, _dp, ctypes.POINTER(_i), _dp]),
@@ -173,6 +176,7 @@ class Context:
         _check(_lib.vie_create(ctypes.byref(h), device, _stream_ptr(stream)))
         self._h = h
         self.N = None
+        self.nc = 12
 
     def close(self):
         if self._h:
@@ -195,6 +199,11 @@ class Context:
                                  float(freq_hz), fs))
         self.N = (nx, ny, nz)
 
+    def set_basis(self, ncomp):
+        """12: PWL basis (default); 3: PWC basis (pulse functions alone)."""
+        _check(_lib.vie_set_basis(self._h, int(ncomp)))
+        self.nc = int(ncomp)
+
     def share_grid(self, other):
         """Use other's grid and operator (shared device buffers)."""
         _check(_lib.vie_share_grid(self._h, other._h))
@@ -212,7 +221,7 @@ class Context:
         return self.N[0] * self.N[1] * self.N[2]
 
     def vec_shape(self, nrhs=1):
-        return (nrhs, 12, self.N[2], self.N[1], self.N[0])
+        return (nrhs, self.nc, self.N[2], self.N[1], self.N[0])
 
     def set_toeplitz(self, T_unique):
         """T_unique: complex128 [60, Nz, Ny, Nx] (offsets d >= 0)."""

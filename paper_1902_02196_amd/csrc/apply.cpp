@@ -10,8 +10,10 @@
 //         A:     y = eps_r G x - chi w            (eq. 24a)
 //         N:     y = w                            (eq. 25a)
 //         RESID: y = rhs - (x - tau G^-1 w)       (refinement residual)
-// B = 12 nrhs component arrays; the 1/(Mx My Mz) of the inverse FFT is folded
-// into the epilogue.
+// B = nc nrhs component arrays (nc = 12 unknowns per voxel for the PWL basis,
+// 3 for the PWC basis, whose x pass applies the 3 x 3 blocks of the constant
+// functions); the 1/(Mx My Mz) of the inverse FFT is folded into the
+// epilogue.
 #include <algorithm>
 
 #include "ctx.hpp"
@@ -39,12 +41,13 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     if (op != OP_N) VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "operator needs vie_set_contrast");
     const int Nx = c.N[0], Ny = c.N[1], Nz = c.N[2];
     const int Mx = c.M[0], My = c.M[1], Mz = c.M[2];
-    const long long B = 12LL * nrhs;
-    // intermediate layouts per right-hand side [Mz][Ny|My][12][Nx]: the 12
+    const int nc = c.nc;
+    const long long B = (long long)nc * nrhs;
+    // intermediate layouts per right-hand side [Mz][Ny|My][nc][Nx]: the nc
     // components of one (z, y) row are adjacent, so a pencil group of the x
     // pass is one contiguous block; planes are padded so that rows used
     // together are not a large power of two apart
-    const long long row = 12LL * Nx;
+    const long long row = (long long)nc * Nx;
     const long long pl1 = (long long)Ny * row + 32, pl2 = (long long)My * row + 32;
     const long long sR1 = (long long)Mz * pl1 + 96;   // per right-hand side, after P1 / P4
     const long long sR2 = (long long)Mz * pl2 + 96;   // after P2 / P3
@@ -63,7 +66,8 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     p1.n_inner = Nx;
     p1.tile = tn.tile_z ? tn.tile_z : pick_tile(Mz, es);
     p1.pitch = p1.tile;
-    p1.in_s1 = 12 * V;
+    p1.nc = nc;
+    p1.in_s1 = nc * V;
     p1.in_sc = V;
     p1.in_s2 = Nx;
     p1.in_sk = (long long)Ny * Nx;
@@ -80,6 +84,7 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     // P2: y
     StridedPass p2{};
     p2.plan = c.ax[1].plan;
+    p2.nc = nc;
     p2.n_in = Ny;
     p2.n_out = My;
     p2.n_inner = Nx;
@@ -114,7 +119,14 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     p3.s_y = row;
     p3.u_e = c.O[0];
     p3.pitch = Mx;
-    {
+    if (nc == 3) {
+        // PWC: 6 of the operator's unique tensors per frequency
+        VIE_REQUIRE(p3_ct_supported(Mx), VIE_EINVAL,
+                    "the PWC x pass needs an fft length along x of 8, 16, 32, 64, 96, 128, 160, 192, 256, 320, 384 "
+                    "or 512");
+        KernelTiming kt(c.prof, VIE_K_BLOCK, 2 * bA2 + 6.0 * c.Osz * es);
+        launch_p3_pwc<R>(A2, opspec<R>(c), p3, twid<R>(c.ax[0]), s);
+    } else {
         // as many pencil groups per LDS pass as fit 64 KiB and the
         // butterfly bound of the in-place passes (at most 4 siblings share
         // an octant row)
@@ -144,8 +156,6 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
         p3.groups = g;
         p3.magic_nx = magic_for((unsigned)Nx);
         p3.magic_ox = magic_for((unsigned)c.O[0]);
-    }
-    {
         KernelTiming kt(c.prof, VIE_K_BLOCK, 2 * bA2 + 60.0 * c.Osz * es);
         launch_p3<R>(A2, opspec<R>(c), p3, twid<R>(c.ax[0]), s);
     }
@@ -175,7 +185,7 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     p5.in_sc = Nx;
     p5.in_s2 = row;
     p5.in_sk = pl1;
-    p5.out_s1 = 12 * V;
+    p5.out_s1 = nc * V;
     p5.out_sc = V;
     p5.out_s2 = Nx;
     p5.out_sk = (long long)Ny * Nx;

@@ -303,7 +303,7 @@ int vie_incident_planewave(vie_ctx* ctx, const double pol[3], const double dir[3
         VIE_REQUIRE(pa >= 0 && da >= 0 && pa != da, VIE_EINVAL,
                     "pol and dir must be distinct unit vectors along coordinate axes");
         launch_planewave(static_cast<double2*>(e_t), c.N[0], c.N[1], c.N[2], c.D, c.k0, pa, da, dir[da] > 0 ? 1.0 : -1.0,
-                         amp, c.stream);
+                         amp, c.nc, c.stream);
     });
 }
 
@@ -329,7 +329,7 @@ int vie_incident_dipoles(vie_ctx* ctx, int nrhs, const double* pos, const double
         double* dev = static_cast<double*>(c.small.get(host.size() * sizeof(double)));
         VIE_HIP(hipMemcpyAsync(dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
         launch_dipoles(static_cast<double2*>(e_t), nrhs, dev, dev + 3 * nrhs, nq, dev + 6 * nrhs, dev + 6 * nrhs + nq,
-                       c.mat.chi, c.N[0], c.N[1], c.N[2], c.D, c.k0, c.omega * kEps0, c.stream);
+                       c.mat.chi, c.N[0], c.N[1], c.N[2], c.D, c.k0, c.omega * kEps0, c.nc, c.stream);
         VIE_HIP(hipStreamSynchronize(c.stream));   // the host staging buffer is reused
     });
 }
@@ -344,7 +344,7 @@ int vie_rhs_prec(vie_ctx* ctx, int nrhs, const void* e_t, void* rhs) {
         const double dv = c.D[0] * c.D[1] * c.D[2];
         const double ginv[4] = {1 / dv, 12 / dv, 12 / dv, 12 / dv};
         launch_rhs_prec(static_cast<double2*>(rhs), static_cast<const double2*>(e_t), c.mat.tau, ginv,
-                        make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.stream);
+                        make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.nc, c.stream);
     });
 }
 
@@ -406,7 +406,7 @@ int vie_fields(vie_ctx* ctx, int nrhs, const void* x, void* e) {
         VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "no contrast");
         VIE_REQUIRE(nrhs >= 1 && x && e, VIE_EINVAL, "bad arguments");
         launch_fields(static_cast<double2*>(e), static_cast<const double2*>(x), c.mat.chi,
-                      make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.stream);
+                      make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.nc, c.stream);
     });
 }
 
@@ -422,7 +422,7 @@ int vie_absorbed_power(vie_ctx* ctx, int nrhs, const void* x, double* p_abs_host
         const double dv = c.D[0] * c.D[1] * c.D[2];
         const double gram[4] = {dv, dv / 12, dv / 12, dv / 12};
         launch_power_partials(part, static_cast<const double2*>(x), c.mat.chi, gram,
-                              make_double2(0.0, c.omega * kEps0), c.V, nrhs, nb, c.stream);
+                              make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.nc, nb, c.stream);
         std::vector<double> h((size_t)nb * nrhs);
         VIE_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
         VIE_HIP(hipStreamSynchronize(c.stream));
@@ -441,7 +441,7 @@ int vie_power_density(vie_ctx* ctx, int nrhs, const void* e, double* p_dev) {
         set_device(c);
         VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "no contrast");
         VIE_REQUIRE(nrhs >= 1 && e && p_dev, VIE_EINVAL, "bad arguments");
-        launch_power_density(p_dev, static_cast<const double2*>(e), c.sigma, c.V, nrhs, c.stream);
+        launch_power_density(p_dev, static_cast<const double2*>(e), c.sigma, c.V, nrhs, c.nc, c.stream);
     });
 }
 
@@ -470,6 +470,16 @@ int vie_autotune(vie_ctx* ctx, int precision, int nrhs, int* choice, double* bes
             choice[2] = t.tile_z;
             choice[3] = t.tile_y;
         }
+    });
+}
+
+int vie_set_basis(vie_ctx* ctx, int ncomp) {
+    return guarded([&] {
+        check_ctx(ctx);
+        VIE_REQUIRE(ncomp == 12 || ncomp == 3, VIE_EINVAL, "ncomp must be 12 (PWL) or 3 (PWC)");
+        Ctx& c = ctx->c;
+        c.nc = ncomp;
+        c.tune.clear();
     });
 }
 

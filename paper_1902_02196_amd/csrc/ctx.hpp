@@ -165,6 +165,7 @@ struct Ctx {
     hipStream_t stream = nullptr;
 
     bool has_grid = false;
+    int nc = 12;               // unknowns per voxel: 12 PWL, 3 PWC (l = 1 only)
     int N[3] = {0, 0, 0};
     int M[3] = {0, 0, 0};
     int O[3] = {0, 0, 0};

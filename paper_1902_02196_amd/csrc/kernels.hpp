@@ -30,6 +30,9 @@ void launch_strided(bool fwd, const C<R>* in, C<R>* out, const StridedPass& p, l
                     const C<R>* tw, const Epilogue<R>* ep, hipStream_t s);
 template <typename R>
 void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s);
+// x pass of the PWC basis (3 component rows per pencil, compiled lengths only)
+template <typename R>
+void launch_p3_pwc(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s);
 bool p3_ct_supported(int n);
 int p3_ct_groups(int es, int n);
 bool p3_ct_fits(int es, int n);
@@ -64,18 +67,20 @@ struct Materials {
 };
 void launch_materials(const double* eps_re, const double* sigma, double omega_eps0, Materials m, long long V,
                       int* bad_flag, hipStream_t s);
+// nc: unknowns per voxel (12 PWL, 3 PWC)
 void launch_planewave(double2* et, int Nx, int Ny, int Nz, const double D[3], double k0, int pol, int dir,
-                      double sgn, double amp, hipStream_t s);
+                      double sgn, double amp, int nc, hipStream_t s);
 void launch_dipoles(double2* et, int nrhs, const double* pos_dev, const double* mom_dev, int nq,
                     const double* glx, const double* glw, const double2* chi, int Nx, int Ny, int Nz,
-                    const double D[3], double k0, double omega_eps0, hipStream_t s);
+                    const double D[3], double k0, double omega_eps0, int nc, hipStream_t s);
 void launch_rhs_prec(double2* rhs, const double2* et, const double2* tau, const double ginv[4], double2 ce,
-                     long long V, int nrhs, hipStream_t s);
-void launch_fields(double2* e, const double2* x, const double2* chi, double2 ce, long long V, int nrhs,
+                     long long V, int nrhs, int nc, hipStream_t s);
+void launch_fields(double2* e, const double2* x, const double2* chi, double2 ce, long long V, int nrhs, int nc,
                    hipStream_t s);
 void launch_power_partials(double* partial, const double2* x, const double2* chi, const double gram[4], double2 ce,
-                           long long V, int nrhs, int nblocks, hipStream_t s);
-void launch_power_density(double* p, const double2* e, const double* sigma, long long V, int nrhs, hipStream_t s);
+                           long long V, int nrhs, int nc, int nblocks, hipStream_t s);
+void launch_power_density(double* p, const double2* e, const double* sigma, long long V, int nrhs, int nc,
+                          hipStream_t s);
 
 // krylov.hip: Gram-Schmidt and vector kernels, FP64 accumulation
 template <typename R>

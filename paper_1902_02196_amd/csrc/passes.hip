@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(256) k_strided(const C<R>* in, C<R>* out,
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int t0 = blockIdx.x * p.tile;
     const long long o2 = blockIdx.y;
-    const int o1 = blockIdx.z, rr = o1 / 12, cc = o1 - 12 * rr;
+    const int o1 = blockIdx.z, rr = o1 / p.nc, cc = o1 - p.nc * rr;
     const int tw_n = min(p.tile, p.n_inner - t0);
     const C<R>* src = in + rr * p.in_s1 + cc * p.in_sc + o2 * p.in_s2 + t0;
     const int n = p.plan.n;
@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(256) k_strided(const C<R>* in, C<R>* out,
         if (EPI) {
             const long long v = o2 * p.out_s2 + k * p.out_sk + t0 + t;   // voxel
             const long long e = obase + v;                                  // element
-            const int l = cc & 3;
+            const int l = p.nc == 12 ? (cc & 3) : 0;
             C<R> bv = ep.b ? ep.b[v] : mk<R>(ep.b_const, 0);
             C<R> y = cscale(cmul(bv, w), ep.gb[l]);
             if (ep.a || ep.a_const != R(0)) {
@@ -725,6 +725,98 @@ __global__ void __launch_bounds__(kP3QuadThreads) k_p3_quad(C<R>* __restrict__ A
     lds_to_rows<R, N, NT>(buf, nrows, p.Nx, rowp);
 }
 
+// x pass of the PWC basis (3 unknowns per voxel, the pulse functions): one
+// workgroup per (octant row, right-hand side) holds the 3 component rows of
+// each of the up to four sibling pencils of the row (at most 12 rows, the LDS
+// of one PWL pencil group).  The 3 x 3 block of a frequency comes from the 6
+// tensors of the pulse functions, unique entries u = 10 pq (ll = 11), placed
+// by the PWL orbit table restricted to the unknowns a = 4 p; one work item
+// per (sibling, frequency).
+template <typename R, int E, int K>
+__device__ __forceinline__ void orbit_apply_pwc(C<R>* yv, const C<R>* xv, C<R> u) {
+    constexpr Orbits o = make_orbits();
+    if constexpr (K < o.cnt[E]) {
+        constexpr int a = o.m[E][K].a, b = o.m[E][K].b, sg = o.m[E][K].s;
+        static_assert(a % 4 == 0 && b % 4 == 0, "pulse-pulse entries couple the unknowns a = 4 p only");
+        if constexpr (sg > 0) cfma(yv[a / 4], u, xv[b / 4]);
+        else cfma(yv[a / 4], mk<R>(-u.x, -u.y), xv[b / 4]);
+        orbit_apply_pwc<R, E, K + 1>(yv, xv, u);
+    }
+}
+
+template <typename R, int Q>
+__device__ __forceinline__ void orbit_product_pwc(C<R>* yv, const C<R>* xv, const C<R>* __restrict__ Ur, int ox,
+                                                  int OXs) {
+    if constexpr (Q < 6) {
+        orbit_apply_pwc<R, 10 * Q, 0>(yv, xv, Ur[10 * Q * OXs + ox]);
+        orbit_product_pwc<R, Q + 1>(yv, xv, Ur, ox, OXs);
+    }
+}
+
+constexpr int kP3PwcThreads = 256;
+
+template <typename R, int N>
+__global__ void __launch_bounds__(kP3PwcThreads) k_p3_pwc(C<R>* __restrict__ A, const C<R>* __restrict__ U,
+                                                          P3Params p, const C<R>* __restrict__ tw) {
+    constexpr int NT = kP3PwcThreads;
+    constexpr int OX = N / 2 + 1;
+    extern __shared__ unsigned char smem_raw[];
+    C<R>* twl = reinterpret_cast<C<R>*>(smem_raw);
+    C<R>* buf = twl + N;
+    const int tid = threadIdx.x;
+    // block -> (octant row, right-hand side), rows dealt to XCDs as in the
+    // sibling variant
+    const int K = p.nrhs;
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+    const int row = (q / K) * 8 + xcd;
+    if (row >= p.Oy * p.Oz) return;   // padding rows, uniform over the workgroup
+    const int r = q - (q / K) * K;
+    const int oz = row / p.Oy, oy = row - oz * p.Oy;
+    const int ny_sib = (oy == 0 || 2 * oy == p.My) ? 1 : 2;
+    const int nz_sib = (oz == 0 || 2 * oz == p.Mz) ? 1 : 2;
+    const int nsib = ny_sib * nz_sib;
+    const int nrows = 3 * nsib;   // LDS row sb * 3 + c, sibling sb = sz * ny_sib + sy
+    C<R>* base = A + (long long)r * p.s_r;
+    const long long s_c = p.s_c, s_y = p.s_y, s_z = p.s_z;
+    const int Mz = p.Mz, My = p.My;
+    auto rowp = [=](int rr) {
+        const int sb = rr / 3, c = rr - 3 * sb;
+        const int sz = sb >= ny_sib, sy = sb - sz * ny_sib;
+        const int z = sz ? Mz - oz : oz, y = sy ? My - oy : oy;
+        return base + z * s_z + y * s_y + c * s_c;
+    };
+    for (int m = tid; m < N; m += NT) twl[m] = tw[m];
+    rows_to_lds<R, N, NT>(buf, nrows, p.Nx, rowp);
+    __syncthreads();
+    ct_passes<R, true, N, 0, 1, NT, 12, true>(buf, twl, nrows, N, tid);   // Nx <= N / 2
+    const C<R>* Ur = U + (long long)row * 60 * OX;
+    for (int w = tid; w < nsib * N; w += NT) {
+        const int sb = w / N, xi = w - sb * N;
+        const int sz = sb >= ny_sib, sy = sb - sz * ny_sib;
+        const int fx = 2 * xi > N;
+        const int ox = fx ? N - xi : xi;
+        const unsigned mask = fold_mask(fx, sy, sz);
+        C<R> xv[3], yv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            C<R> v = buf[lds_pad((sb * 3 + c) * N + xi)];
+            if (mask & (1u << (4 * c))) { v.x = -v.x; v.y = -v.y; }
+            xv[c] = v;
+            yv[c] = mk<R>(0, 0);
+        }
+        orbit_product_pwc<R, 0>(yv, xv, Ur, ox, OX);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            C<R> v = yv[c];
+            if (mask & (1u << (4 * c))) { v.x = -v.x; v.y = -v.y; }
+            buf[lds_pad((sb * 3 + c) * N + xi)] = v;
+        }
+    }
+    __syncthreads();
+    ct_passes<R, false, N, 0, 1, NT, 12, false, true>(buf, twl, nrows, N, tid);   // crop to Nx
+    lds_to_rows<R, N, NT>(buf, nrows, p.Nx, rowp);
+}
+
 // lengths with a compile-time kernel
 #define VIE_P3_LENGTHS(X) X(8) X(16) X(32) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
 
@@ -766,6 +858,22 @@ static void launch_p3_quad_n(C<R>* A, const C<R>* U, const P3Params& p, const C<
         (void)hipGetLastError();
     });
     timed_launch(k_p3_quad<R, N>, dim3((unsigned)nblk), dim3(kP3QuadThreads), (unsigned)lds, s, A, U, p, tw);
+    VIE_HIP(hipGetLastError());
+}
+
+template <typename R, int N>
+static void launch_p3_pwc_n(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
+    const size_t lds = ((size_t)N + lds_pad(12 * N) + 2) * sizeof(C<R>);
+    const long long rows8 = ((long long)p.Oy * p.Oz + 7) / 8 * 8;
+    const long long nblk = rows8 * p.nrhs;
+    VIE_REQUIRE(nblk < (1LL << 31), -1, "x pass: too many workgroups");
+    VIE_REQUIRE(lds <= 160 * 1024, -1, "PWC x pass does not fit LDS");
+    static std::once_flag once;
+    std::call_once(once, [&] {
+        (void)hipFuncSetAttribute((const void*)k_p3_pwc<R, N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    });
+    timed_launch(k_p3_pwc<R, N>, dim3((unsigned)nblk), dim3(kP3PwcThreads), (unsigned)lds, s, A, U, p, tw);
     VIE_HIP(hipGetLastError());
 }
 
@@ -921,6 +1029,22 @@ void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStr
 }
 
 template <typename R>
+void launch_p3_pwc(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
+    VIE_REQUIRE(2 * p.Nx <= p.plan.n, -1, "x pass: fft length below 2 Nx");
+    switch (p.plan.n) {
+#define CASE(n_)                                        \
+    case n_:                                           \
+        launch_p3_pwc_n<R, n_>(A, U, p, tw, s);        \
+        return;
+        VIE_P3_LENGTHS(CASE)
+#undef CASE
+        default: break;
+    }
+    throw Error(-1, "the PWC x pass needs an fft length along x of 8, 16, 32, 64, 96, 128, 160, 192, 256, "
+                            "320, 384 or 512");
+}
+
+template <typename R>
 void launch_rows(bool fwd, C<R>* data, long long nrows, const FftPlan& plan, const C<R>* tw, hipStream_t s) {
     int rpb = std::max(1, std::min(16, 2048 / plan.n));
     int pitch = plan.n;
@@ -937,6 +1061,8 @@ template void launch_strided<double>(bool, const C<double>*, C<double>*, const S
                                      const C<double>*, const Epilogue<double>*, hipStream_t);
 template void launch_p3<float>(C<float>*, const C<float>*, const P3Params&, const C<float>*, hipStream_t);
 template void launch_p3<double>(C<double>*, const C<double>*, const P3Params&, const C<double>*, hipStream_t);
+template void launch_p3_pwc<float>(C<float>*, const C<float>*, const P3Params&, const C<float>*, hipStream_t);
+template void launch_p3_pwc<double>(C<double>*, const C<double>*, const P3Params&, const C<double>*, hipStream_t);
 template void launch_rows<double>(bool, C<double>*, long long, const FftPlan&, const C<double>*, hipStream_t);
 
 }  // namespace vie

@@ -20,11 +20,13 @@ struct StridedPass {
     int pitch;        // LDS row pitch (elements) >= tile
     long long in_s1, in_sc, in_s2, in_sk;
     long long out_s1, out_sc, out_s2, out_sk;
+    int nc;           // unknowns per voxel: the grid's z index splits into (rhs, component)
 };
 
 // Epilogue of the last pass: y = rhs + a(v) ga[l] x + b(v) gb[l] w
 // with w the transformed value, v the voxel (k = z, o2 = y, t = x), and
-// l = (component mod 4); a / b null mean the constants a_const / b_const.
+// l = (component mod 4) for the PWL basis, 0 for the PWC basis; a / b null
+// mean the constants a_const / b_const.
 template <typename R>
 struct Epilogue {
     const C<R>* x;

@@ -1,5 +1,8 @@
 // Materials (eq. 2, 7, 17), tested incident fields (eq. 27, 30-31) and
-// post-processing (Sec. IV-C, eq. 44, Sec. V-C).
+// post-processing (Sec. IV-C, eq. 44, Sec. V-C).  Vectors hold nc unknowns per
+// voxel: nc = 12 for the PWL basis (a = 4 p + l - 1), nc = 3 for the PWC basis
+// (the constant functions alone, unknown p), whose coefficients are the l = 1
+// ones of the PWL basis.
 #include "kernels.hpp"
 
 namespace vie {
@@ -36,7 +39,7 @@ void launch_materials(const double* eps_re, const double* sigma, double weps0, M
 // dV / D_dir^2 exp(-i k0 sgn c); the other two linear functions integrate
 // to zero.
 __global__ void k_planewave(double2* __restrict__ et, int Nx, int Ny, int Nz, double Dx, double Dy, double Dz,
-                            double k0, int pol, int dir, double sgn, double amp) {
+                            double k0, int pol, int dir, double sgn, double amp, int nc) {
     const long long V = (long long)Nx * Ny * Nz;
     const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (v >= V) return;
@@ -56,17 +59,21 @@ __global__ void k_planewave(double2* __restrict__ et, int Nx, int Ny, int Nz, do
         l1 = dv * sin(ka) / ka;
         l4 = -2.0 * sgn * (sin(ka) - ka * cos(ka)) / (k0 * k0) * dv / (D[dir] * D[dir]);
     }
-    for (int a_ = 0; a_ < 12; ++a_) et[a_ * V + v] = make_double2(0, 0);
+    for (int a_ = 0; a_ < nc; ++a_) et[a_ * V + v] = make_double2(0, 0);
+    if (nc == 3) {
+        et[pol * V + v] = make_double2(l1 * ph.x, l1 * ph.y);
+        return;
+    }
     et[(4 * pol + 0) * V + v] = make_double2(l1 * ph.x, l1 * ph.y);
     // times -i: (l4 i) * ph with l4 already carrying -2 sgn ...; value = -2i sgn(...) ph
     et[(4 * pol + dir + 1) * V + v] = make_double2(-l4 * ph.y, l4 * ph.x);
 }
 
 void launch_planewave(double2* et, int Nx, int Ny, int Nz, const double D[3], double k0, int pol, int dir,
-                      double sgn, double amp, hipStream_t s) {
+                      double sgn, double amp, int nc, hipStream_t s) {
     const long long V = (long long)Nx * Ny * Nz;
     hipLaunchKernelGGL(k_planewave, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, s, et, Nx, Ny, Nz, D[0], D[1],
-                       D[2], k0, pol, dir, sgn, amp);
+                       D[2], k0, pol, dir, sgn, amp, nc);
     VIE_HIP(hipGetLastError());
 }
 
@@ -75,15 +82,15 @@ void launch_planewave(double2* et, int Nx, int Ny, int Nz, const double D[3], do
 __global__ void k_dipoles(double2* __restrict__ et, const double* __restrict__ pos, const double* __restrict__ mom,
                           int nq, const double* __restrict__ glx, const double* __restrict__ glw,
                           const double2* __restrict__ chi, int Nx, int Ny, int Nz, double Dx, double Dy, double Dz,
-                          double k0, double weps0) {
+                          double k0, double weps0, int nc) {
     const long long V = (long long)Nx * Ny * Nz;
     const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     if (v >= V) return;
-    double2* out = et + (long long)r * 12 * V;
+    double2* out = et + (long long)r * nc * V;
     const double2 ch = chi[v];
     if (ch.x == 0.0 && ch.y == 0.0) {
-        for (int a = 0; a < 12; ++a) out[a * V + v] = make_double2(0, 0);
+        for (int a = 0; a < nc; ++a) out[a * V + v] = make_double2(0, 0);
         return;
     }
     const int ix = int(v % Nx), iy = int((v / Nx) % Ny), iz = int(v / ((long long)Nx * Ny));
@@ -128,35 +135,38 @@ __global__ void k_dipoles(double2* __restrict__ et, const double* __restrict__ p
             }
         }
     }
-    for (int a = 0; a < 12; ++a) out[a * V + v] = make_double2(acc[a][0], acc[a][1]);
+    if (nc == 3)
+        for (int p = 0; p < 3; ++p) out[p * V + v] = make_double2(acc[4 * p][0], acc[4 * p][1]);
+    else
+        for (int a = 0; a < 12; ++a) out[a * V + v] = make_double2(acc[a][0], acc[a][1]);
 }
 
 void launch_dipoles(double2* et, int nrhs, const double* pos, const double* mom, int nq, const double* glx,
                     const double* glw, const double2* chi, int Nx, int Ny, int Nz, const double D[3], double k0,
-                    double weps0, hipStream_t s) {
+                    double weps0, int nc, hipStream_t s) {
     const long long V = (long long)Nx * Ny * Nz;
     hipLaunchKernelGGL(k_dipoles, dim3((unsigned)((V + 127) / 128), nrhs), dim3(128), 0, s, et, pos, mom, nq, glx,
-                       glw, chi, Nx, Ny, Nz, D[0], D[1], D[2], k0, weps0);
+                       glw, chi, Nx, Ny, Nz, D[0], D[1], D[2], k0, weps0, nc);
     VIE_HIP(hipGetLastError());
 }
 
 // P^-1 b = c_e tau G^-1 e_t (eq. 17, 31)
 __global__ void k_rhs_prec(double2* __restrict__ rhs, const double2* __restrict__ et, const double2* __restrict__ tau,
-                           double g0, double g1, double2 ce, long long V, long long n) {
+                           double g0, double g1, double2 ce, long long V, long long n, int nc) {
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const long long v = i % V;
-    const int l = int((i / V) % 12) & 3;
+    const int l = nc == 12 ? int((i / V) % 12) & 3 : 0;
     const double gi = l == 0 ? g0 : g1;
     const double2 t = cmul(cmul(ce, tau[v]), et[i]);
     rhs[i] = make_double2(t.x * gi, t.y * gi);
 }
 
 void launch_rhs_prec(double2* rhs, const double2* et, const double2* tau, const double ginv[4], double2 ce,
-                     long long V, int nrhs, hipStream_t s) {
-    const long long n = 12 * V * nrhs;
+                     long long V, int nrhs, int nc, hipStream_t s) {
+    const long long n = nc * V * nrhs;
     hipLaunchKernelGGL(k_rhs_prec, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rhs, et, tau, ginv[0], ginv[1],
-                       ce, V, n);
+                       ce, V, n, nc);
     VIE_HIP(hipGetLastError());
 }
 
@@ -173,9 +183,9 @@ __global__ void k_fields(double2* __restrict__ e, const double2* __restrict__ x,
     e[i] = make_double2((xv.x * q.x + xv.y * q.y) / den, (xv.y * q.x - xv.x * q.y) / den);
 }
 
-void launch_fields(double2* e, const double2* x, const double2* chi, double2 ce, long long V, int nrhs,
+void launch_fields(double2* e, const double2* x, const double2* chi, double2 ce, long long V, int nrhs, int nc,
                    hipStream_t s) {
-    const long long n = 12 * V * nrhs;
+    const long long n = nc * V * nrhs;
     hipLaunchKernelGGL(k_fields, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, e, x, chi, ce, V, n);
     VIE_HIP(hipGetLastError());
 }
@@ -183,19 +193,19 @@ void launch_fields(double2* e, const double2* x, const double2* chi, double2 ce,
 // partial sums of 1/2 Re{conj(x) G x / (c_e chi)} (eq. 44), one per block
 __global__ void __launch_bounds__(256) k_power(double* __restrict__ partial, const double2* __restrict__ x,
                                                const double2* __restrict__ chi, double g0, double g1, double2 ce,
-                                               long long V) {
+                                               long long V, int nc) {
     __shared__ double red[256];
     const int r = blockIdx.y;
-    const double2* xr = x + (long long)r * 12 * V;
+    const double2* xr = x + (long long)r * nc * V;
     double acc = 0.0;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < 12 * V;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nc * V;
          i += (long long)gridDim.x * blockDim.x) {
         const long long v = i % V;
         const double2 ch = chi[v];
         if (ch.x == 0.0 && ch.y == 0.0) continue;
         const double2 q = cmul(ce, ch);
         const double req = q.x / (q.x * q.x + q.y * q.y);   // Re(1/q)
-        const int l = int(i / V) & 3;
+        const int l = nc == 12 ? int(i / V) & 3 : 0;
         const double2 xv = xr[i];
         acc += 0.5 * (l == 0 ? g0 : g1) * (xv.x * xv.x + xv.y * xv.y) * req;
     }
@@ -209,28 +219,30 @@ __global__ void __launch_bounds__(256) k_power(double* __restrict__ partial, con
 }
 
 void launch_power_partials(double* partial, const double2* x, const double2* chi, const double gram[4], double2 ce,
-                           long long V, int nrhs, int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_power, dim3(nblocks, nrhs), dim3(256), 0, s, partial, x, chi, gram[0], gram[1], ce, V);
+                           long long V, int nrhs, int nc, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_power, dim3(nblocks, nrhs), dim3(256), 0, s, partial, x, chi, gram[0], gram[1], ce, V, nc);
     VIE_HIP(hipGetLastError());
 }
 
-// 1/2 sigma (sum_p |e^{p1}|^2 + 1/12 sum_{p, l>1} |e^{pl}|^2)
+// 1/2 sigma (sum_p |e^{p1}|^2 + 1/12 sum_{p, l>1} |e^{pl}|^2); PWC: the first sum
 __global__ void k_power_density(double* __restrict__ p, const double2* __restrict__ e,
-                                const double* __restrict__ sigma, long long V) {
+                                const double* __restrict__ sigma, long long V, int nc) {
     const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     if (v >= V) return;
-    const double2* er = e + (long long)r * 12 * V;
+    const double2* er = e + (long long)r * nc * V;
     double acc = 0.0;
-    for (int a = 0; a < 12; ++a) {
+    for (int a = 0; a < nc; ++a) {
         const double2 z = er[a * V + v];
-        acc += ((a & 3) == 0 ? 1.0 : 1.0 / 12.0) * (z.x * z.x + z.y * z.y);
+        acc += ((nc == 3 || (a & 3) == 0) ? 1.0 : 1.0 / 12.0) * (z.x * z.x + z.y * z.y);
     }
     p[(long long)r * V + v] = 0.5 * sigma[v] * acc;
 }
 
-void launch_power_density(double* p, const double2* e, const double* sigma, long long V, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(k_power_density, dim3((unsigned)((V + 255) / 256), nrhs), dim3(256), 0, s, p, e, sigma, V);
+void launch_power_density(double* p, const double2* e, const double* sigma, long long V, int nrhs, int nc,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_power_density, dim3((unsigned)((V + 255) / 256), nrhs), dim3(256), 0, s, p, e, sigma, V,
+                       nc);
     VIE_HIP(hipGetLastError());
 }
 

@@ -49,7 +49,7 @@ struct Layout {
 template <typename R>
 static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layout& L, vie_solve_stats* st,
                std::vector<double>& bnorm) {
-    const long long n = 12 * c.V;
+    const long long n = (long long)c.nc * c.V;
     const int m = o.restart;
     const bool ir = (sizeof(R) == 4);
     const int nb = blocks_for(n);
@@ -264,7 +264,7 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
 
 int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2* x, vie_solve_stats* st) {
     auto t0 = std::chrono::steady_clock::now();
-    const long long n = 12 * c.V;
+    const long long n = (long long)c.nc * c.V;
     const int m = o.restart;
     const int nb = blocks_for(n);
     // workspace layout
@@ -301,7 +301,7 @@ int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2*
 
     const double dv = c.D[0] * c.D[1] * c.D[2];
     const double ginv[4] = {1 / dv, 12 / dv, 12 / dv, 12 / dv};
-    launch_rhs_prec(L.rhs, et, c.mat.tau, ginv, make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.stream);
+    launch_rhs_prec(L.rhs, et, c.mat.tau, ginv, make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.nc, c.stream);
     std::vector<double> bnorm;
     norms<double>(c, L.rhs, n, nrhs, L.npart, L.bn, bnorm);
     for (int r = 0; r < nrhs; ++r)

@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(256) k_strided_ct(const C<R>* in, C<R>* out, S
     const int tid = threadIdx.x;
     const int t0 = blockIdx.x * T;
     const long long o2 = blockIdx.y;
-    const int o1 = blockIdx.z, rr = o1 / 12, cc = o1 - 12 * rr;
+    const int o1 = blockIdx.z, rr = o1 / p.nc, cc = o1 - p.nc * rr;
     const int tw_n = min(T, p.n_inner - t0);
     const C<R>* src = in + rr * p.in_s1 + cc * p.in_sc + o2 * p.in_s2 + t0;
     for (int m = tid; m < N; m += NT) twl[m] = tw[m];
@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(256) k_strided_ct(const C<R>* in, C<R>* out, S
     else ct_passes<R, FWD, N, 0, 1, NT, T>(buf, twl, T, N, tid);
     const long long obase = rr * p.out_s1 + cc * p.out_sc;
     C<R>* dst = out + obase + o2 * p.out_s2 + t0;
-    const int l = cc & 3;
+    const int l = p.nc == 12 ? (cc & 3) : 0;
 #pragma unroll
     for (int i = 0; i < LPT; ++i) {
         const int idx = tid + i * NT;

@@ -1,6 +1,7 @@
 // Autotuner for the launch shapes of the operator product: times each
 // candidate with HIP events on the context stream and keeps the fastest per
-// (precision, nrhs).  The candidates only change the work distribution; the
+// (precision, nrhs).  The candidates only change the work distribution (for
+// the PWC basis, only the strided passes' tiles); the
 // staged x-pass variant adds the terms of the block product in another order
 // than the other two, so results agree to rounding.
 #include <vector>
@@ -28,7 +29,7 @@ static double time_apply(Ctx& c, int nrhs, const C<R>* x, C<R>* y, int reps) {
 
 template <typename R>
 static Tune tune_t(Ctx& c, int nrhs, double* best_ms) {
-    const size_t n = (size_t)12 * c.V * nrhs;
+    const size_t n = (size_t)c.nc * c.V * nrhs;
     C<R>* x = nullptr;
     C<R>* y = nullptr;
     VIE_HIP(hipMalloc(&x, n * sizeof(C<R>)));
@@ -39,6 +40,7 @@ static Tune tune_t(Ctx& c, int nrhs, double* best_ms) {
     for (int var = 0; var <= 4; ++var)
         for (int sb : {1, 2, 4}) {
             if (var >= 1 && sb != 1) continue;
+            if (c.nc == 3 && var != 1) continue;   // one x-pass kernel for the PWC basis: tiles only
             if (var == 0 && p3_ct_supported(c.M[0]) && !p3_ct_fits((int)sizeof(C<R>), c.M[0])) continue;
             if (var == 2 && !p3_quad_fits((int)sizeof(C<R>), c.M[0])) continue;
             if (var == 3 && !p3_pref_fits(c.M[0])) continue;

@@ -1,0 +1,260 @@
+"""The PWC basis on the device (Sec. V: 3 unknowns per voxel, 6 unique
+tensors) against the oracle's PWC discretisation, the l = 1 restriction of
+the PWL system: operator products on the same blocks and on the device's own
+assembly (ragged sizes, several tiles), incident fields, right-hand side,
+fields and power, solves against dense LU, and on the 16^3 sphere the
+paper's PWC-vs-PWL comparison against the Mie series."""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import vie_inputs as vi
+from oracle import incident, mie, physics, post, pwc, solve, toeplitz
+from tests.layout import relerr, unique_from_full, vec_from_lib, vec_to_lib, vox_to_lib
+
+pytestmark = pytest.mark.gpu
+
+F = 298e6
+K = physics.k0(F)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def vie(torch):
+    import paper_1902_02196_amd as v
+    return v
+
+
+@functools.lru_cache(None)
+def _T3(N, D):
+    return pwc.blocks_from_pwl(toeplitz.toeplitz_full(N, D, K))
+
+
+@functools.lru_cache(None)
+def _T12(N, D):
+    return toeplitz.toeplitz_full(N, D, K)
+
+
+def _ctx(vie, N, D, fft=None, blocks=None):
+    c = vie.Context(0)
+    c.set_grid(N, D, F, fft)
+    c.set_basis(3)
+    if blocks is not None:
+        c.set_toeplitz(unique_from_full(blocks))
+    return c
+
+
+def _dev(torch, x, dtype):
+    return torch.from_numpy(vec_to_lib(x)[None]).to(device="cuda", dtype=dtype).contiguous()
+
+
+def _host(y):
+    return vec_from_lib(y[0].cpu().numpy())
+
+
+# (N, Delta, fft size or None): x lengths 8, 16, 32 and 96 (a compiled x-pass
+# length is required), a ragged last tile (Nx = 40 in tiles of 16), odd and
+# non-smooth y / z extents
+CASES = [((4, 4, 4), (0.005,) * 3, None), ((4, 5, 3), (0.006, 0.005, 0.004), None),
+         ((8, 3, 7), (0.005, 0.004, 0.006), None), ((5, 6, 4), (0.004, 0.005, 0.006), (16, 12, 8)),
+         ((16, 9, 5), (0.004,) * 3, None), ((40, 3, 2), (0.003, 0.004, 0.005), (96, 6, 4))]
+
+
+@pytest.mark.parametrize("N,D,fft", CASES)
+def test_pwc_products_same_blocks(vie, torch, N, D, fft):
+    """N x, P^-1 A x and A x on the device vs the oracle's voxel-pair sum,
+    both fed the oracle's PWL blocks (the device reads the 6 pulse tensors)."""
+    _say("PWC products %s fft %s" % (N, fft))
+    T = _T12(N, D)
+    T3 = pwc.blocks_from_pwl(T)
+    c = _ctx(vie, N, D, fft, T)
+    e, s = vi.ellipsoid_phantom(N, D, 21)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    tau, chi, er = physics.tau(e, s, F), physics.chi(e, s, F), physics.eps_r(e, s, F)
+    x = vi.complex_normal(22, (3,) + N)
+    refs = {vie.OP_N: pwc.direct_N(T3, x), vie.OP_PREC: pwc.apply_prec(T3, x, tau, D),
+            vie.OP_A: pwc.apply_A(T3, x, er, chi, D)}
+    for dtype, tol in ((torch.complex128, 1e-11), (torch.complex64, 2e-5)):
+        xd = _dev(torch, x, dtype)
+        for op, ref in refs.items():
+            yd = torch.empty_like(xd)
+            c.apply(xd, yd, op=op)
+            err = relerr(_host(yd), ref)
+            _say("  %s op %d err %.3e" % (dtype, op, err))
+            assert err < tol
+
+
+@pytest.mark.parametrize("N,D,fft", CASES[:3])
+def test_pwc_product_device_assembly(vie, torch, N, D, fft):
+    """The device's own assembly in the PWC product vs the oracle's blocks."""
+    T3 = _T3(N, D)
+    c = _ctx(vie, N, D, fft)
+    x = vi.complex_normal(23, (3,) + N)
+    xd = _dev(torch, x, torch.complex128)
+    yd = torch.empty_like(xd)
+    c.apply(xd, yd, op=vie.OP_N)
+    err = relerr(_host(yd), pwc.direct_N(T3, x))
+    _say("  PWC device assembly %s err %.3e" % (N, err))
+    assert err < 1e-9
+
+
+def test_pwc_length_not_compiled_is_refused(vie, torch):
+    c = _ctx(vie, (5, 4, 3), (0.005,) * 3)   # default fft length 10 along x
+    x = torch.zeros(c.vec_shape(1), dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    with pytest.raises(vie.VieError) as ei:
+        c.apply(x, y, op=vie.OP_N)
+    assert ei.value.code == vie.VIE_EINVAL and "PWC" in str(ei.value)
+
+
+def test_pwc_excitation_rhs_fields_power(vie, torch):
+    N, D = (8, 5, 6), (0.005, 0.006, 0.004)
+    c = _ctx(vie, N, D)
+    e, s = vi.ellipsoid_phantom(N, D, 24)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    tau, chi = physics.tau(e, s, F), physics.chi(e, s, F)
+    et = torch.empty(c.vec_shape(1), dtype=torch.complex128, device="cuda")
+    c.incident_planewave(et)
+    ref = pwc.restrict(incident.planewave_tested(N, D, K))
+    assert relerr(_host(et), ref) < 1e-13
+    b = torch.empty_like(et)
+    c.rhs_prec(et, b)
+    assert relerr(_host(b), pwc.rhs_prec(ref, tau, D, F)) < 1e-13
+    pos, mom = vi.dipoles_on_cylinder(25, 2, 0.03, N[2] * D[2])
+    ed = torch.empty(c.vec_shape(2), dtype=torch.complex128, device="cuda")
+    c.incident_dipoles(ed, pos, mom, nq=6)
+    refd = incident.dipoles_tested(N, D, F, pos, mom, chi != 0, nq=6)
+    for r in range(2):
+        assert relerr(vec_from_lib(ed[r].cpu().numpy()), pwc.restrict(refd[r])) < 1e-12
+    x = vi.complex_normal(26, (3,) + N) * (chi != 0)[None]
+    xd = _dev(torch, x, torch.complex128)
+    ef = torch.empty_like(xd)
+    c.fields(xd, ef)
+    eref = post.fields_from_currents(x, chi, F)
+    assert relerr(_host(ef), eref) < 1e-13
+    P = c.absorbed_power(xd)[0]
+    assert abs(P - pwc.absorbed_power(x, chi, D, F)) < 1e-12 * abs(P)
+    pd = torch.empty((1,) + tuple(reversed(N)), dtype=torch.float64, device="cuda")
+    c.power_density(ef, pd)
+    assert relerr(pd[0].cpu().numpy().transpose(2, 1, 0), pwc.power_density(eref, s)) < 1e-13
+
+
+@pytest.mark.parametrize("mode,tol,bound", [(0, 1e-12, 1e-9), (1, 1e-10, 1e-7)])
+def test_pwc_solve_matches_dense(vie, torch, mode, tol, bound):
+    N, D = (4, 4, 4), (0.005,) * 3
+    T3 = _T3(N, D)
+    c = _ctx(vie, N, D)
+    e, s = vi.sphere(N, D, 0.0101, 50.0, 0.7)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    tau = physics.tau(e, s, F)
+    et = pwc.restrict(incident.planewave_tested(N, D, K))
+    xref = pwc.solve_dense(T3, tau, D, pwc.rhs_prec(et, tau, D, F))
+    etd = _dev(torch, et, torch.complex128)
+    xd = torch.empty_like(etd)
+    code, st = c.solve(etd, xd, mode=mode, tol=tol, restart=20)
+    _say("  PWC solve mode %d: %s" % (mode, st[0]))
+    assert code == vie.VIE_OK and st[0]["converged"]
+    assert relerr(_host(xd), xref) < bound
+
+
+def test_basis_switch_keeps_pwl(vie, torch):
+    """A context switched to PWC and back gives the PWL product bit for bit."""
+    N, D = (8, 4, 6), (0.005,) * 3
+    x = torch.from_numpy(vec_to_lib(vi.complex_normal(27, (12,) + N))[None]).cuda()
+    a = vie.Context(0)
+    a.set_grid(N, D, F)
+    ya = torch.empty_like(x)
+    a.apply(x, ya, op=vie.OP_N)
+    a.set_basis(3)
+    x3 = torch.from_numpy(vec_to_lib(vi.complex_normal(28, (3,) + N))[None]).cuda()
+    y3 = torch.empty_like(x3)
+    a.apply(x3, y3, op=vie.OP_N)
+    a.set_basis(12)
+    yb = torch.empty_like(x)
+    a.apply(x, yb, op=vie.OP_N)
+    assert torch.equal(ya, yb)
+    with pytest.raises(vie.VieError):
+        a.set_basis(4)
+
+
+def test_pwc_delta_columns_phantom64(vie, torch):
+    """Full size (64^3, fft length 128): a unit current at one voxel and
+    component makes the PWC product's output the pulse-pulse column of the
+    blocks T(m - n0), checked at sampled voxels."""
+    N, D = (64, 64, 64), (0.003,) * 3
+    c = _ctx(vie, N, D)
+    c.autotune(vie.C64, 1)
+    g = vi.rng(7101)
+    sources = [((0, 0, 0), 0), ((31, 32, 30), 1), ((63, 17, 40), 2), ((10, 63, 63), 1)]
+    for dtype, tol in ((torch.complex128, 1e-10), (torch.complex64, 1e-5)):
+        x = torch.zeros((len(sources), 3, N[2], N[1], N[0]), dtype=dtype, device="cuda")
+        for r, (n0, p) in enumerate(sources):
+            x[r, p, n0[2], n0[1], n0[0]] = 1.0
+        y = torch.empty_like(x)
+        c.apply(x, y, op=vie.OP_N)
+        worst = 0.0
+        for r, (n0, p) in enumerate(sources):
+            ms = {tuple(n0), (0, 0, 0), (63, 63, 63)}
+            while len(ms) < 12:
+                ms.add(tuple(int(g.integers(0, 64)) for _ in range(3)))
+            ms = sorted(ms)
+            offs = np.array([[m[i] - n0[i] for i in range(3)] for m in ms])
+            ref = toeplitz.galerkin_blocks(offs, D, K)[:, list(pwc.PWL_INDEX)][:, :, 4 * p]
+            got = np.stack([y[r, :, m[2], m[1], m[0]].cpu().numpy() for m in ms])
+            err = float(np.abs(got - ref).max() / np.abs(ref).max())
+            worst = max(worst, err)
+            assert err < tol, (dtype, n0, p, err)
+        _say("  PWC 64^3 %s: worst sampled error %.3e" % (dtype, worst))
+
+
+def test_pwc_sphere16_vs_pwl_and_mie(vie, torch):
+    """16^3 sphere (r = 3 cm, eps' 50, sigma 0.7 S/m, 5 mm, 298 MHz): the
+    device's PWC solution against the oracle's PWC FFT-GMRES element by
+    element, and the paper's comparison: the PWL absorbed power is far closer
+    to the Mie series than the PWC one on the same voxels (Sec. V-A)."""
+    N, D = (16, 16, 16), (0.005,) * 3
+    e, s = vi.sphere(N, D, 0.03, 50.0, 0.7)
+    tau, chi = physics.tau(e, s, F), physics.chi(e, s, F)
+    T3 = _T3(N, D)
+    Ch = pwc.spectrum(T3, (32, 32, 32))
+    b = pwc.rhs_prec(pwc.restrict(incident.planewave_tested(N, D, K)), tau, D, F)
+    xref, info = solve.gmres(lambda v: pwc.apply_prec(T3, v, tau, D, Nx_fn=lambda _t, u: pwc.fft_N(Ch, u)), b,
+                             restart=50, tol=1e-11)
+    assert info["converged"]
+    p_ref = pwc.absorbed_power(xref, chi, D, F)
+    req = (np.count_nonzero(chi) * D[0] * D[1] * D[2] * 3 / (4 * np.pi)) ** (1 / 3)
+    pm = mie.absorbed_power(req, 50.0, 0.7, F)
+    powers = {}
+    for nc in (3, 12):
+        c = vie.Context(0)
+        c.set_grid(N, D, F)
+        c.set_basis(nc)
+        c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+        et = torch.empty(c.vec_shape(1), dtype=torch.complex128, device="cuda")
+        c.incident_planewave(et)
+        x = torch.empty_like(et)
+        code, st = c.solve(et, x, mode=vie.SOLVE_FP32_IR, tol=1e-10)
+        assert code == vie.VIE_OK
+        powers[nc] = c.absorbed_power(x)[0]
+        if nc == 3:
+            err = relerr(_host(x), xref)
+            _say("  PWC: %d iterations, solution vs oracle %.3e" % (st[0]["iterations"], err))
+            assert err < 1e-8
+            assert abs(powers[3] - p_ref) < 1e-8 * p_ref
+    e3, e12 = (abs(powers[k] - pm) / pm for k in (3, 12))
+    _say("  P_abs error vs Mie (r_eq %.4f m): PWC %.3e, PWL %.3e" % (req, e3, e12))
+    assert e12 < 0.02 and e3 > 10 * e12

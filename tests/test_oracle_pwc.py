@@ -119,3 +119,22 @@ def test_pwc_farther_from_mie_than_pwl():
     err3 = abs(pwc.absorbed_power(x3, chi, D, F) - Pm) / Pm
     print("PWL %.4f PWC %.4f" % (err12, err3))
     assert err3 > 2 * err12
+
+
+def test_operators_are_pwl_restricted():
+    """N x, P^-1 A x and A x of the PWC system equal the PWL operators applied
+    to the vector with zero linear coefficients, read at the unknowns a = 4 p."""
+    N, D = (3, 4, 2), (0.005, 0.004, 0.006)
+    T = _T(N, D)
+    T3 = pwc.blocks_from_pwl(T)
+    e, s = vi.ellipsoid_phantom(N, D, 15)
+    tau, chi, er = physics.tau(e, s, F), physics.chi(e, s, F), physics.eps_r(e, s, F)
+    x3 = vi.complex_normal(16, (3,) + N)
+    x12 = np.zeros((12,) + N, dtype=np.complex128)
+    x12[list(pwc.PWL_INDEX)] = x3
+    pairs = [(pwc.direct_N(T3, x3), matvec.direct_N(T, x12)),
+             (pwc.apply_prec(T3, x3, tau, D), matvec.apply_prec(T, x12, tau, D)),
+             (pwc.apply_A(T3, x3, er, chi, D), matvec.apply_A(T, x12, er, chi, D))]
+    for a, b in pairs:
+        b3 = pwc.restrict(b)
+        assert np.abs(a - b3).max() < 1e-13 * np.abs(b3).max()
