@@ -10,7 +10,7 @@ constexpr int kTpb = 256;
 
 // Basis vectors are streamed once per Gram-Schmidt pass and a whole basis is
 // larger than the caches, so their loads are non-temporal (stream_load).
-constexpr int kGroup = 8;   // basis vectors per sweep of the dot kernel
+constexpr int kGroup = 8;   // basis vectors per workgroup of the dot kernel
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -82,8 +82,10 @@ __device__ __forceinline__ void dot_group(double2* __restrict__ partial, const t
     __syncthreads();
 }
 
-// partial sums of conj(V_i) w for i < nvec, groups of kGroup vectors and one
-// remainder group (vectors read in 16-byte units; n a multiple of the unit)
+// partial sums of conj(V_i) w for i < nvec: workgroup (b, r, g) takes group g
+// of kGroup basis vectors (the last group may hold fewer) over its share of
+// the elements, so the groups stream side by side (vectors read in 16-byte
+// units; n a multiple of the unit)
 template <typename R>
 __global__ void __launch_bounds__(kTpb) k_multidot(double2* __restrict__ partial, const C<R>* __restrict__ Vb,
                                                    long long ldv, int nvec, const C<R>* __restrict__ w, long long n,
@@ -95,15 +97,13 @@ __global__ void __launch_bounds__(kTpb) k_multidot(double2* __restrict__ partial
     const T* V = reinterpret_cast<const T*>(Vb + r * rsv);
     const T* wr = reinterpret_cast<const T*>(w + r * rsw);
     const long long nu = n / U::per, ldu = ldv / U::per;
-    static_assert(kGroup == 8, "the remainder cases below cover groups of 8");
-    int i0 = 0;
-    for (; i0 + kGroup <= nvec; i0 += kGroup) dot_group<R, kGroup>(partial, V, wr, ldu, nu, i0, nvec, r, red);
-    switch (nvec - i0) {
-#define VIE_DOT_REM(g_) \
+    static_assert(kGroup == 8, "the group sizes below cover 1 to 8");
+    const int i0 = blockIdx.z * kGroup;
+    switch (min(kGroup, nvec - i0)) {   // uniform over the workgroup
+#define VIE_DOT_G(g_) \
     case g_: dot_group<R, g_>(partial, V, wr, ldu, nu, i0, nvec, r, red); break;
-        VIE_DOT_REM(1) VIE_DOT_REM(2) VIE_DOT_REM(3) VIE_DOT_REM(4) VIE_DOT_REM(5) VIE_DOT_REM(6)
-        VIE_DOT_REM(7)
-#undef VIE_DOT_REM
+        VIE_DOT_G(1) VIE_DOT_G(2) VIE_DOT_G(3) VIE_DOT_G(4) VIE_DOT_G(5) VIE_DOT_G(6) VIE_DOT_G(7) VIE_DOT_G(8)
+#undef VIE_DOT_G
         default: break;
     }
 }
@@ -111,7 +111,9 @@ __global__ void __launch_bounds__(kTpb) k_multidot(double2* __restrict__ partial
 template <typename R>
 void launch_multidot(double2* partial, const C<R>* Vb, long long ldv, int nvec, const C<R>* w, long long n,
                      long long rsv, long long rsw, int nrhs, int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_multidot<R>, dim3(nblocks, nrhs), dim3(kTpb), 0, s, partial, Vb, ldv, nvec, w, n, rsv, rsw);
+    const unsigned ngroups = (unsigned)((nvec + kGroup - 1) / kGroup);
+    hipLaunchKernelGGL(k_multidot<R>, dim3(nblocks, nrhs, ngroups), dim3(kTpb), 0, s, partial, Vb, ldv, nvec, w, n,
+                       rsv, rsw);
     VIE_HIP(hipGetLastError());
 }
 

@@ -24,8 +24,11 @@ namespace vie {
 
 using cd = std::complex<double>;
 
+// workgroups of the Gram-Schmidt and norm kernels: up to 1024, at least 512
+// elements each (two per thread), so that vectors of a few MB (PWC basis,
+// small grids) still spread over all CUs
 static int blocks_for(long long n) {
-    long long b = (n + 256 * 8 - 1) / (256 * 8);
+    long long b = (n + 512 - 1) / 512;
     return (int)std::max(1LL, std::min(1024LL, b));
 }
 
