@@ -350,6 +350,11 @@ void vie_server_destroy(vie_server* s);
  * points x 16 B (complex128) = 1536 N_V (Tables III, V, VII, VIII). */
 size_t vie_unknowns_bytes_paper(int nx, int ny, int nz);
 
+/* The same count for ncomp unknowns per voxel: ncomp x 8 N_V x 16 B, with
+ * ncomp = 12 (PWL) or 3 (PWC, 384 N_V B; the PWC rows of the same tables).
+ * Returns 0 for other ncomp or non-positive sizes. */
+size_t vie_unknowns_bytes_basis(int nx, int ny, int nz, int ncomp);
+
 /* Device bytes this library needs to solve nrhs right-hand sides on the
  * grid with fft size 2N: resident operator, contrast, padded FFT buffers and
  * the Krylov basis of GMRES(restart) for the given mode. */

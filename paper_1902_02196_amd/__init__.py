@@ -103,6 +103,7 @@ _sig = {
     "vie_server_destroy": (None, [_vp]),
     "vie_server_set_operator_cache": (_i, [_vp, ctypes.c_size_t]),
     "vie_unknowns_bytes_paper": (ctypes.c_size_t, [_i, _i, _i]),
+    "vie_unknowns_bytes_basis": (ctypes.c_size_t, [_i, _i, _i, _i]),
     "vie_footprint_bytes": (_i, [_i, _i, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_size_t)]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -139,6 +140,11 @@ def _stream_ptr(stream):
 def unknowns_bytes_paper(nx, ny, nz):
     """Unknowns memory as the paper counts it: 12 x 8 N_V x 16 B."""
     return int(_lib.vie_unknowns_bytes_paper(nx, ny, nz))
+
+
+def unknowns_bytes_basis(nx, ny, nz, ncomp):
+    """The same count for ncomp unknowns per voxel (12 PWL, 3 PWC)."""
+    return int(_lib.vie_unknowns_bytes_basis(nx, ny, nz, ncomp))
 
 
 def footprint_bytes(nx, ny, nz, nrhs, mode, restart=50):

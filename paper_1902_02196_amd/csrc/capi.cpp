@@ -560,10 +560,12 @@ int vie_profile_read(vie_ctx* ctx, int kind, double* total_ms, int* launches, do
     });
 }
 
-size_t vie_unknowns_bytes_paper(int nx, int ny, int nz) {
-    if (nx < 1 || ny < 1 || nz < 1) return 0;
-    return (size_t)12 * 8 * (size_t)nx * ny * nz * 16;
+size_t vie_unknowns_bytes_basis(int nx, int ny, int nz, int ncomp) {
+    if (nx < 1 || ny < 1 || nz < 1 || (ncomp != 12 && ncomp != 3)) return 0;
+    return (size_t)ncomp * 8 * (size_t)nx * ny * nz * 16;
 }
+
+size_t vie_unknowns_bytes_paper(int nx, int ny, int nz) { return vie_unknowns_bytes_basis(nx, ny, nz, 12); }
 
 int vie_footprint_bytes(int nx, int ny, int nz, int nrhs, int mode, int restart, size_t* out) {
     return guarded([&] {

@@ -48,6 +48,26 @@ def test_unknowns_memory_matches_paper_tables():
         assert round(12 * nx * ny * nz / 1e6, digits) == pytest.approx(dofs, abs=1e-9)
 
 
+def test_pwc_unknowns_memory_matches_paper_tables():
+    """The PWC rows of Tables III, V, VII and VIII: 3 unknowns per voxel
+    (Sec. V), 24 N_V complex128 numbers."""
+    vie = _lib()
+    rows = []
+    for line in open(os.path.join(ROOT, "tests", "golden", "unknowns_memory_pwc.txt")):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            nx, ny, nz, dofs, mem = line.split()
+            rows.append((int(nx), int(ny), int(nz), dofs, float(mem)))
+    assert len(rows) == 16
+    for nx, ny, nz, dofs, mem in rows:
+        b = vie.unknowns_bytes_basis(nx, ny, nz, 3)
+        assert round(b / 2 ** 30, 3) == pytest.approx(mem, abs=1e-9), (nx, ny, nz)
+        digits = len(dofs.split(".")[1]) if "." in dofs else 0
+        assert round(3 * nx * ny * nz / 1e6, digits) == pytest.approx(float(dofs), abs=1e-9), (nx, ny, nz)
+        assert vie.unknowns_bytes_basis(nx, ny, nz, 12) == 4 * b == vie.unknowns_bytes_paper(nx, ny, nz)
+    assert vie.unknowns_bytes_basis(4, 4, 4, 5) == 0
+
+
 def test_footprint_model_counts_basis_and_buffers():
     vie = _lib()
     n = 64
