@@ -12,8 +12,9 @@
 * The 16^3 sphere is solved whole on both sides (device GMRES vs the
   oracle's GMRES on its own FFT product) and compared element by element.
 
-Grids: 64 x 64 x 64 at 3 mm, 298 MHz (single right-hand side) and
-96 x 128 x 128 at 2 mm, 298 MHz with 16 right-hand sides in one batch.
+Grids: 64 x 64 x 64 at 3 mm, 298 MHz (single right-hand side),
+96 x 128 x 128 at 2 mm, 298 MHz with 16 right-hand sides in one batch, and
+the whole-body 128 x 256 x 384 at 5 mm, 128 MHz.
 """
 import sys
 
@@ -64,7 +65,7 @@ def _samples(N, n0, g, count):
     return sorted(pts)
 
 
-def _check_delta_columns(vie, torch, c, N, D, sources, dtype, tol, tag):
+def _check_delta_columns(vie, torch, c, N, D, sources, dtype, tol, tag, k0=K):
     """sources: list of (n0 (ix, iy, iz), component a), one per right-hand side."""
     nrhs = len(sources)
     x = torch.zeros((nrhs, 12, N[2], N[1], N[0]), dtype=dtype, device="cuda")
@@ -77,7 +78,7 @@ def _check_delta_columns(vie, torch, c, N, D, sources, dtype, tol, tag):
     for r, (n0, a) in enumerate(sources):
         ms = _samples(N, n0, g, 14)
         offs = np.array([[m[i] - n0[i] for i in range(3)] for m in ms])
-        ref = toeplitz.galerkin_blocks(offs, D, K)[:, :, a]          # [S, 12]
+        ref = toeplitz.galerkin_blocks(offs, D, k0)[:, :, a]         # [S, 12]
         got = np.stack([y[r, :, m[2], m[1], m[0]].cpu().numpy() for m in ms])
         scale = np.abs(ref).max()
         err = float(np.abs(got - ref).max() / scale)
@@ -107,6 +108,25 @@ def test_delta_columns_head_batch16(vie, torch):
     _say("  autotune c64 x16: %s %.3f ms" % (choice, ms))
     _check_delta_columns(vie, torch, c, N, D, sources, torch.complex64, 1e-5, "head c64 x16")
     _check_delta_columns(vie, torch, c, N, D, sources[:4], torch.complex128, 1e-10, "head c128 x4")
+
+
+def test_delta_columns_body_box(vie, torch):
+    """The whole-body grid (128 x 256 x 384 at 5 mm, 128 MHz; fft lengths 256,
+    512, 768) in the shapes the benchmark autotunes: complex64 with two
+    right-hand sides per product (the solve groups), complex128 with one."""
+    N, D, f = (128, 256, 384), (0.005,) * 3, 128e6
+    k0 = physics.k0(f)
+    c = vie.Context(0)
+    c.set_grid(N, D, f)
+    assert c.fft_size == (256, 512, 768)
+    g = vi.rng(7003)
+    sources = [((0, 255, 383), 3), (tuple(int(g.integers(0, N[i])) for i in range(3)), 9)]
+    choice, ms = c.autotune(vie.C64, 2)
+    _say("  autotune c64 x2: %s %.3f ms" % (choice, ms))
+    _check_delta_columns(vie, torch, c, N, D, sources, torch.complex64, 1e-5, "body c64 x2", k0)
+    choice, ms = c.autotune(vie.C128, 1)
+    _say("  autotune c128 x1: %s %.3f ms" % (choice, ms))
+    _check_delta_columns(vie, torch, c, N, D, sources[1:], torch.complex128, 1e-10, "body c128", k0)
 
 
 def test_complex_symmetry_full_size(vie, torch):
