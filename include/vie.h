@@ -357,7 +357,8 @@ size_t vie_unknowns_bytes_basis(int nx, int ny, int nz, int ncomp);
 
 /* Device bytes this library needs to solve nrhs right-hand sides on the
  * grid with fft size 2N: resident operator, contrast, padded FFT buffers and
- * the Krylov basis of GMRES(restart) for the given mode. */
+ * the Krylov basis of GMRES(restart) for the given mode, PWL basis (a PWC
+ * solve needs a quarter of the vector, FFT and basis bytes). */
 int vie_footprint_bytes(int nx, int ny, int nz, int nrhs, int mode, int restart, size_t* out);
 
 #ifdef __cplusplus
