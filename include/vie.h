@@ -123,8 +123,11 @@ int vie_set_grid(vie_ctx* ctx, int nx, int ny, int nz, double dx, double dy, dou
  * members of the PWL basis, so its Galerkin system is the PWL one restricted
  * to a = 4 p: operator tensors u = 10 pq (ll = 11) of the same assembled
  * operator, Gram dV.  Vectors of every later call hold ncomp unknowns per
- * voxel.  Clears the launch-shape choices; may be called at any time.
- * Returns VIE_EINVAL for other values. */
+ * voxel.  Clears the launch-shape choices; may be called at any time.  The
+ * PWC product needs an fft length along x of 8, 16, 32, 64, 96, 128, 160,
+ * 192, 256, 320, 384 or 512: a later vie_set_grid without fft_size picks the
+ * smallest of them >= 2 Nx for a PWC context; products on other lengths
+ * return VIE_EINVAL.  Returns VIE_EINVAL for ncomp other than 12 or 3. */
 int vie_set_basis(vie_ctx* ctx, int ncomp);
 
 /* Debug / parity entry: replace the operator by caller-supplied unique block

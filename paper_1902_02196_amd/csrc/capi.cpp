@@ -126,6 +126,14 @@ int vie_set_grid(vie_ctx* ctx, int nx, int ny, int nz, double dx, double dy, dou
             if (!fft_size)
                 while (!smooth235(M[i])) M[i] += 2;
         }
+        // the PWC x pass exists for the compiled lengths only: a PWC context
+        // takes the smallest compiled length >= 2 Nx along x when it has one
+        if (!fft_size && c.nc == 3 && !p3_ct_supported(M[0]))
+            for (int m = M[0]; m <= 512; m += 2)
+                if (p3_ct_supported(m)) {
+                    M[0] = m;
+                    break;
+                }
         for (int i = 0; i < 3; ++i) {
             VIE_REQUIRE(M[i] >= 2 * N[i] - 1 && M[i] % 2 == 0 && smooth235(M[i]), VIE_EINVAL,
                         "fft size must be even, 2/3/5-smooth and >= 2N-1");

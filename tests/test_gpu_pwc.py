@@ -112,13 +112,25 @@ def test_pwc_product_device_assembly(vie, torch, N, D, fft):
     assert err < 1e-9
 
 
-def test_pwc_length_not_compiled_is_refused(vie, torch):
-    c = _ctx(vie, (5, 4, 3), (0.005,) * 3)   # default fft length 10 along x
+def test_pwc_fft_length_choice(vie, torch):
+    """A grid set before the switch keeps its default x length (10 for Nx = 5),
+    which the PWC product refuses; a grid set on a PWC context takes the
+    smallest compiled length >= 2 Nx (16) and gives the oracle's product."""
+    N, D = (5, 4, 3), (0.005,) * 3
+    c = _ctx(vie, N, D)
+    assert c.fft_size == (10, 8, 6)
     x = torch.zeros(c.vec_shape(1), dtype=torch.complex128, device="cuda")
     y = torch.empty_like(x)
     with pytest.raises(vie.VieError) as ei:
         c.apply(x, y, op=vie.OP_N)
     assert ei.value.code == vie.VIE_EINVAL and "PWC" in str(ei.value)
+    c.set_grid(N, D, F)
+    assert c.fft_size == (16, 8, 6)
+    xs = vi.complex_normal(32, (3,) + N)
+    xd = _dev(torch, xs, torch.complex128)
+    yd = torch.empty_like(xd)
+    c.apply(xd, yd, op=vie.OP_N)
+    assert relerr(_host(yd), pwc.direct_N(_T3(N, D), xs)) < 1e-9
 
 
 def test_pwc_excitation_rhs_fields_power(vie, torch):
