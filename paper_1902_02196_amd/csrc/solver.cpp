@@ -24,11 +24,18 @@ namespace vie {
 
 using cd = std::complex<double>;
 
-// workgroups of the Gram-Schmidt and norm kernels: up to 1024, at least 512
-// elements each (two per thread), so that vectors of a few MB (PWC basis,
-// small grids) still spread over all CUs
+// workgroups of the update and norm kernels: up to 1024, at least 1024
+// elements each, so that vectors of a few MB (PWC basis, small grids) still
+// spread over all CUs
 static int blocks_for(long long n) {
-    long long b = (n + 512 - 1) / 512;
+    long long b = (n + 1024 - 1) / 1024;
+    return (int)std::max(1LL, std::min(1024LL, b));
+}
+
+// workgroups per group of basis vectors of the dot kernel (whose groups run
+// side by side): up to 1024, at least 2048 elements each
+static int dot_blocks_for(long long n) {
+    long long b = (n + 2048 - 1) / 2048;
     return (int)std::max(1LL, std::min(1024LL, b));
 }
 
@@ -55,7 +62,7 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
     const long long n = (long long)c.nc * c.V;
     const int m = o.restart;
     const bool ir = (sizeof(R) == 4);
-    const int nb = blocks_for(n);
+    const int nb = blocks_for(n), nbd = dot_blocks_for(n);
     // consecutive basis vectors are staggered by a little over 4 KiB, so that
     // the j + 1 streams the Gram-Schmidt kernels read side by side do not
     // start at equal offsets modulo large powers of two
@@ -199,8 +206,8 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
                 const int jw = pass ? -1 : j;
                 {
                     ProfScope ps(c.prof, c.stream, VIE_K_GS_DOT, dot_bytes);
-                    launch_multidot<R>(L.partial, Vb, ldv, nvec, w, n, n, n, na, nb, c.stream);
-                    launch_reduce_partials(hp, L.coef, L.partial, nvec, nb, na, L.ivn, ivld, jw, c.stream);
+                    launch_multidot<R>(L.partial, Vb, ldv, nvec, w, n, n, n, na, nbd, c.stream);
+                    launch_reduce_partials(hp, L.coef, L.partial, nvec, nbd, na, L.ivn, ivld, jw, c.stream);
                 }
                 {
                     ProfScope ps(c.prof, c.stream, VIE_K_GS_UPDATE, upd_bytes);
@@ -278,7 +285,7 @@ int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2*
         return o_;
     };
     const size_t o_rhs = take((size_t)nrhs * n * 16), o_r = take((size_t)nrhs * n * 16);
-    const size_t o_part = take((size_t)nrhs * (m + 1) * nb * 16);
+    const size_t o_part = take((size_t)nrhs * (m + 1) * std::max(nb, dot_blocks_for(n)) * 16);
     const size_t o_h1 = take((size_t)nrhs * (m + 1) * 16), o_h2 = take((size_t)nrhs * (m + 1) * 16);
     const size_t o_coef = take((size_t)nrhs * (m + 1) * 16), o_ivn = take((size_t)nrhs * (m + 1) * 8);
     const size_t o_y = take((size_t)nrhs * m * 16);
