@@ -203,6 +203,14 @@ int vie_solve(vie_ctx* ctx, const vie_solve_opts* opts, int nrhs, const void* e_
  * elsewhere (eq. 6); complex128 device arrays in x layout. */
 int vie_fields(vie_ctx* ctx, int nrhs, const void* x, void* e);
 
+/* Total field coefficients everywhere in the box, tissue and air, through
+ * one operator product (Sec. IV-C): G e = e_t + (N - G) x / c_e, i.e.
+ * e = G^-1 (e_t + (N x - G x) / c_e) with the tested incident field e_t.  On
+ * tissue voxels this equals vie_fields at the exact discrete solution.
+ * e_t, x and e: complex128 device arrays in x layout; e must not overlap x
+ * (it receives N x first).  Requires vie_set_grid. */
+int vie_total_field(vie_ctx* ctx, int nrhs, const void* e_t, const void* x, void* e);
+
 /* Absorbed power P_abs = 1/2 Re{x^* (c_e M_chi)^-1 G x} (eq. 44) per
  * right-hand side, into p_abs_host[nrhs] (W). */
 int vie_absorbed_power(vie_ctx* ctx, int nrhs, const void* x, double* p_abs_host);

@@ -110,6 +110,13 @@ def solve_dense(T3, tau, Delta, rhs_prec_):
     return x.reshape(rhs_prec_.shape)
 
 
+def total_field(T3, x, e_t3, Delta, freq_hz, Nx_fn=direct_N):
+    """Total field everywhere in the box through one operator product
+    (Sec. IV-C): dV e = e_t + (N x - dV x) / c_e."""
+    dv = Delta[0] * Delta[1] * Delta[2]
+    return (e_t3 + (Nx_fn(T3, x) - dv * x) / physics.c_e(freq_hz)) / dv
+
+
 def absorbed_power(x3, chi, Delta, freq_hz):
     """P_abs = 1/2 Re{ x^* (c_e M_chi)^-1 dV x } (eq. 44 with G = dV I)."""
     dv = Delta[0] * Delta[1] * Delta[2]

@@ -85,6 +85,7 @@ _sig = {
     "vie_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
     "vie_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _vp, _vp, ctypes.POINTER(SolveStats)]),
     "vie_fields": (_i, [_vp, _i, _vp, _vp]),
+    "vie_total_field": (_i, [_vp, _i, _vp, _vp, _vp]),
     "vie_absorbed_power": (_i, [_vp, _i, _vp, _dp]),
     "vie_power_density": (_i, [_vp, _i, _vp, _vp]),
     "vie_copy": (_i, [_vp, _vp, _vp, ctypes.c_longlong]),
@@ -296,6 +297,14 @@ class Context:
         n = x.shape[0]
         _check(_lib.vie_fields(self._h, n, _tensor_ptr(x, torch.complex128, self.vec_shape(n)),
                                _tensor_ptr(out, torch.complex128, self.vec_shape(n))))
+
+    def total_field(self, e_t, x, out):
+        """Total field coefficients in the whole box (one operator product)."""
+        import torch
+        n = x.shape[0]
+        _check(_lib.vie_total_field(self._h, n, _tensor_ptr(e_t, torch.complex128, self.vec_shape(n)),
+                                    _tensor_ptr(x, torch.complex128, self.vec_shape(n)),
+                                    _tensor_ptr(out, torch.complex128, self.vec_shape(n))))
 
     def absorbed_power(self, x):
         import torch

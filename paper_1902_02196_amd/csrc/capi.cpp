@@ -418,6 +418,22 @@ int vie_fields(vie_ctx* ctx, int nrhs, const void* x, void* e) {
     });
 }
 
+int vie_total_field(vie_ctx* ctx, int nrhs, const void* e_t, const void* x, void* e) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_grid, VIE_ESTATE, "no grid");
+        VIE_REQUIRE(nrhs >= 1 && e_t && x && e, VIE_EINVAL, "bad arguments");
+        VIE_REQUIRE(e != x, VIE_EINVAL, "e and x must not overlap");
+        apply_op<double>(c, OP_N, nrhs, static_cast<const double2*>(x), static_cast<double2*>(e), nullptr);
+        const double dv = c.D[0] * c.D[1] * c.D[2];
+        const double gram[4] = {dv, dv / 12, dv / 12, dv / 12};
+        launch_total_field(static_cast<double2*>(e), static_cast<const double2*>(e_t), static_cast<const double2*>(x),
+                           gram, make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.nc, c.stream);
+    });
+}
+
 int vie_absorbed_power(vie_ctx* ctx, int nrhs, const void* x, double* p_abs_host) {
     return guarded([&] {
         check_ctx(ctx);

@@ -77,6 +77,8 @@ void launch_rhs_prec(double2* rhs, const double2* et, const double2* tau, const 
                      long long V, int nrhs, int nc, hipStream_t s);
 void launch_fields(double2* e, const double2* x, const double2* chi, double2 ce, long long V, int nrhs, int nc,
                    hipStream_t s);
+void launch_total_field(double2* e, const double2* et, const double2* x, const double gram[4], double2 ce,
+                        long long V, int nrhs, int nc, hipStream_t s);
 void launch_power_partials(double* partial, const double2* x, const double2* chi, const double gram[4], double2 ce,
                            long long V, int nrhs, int nc, int nblocks, hipStream_t s);
 void launch_power_density(double* p, const double2* e, const double* sigma, long long V, int nrhs, int nc,

@@ -190,6 +190,30 @@ void launch_fields(double2* e, const double2* x, const double2* chi, double2 ce,
     VIE_HIP(hipGetLastError());
 }
 
+// e = (e_t + (w - G x) / c_e) / G with w = N x already in e (Sec. IV-C)
+__global__ void k_total_field(double2* __restrict__ e, const double2* __restrict__ et,
+                              const double2* __restrict__ x, double g0, double g1, double2 inv_ce, long long V,
+                              long long n, int nc) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int l = nc == 12 ? int((i / V) % 12) & 3 : 0;
+    const double g = l == 0 ? g0 : g1;
+    const double2 w = e[i], xv = x[i], ev = et[i];
+    const double2 d = make_double2(w.x - g * xv.x, w.y - g * xv.y);
+    const double2 t = cmul(d, inv_ce);
+    e[i] = make_double2((ev.x + t.x) / g, (ev.y + t.y) / g);
+}
+
+void launch_total_field(double2* e, const double2* et, const double2* x, const double gram[4], double2 ce,
+                        long long V, int nrhs, int nc, hipStream_t s) {
+    const long long n = nc * V * nrhs;
+    const double den = ce.x * ce.x + ce.y * ce.y;
+    const double2 inv_ce = make_double2(ce.x / den, -ce.y / den);
+    hipLaunchKernelGGL(k_total_field, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, e, et, x, gram[0], gram[1],
+                       inv_ce, V, n, nc);
+    VIE_HIP(hipGetLastError());
+}
+
 // partial sums of 1/2 Re{conj(x) G x / (c_e chi)} (eq. 44), one per block
 __global__ void __launch_bounds__(256) k_power(double* __restrict__ partial, const double2* __restrict__ x,
                                                const double2* __restrict__ chi, double g0, double g1, double2 ce,

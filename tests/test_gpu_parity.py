@@ -211,6 +211,40 @@ def test_solve_matches_dense(vie, torch, mode, tol, bound, reorth):
     assert abs(P - post.absorbed_power(xref, chi, D, F)) / abs(P) < 10 * bound
 
 
+def test_total_field_matches_oracle(vie, torch):
+    """Total field in the whole box (tissue and air) through one product
+    (Sec. IV-C) vs the oracle's, on the same blocks; and at the exact
+    discrete solution it equals x / (c_e chi) on the tissue voxels."""
+    N, D = (5, 4, 6), (0.005, 0.006, 0.004)
+    T = _full_blocks(N, D)
+    c = _ctx(vie, torch, N, D, T)
+    e, s = vi.ellipsoid_phantom(N, D, 33)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    x = vi.complex_normal(34, (12,) + N)
+    et = incident.planewave_tested(N, D, K)
+    xd, etd = _to_dev(torch, x, torch.complex128), _to_dev(torch, et, torch.complex128)
+    out = torch.empty_like(xd)
+    c.total_field(etd, xd, out)
+    assert relerr(_from_dev(out), post.total_field(T, x, et, D, F)) < 1e-12
+    # identity at the solution (4^3 sphere with air corners, dense LU)
+    N, D = (4, 4, 4), (0.005,) * 3
+    T = _full_blocks(N, D)
+    c = _ctx(vie, torch, N, D, T)
+    e, s = vi.sphere(N, D, 0.0101, 50.0, 0.7)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    tau, chi = physics.tau(e, s, F), physics.chi(e, s, F)
+    et = incident.planewave_tested(N, D, K)
+    xref = solve.solve_dense(T, tau, D, matvec.rhs_prec(et, tau, D, F))
+    xd, etd = _to_dev(torch, xref, torch.complex128), _to_dev(torch, et, torch.complex128)
+    tot, fld = torch.empty_like(xd), torch.empty_like(xd)
+    c.total_field(etd, xd, tot)
+    c.fields(xd, fld)
+    m = chi != 0
+    assert 0 < m.sum() < m.size
+    a, b = _from_dev(tot)[:, m], _from_dev(fld)[:, m]
+    assert np.abs(a - b).max() < 1e-9 * np.abs(b).max()
+
+
 def test_fields_and_power_density(vie, torch):
     N, D = (4, 3, 5), (0.005,) * 3
     c = _ctx(vie, torch, N, D)

@@ -165,6 +165,17 @@ def test_pwc_excitation_rhs_fields_power(vie, torch):
     assert relerr(pd[0].cpu().numpy().transpose(2, 1, 0), pwc.power_density(eref, s)) < 1e-13
 
 
+def test_pwc_total_field(vie, torch):
+    N, D = (4, 5, 3), (0.006, 0.005, 0.004)
+    T3 = _T3(N, D)
+    c = _ctx(vie, N, D, None, _T12(N, D))
+    x = vi.complex_normal(35, (3,) + N)
+    et = pwc.restrict(incident.planewave_tested(N, D, K))
+    out = torch.empty(c.vec_shape(1), dtype=torch.complex128, device="cuda")
+    c.total_field(_dev(torch, et, torch.complex128), _dev(torch, x, torch.complex128), out)
+    assert relerr(_host(out), pwc.total_field(T3, x, et, D, F)) < 1e-12
+
+
 @pytest.mark.parametrize("mode,tol,bound", [(0, 1e-12, 1e-9), (1, 1e-10, 1e-7)])
 def test_pwc_solve_matches_dense(vie, torch, mode, tol, bound):
     N, D = (4, 4, 4), (0.005,) * 3

@@ -138,3 +138,18 @@ def test_operators_are_pwl_restricted():
     for a, b in pairs:
         b3 = pwc.restrict(b)
         assert np.abs(a - b3).max() < 1e-13 * np.abs(b3).max()
+
+
+def test_total_field_is_pwl_restricted():
+    """The PWC total field equals the PWL one for a pulse-only current, read
+    at the unknowns a = 4 p."""
+    N, D = (3, 2, 4), (0.006, 0.005, 0.004)
+    T = _T(N, D)
+    x3 = vi.complex_normal(17, (3,) + N)
+    x12 = np.zeros((12,) + N, dtype=np.complex128)
+    x12[list(pwc.PWL_INDEX)] = x3
+    et = incident.planewave_tested(N, D, K)
+    a = pwc.total_field(pwc.blocks_from_pwl(T), x3, pwc.restrict(et), D, F)
+    b = pwc.restrict(post.total_field(T, x12, et, D, F))
+    assert np.abs(a - b).max() < 1e-13 * np.abs(b).max()
+
