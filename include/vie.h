@@ -75,7 +75,10 @@ typedef struct {
     int max_outer;       /* max restart cycles per solve (paper: 200)         */
     double tol;          /* relative residual ||P^-1(b - A x)|| / ||P^-1 b||  */
     double inner_tol;    /* FP32_IR: relative reduction per inner solve       */
-    int max_refine;      /* FP32_IR: max refinement steps                     */
+    int max_refine;      /* FP32_IR: max refinement steps (>= 1); each is one
+                            complex64 GMRES(restart) cycle on the current
+                            residual, so at most min(max_outer, max_refine)
+                            cycles run                                        */
     int reorth;          /* 1: second Gram-Schmidt pass per Arnoldi step      */
     int use_x0;          /* 1: x holds the initial guess, 0: start from zero  */
 } vie_solve_opts;
@@ -181,7 +184,9 @@ int vie_rhs_prec(vie_ctx* ctx, int nrhs, const void* e_t, void* rhs);
 
 /* y = op(x) for nrhs vectors in x layout, precision VIE_C64 or VIE_C128,
  * device pointers, asynchronous on the context stream.  x and y must not
- * overlap.  Requires vie_set_grid (and vie_set_contrast for OP_PREC/OP_A). */
+ * overlap (VIE_EINVAL when their byte ranges intersect).  Requires
+ * vie_set_grid (and vie_set_contrast for OP_PREC/OP_A).  The FFT
+ * intermediates live in a context workspace that grows on demand. */
 int vie_apply(vie_ctx* ctx, int op, int precision, int nrhs, const void* x, void* y);
 
 /* -- solve (Sec. IV-B, V: GMRES(50), left preconditioner P = M_eps G) ------- */
@@ -207,8 +212,9 @@ int vie_fields(vie_ctx* ctx, int nrhs, const void* x, void* e);
  * one operator product (Sec. IV-C): G e = e_t + (N - G) x / c_e, i.e.
  * e = G^-1 (e_t + (N x - G x) / c_e) with the tested incident field e_t.  On
  * tissue voxels this equals vie_fields at the exact discrete solution.
- * e_t, x and e: complex128 device arrays in x layout; e must not overlap x
- * (it receives N x first).  Requires vie_set_grid. */
+ * e_t, x and e: complex128 device arrays in x layout; e must overlap
+ * neither x nor e_t (it receives N x before e_t is read): VIE_EINVAL
+ * otherwise.  Requires vie_set_grid. */
 int vie_total_field(vie_ctx* ctx, int nrhs, const void* e_t, const void* x, void* e);
 
 /* Absorbed power P_abs = 1/2 Re{x^* (c_e M_chi)^-1 G x} (eq. 44) per
@@ -323,12 +329,17 @@ typedef struct {
     long long operator_hits;     /* requests that reused a cached operator     */
     long long operator_misses;   /* requests that assembled their operator     */
     size_t operator_cache_bytes; /* device bytes held by the operator cache    */
+    double oldest_queued_s;      /* age of the oldest request still queued     */
 } vie_serving_stats;
 
 /* Create a server on HIP device `device` that admits requests while the sum
  * of their footprints (vie_footprint_bytes plus the request vectors) stays
- * within hbm_budget bytes and at most max_slots run at once.  Each admitted
- * request runs on its own worker thread, context and stream.  Operators of
+ * within hbm_budget bytes and at most max_slots run at once.  A pool of
+ * max_slots worker threads runs the admitted requests, each on its own
+ * context and stream.  Requests start in arrival order; one that fits may
+ * start ahead of a head of the queue that does not (backfill), at most 8
+ * times per head, after which the head waits for memory to drain and starts
+ * next.  Operators of
  * recently used grids stay resident for later requests on the same grid
  * (extents, voxel size, frequency), in a cache of hbm_budget / 8 bytes by
  * default, held outside the budget (see vie_server_set_operator_cache). */

@@ -66,7 +66,7 @@ class ServingStats(ctypes.Structure):
     _fields_ = [("completed", _i), ("queued", _i), ("running", _i), ("peak_running", _i), ("p50_s", _d),
                 ("p99_s", _d), ("mean_s", _d), ("makespan_s", _d), ("peak_bytes", ctypes.c_size_t),
                 ("operator_hits", ctypes.c_longlong), ("operator_misses", ctypes.c_longlong),
-                ("operator_cache_bytes", ctypes.c_size_t)]
+                ("operator_cache_bytes", ctypes.c_size_t), ("oldest_queued_s", _d)]
 
 
 _sig = {

@@ -15,6 +15,7 @@
 // functions); the 1/(Mx My Mz) of the inverse FFT is folded into the
 // epilogue.
 #include <algorithm>
+#include <string>
 
 #include "ctx.hpp"
 #include "fft_ct.hpp"
@@ -30,8 +31,16 @@ template <> const C<double>* opspec<double>(const Ctx& c) { return c.U128; }
 
 static int pick_tile(int n, size_t elem) { return strided_tile_for((int)elem, n, 16); }
 
+// bytes of FFT intermediates one product of nrhs vectors needs (layouts below)
+size_t apply_workspace_bytes(const Ctx& c, int nrhs, size_t es) {
+    const long long row = (long long)c.nc * c.N[0];
+    const long long sR1 = (long long)c.M[2] * ((long long)c.N[1] * row + 32) + 96;
+    const long long sR2 = (long long)c.M[2] * ((long long)c.M[1] * row + 32) + 96;
+    return (size_t)nrhs * (size_t)(sR1 + sR2) * es;
+}
+
 template <typename R>
-void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs) {
+void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs, void* ws_ext, size_t ws_cap) {
     Tune tn;
     {
         auto it = c.tune.find({sizeof(R) == 4 ? 0 : 1, nrhs});
@@ -52,7 +61,16 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     const long long sR1 = (long long)Mz * pl1 + 96;   // per right-hand side, after P1 / P4
     const long long sR2 = (long long)Mz * pl2 + 96;   // after P2 / P3
     const size_t es = sizeof(C<R>);
-    char* ws = static_cast<char*>(c.ws.get((size_t)nrhs * (sR1 + sR2) * es));
+    const size_t need = apply_workspace_bytes(c, nrhs, es);
+    char* ws = nullptr;
+    if (ws_ext) {
+        VIE_REQUIRE(need <= ws_cap, VIE_EINVAL,
+                    "product needs " + std::to_string(need) + " workspace bytes, above the fixed limit of " +
+                        std::to_string(ws_cap));
+        ws = static_cast<char*>(ws_ext);
+    } else {
+        ws = static_cast<char*>(c.ws.get(need));
+    }
     C<R>* A1 = reinterpret_cast<C<R>*>(ws);
     C<R>* A2 = reinterpret_cast<C<R>*>(ws + (size_t)nrhs * sR1 * es);
     hipStream_t s = c.stream;
@@ -248,7 +266,7 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs)
     }
 }
 
-template void apply_op<float>(Ctx&, int, int, const C<float>*, C<float>*, const C<float>*);
-template void apply_op<double>(Ctx&, int, int, const C<double>*, C<double>*, const C<double>*);
+template void apply_op<float>(Ctx&, int, int, const C<float>*, C<float>*, const C<float>*, void*, size_t);
+template void apply_op<double>(Ctx&, int, int, const C<double>*, C<double>*, const C<double>*, void*, size_t);
 
 }  // namespace vie

@@ -9,28 +9,9 @@
 
 using namespace vie;
 
-struct vie_ctx {
-    Ctx c;
-};
-
-static thread_local std::string g_err;
-
-template <typename F>
-static int guarded(F&& f) {
-    try {
-        g_err.clear();
-        f();
-        return VIE_OK;
-    } catch (const Error& e) {
-        g_err = e.what();
-        return e.code;
-    } catch (const std::exception& e) {
-        g_err = e.what();
-        return VIE_EDEVICE;
-    }
-}
-
 namespace vie {
+
+thread_local std::string g_err;
 
 Ctx::~Ctx() {
     free_grid();
@@ -68,6 +49,12 @@ void Ctx::free_contrast() {
 static void check_ctx(vie_ctx* ctx) { VIE_REQUIRE(ctx != nullptr, VIE_EINVAL, "null context"); }
 
 static void set_device(Ctx& c) { VIE_HIP(hipSetDevice(c.device)); }
+
+// true when the byte ranges [a, a + na) and [b, b + nb) share a byte
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return pa < pb + nb && pb < pa + na;
+}
 
 extern "C" {
 
@@ -363,7 +350,12 @@ int vie_apply(vie_ctx* ctx, int op, int precision, int nrhs, const void* x, void
         set_device(c);
         VIE_REQUIRE(op == VIE_OP_PREC || op == VIE_OP_A || op == VIE_OP_N, VIE_EINVAL, "unknown operator");
         VIE_REQUIRE(nrhs >= 1 && x && y, VIE_EINVAL, "bad arguments");
-        VIE_REQUIRE(x != y, VIE_EINVAL, "x and y must not overlap");
+        VIE_REQUIRE(precision == VIE_C64 || precision == VIE_C128, VIE_EINVAL,
+                    "precision must be VIE_C64 or VIE_C128");
+        if (c.has_grid) {
+            const size_t bytes = (size_t)nrhs * c.nc * c.V * (precision == VIE_C64 ? 8 : 16);
+            VIE_REQUIRE(!overlaps(x, bytes, y, bytes), VIE_EINVAL, "x and y must not overlap");
+        }
         if (precision == VIE_C64)
             apply_op<float>(c, op, nrhs, static_cast<const float2*>(x), static_cast<float2*>(y), nullptr);
         else if (precision == VIE_C128)
@@ -399,6 +391,7 @@ int vie_solve(vie_ctx* ctx, const vie_solve_opts* opts, int nrhs, const void* e_
         VIE_REQUIRE(o.restart >= 1 && o.restart <= 200, VIE_EINVAL, "restart must be in 1..200");
         VIE_REQUIRE(o.max_outer >= 1 && o.tol > 0 && o.tol < 1, VIE_EINVAL, "bad tolerance or max_outer");
         VIE_REQUIRE(o.mode == VIE_SOLVE_FP64 || o.mode == VIE_SOLVE_FP32_IR, VIE_EINVAL, "unknown mode");
+        VIE_REQUIRE(o.mode != VIE_SOLVE_FP32_IR || o.max_refine >= 1, VIE_EINVAL, "max_refine must be >= 1");
         rc = solve(c, o, nrhs, static_cast<const double2*>(e_t), static_cast<double2*>(x), stats);
         if (rc == VIE_ENOCONV) g_err = "solver stopped before reaching the tolerance";
         if (rc == VIE_ENAN) g_err = "non-finite residual";
@@ -425,7 +418,9 @@ int vie_total_field(vie_ctx* ctx, int nrhs, const void* e_t, const void* x, void
         set_device(c);
         VIE_REQUIRE(c.has_grid, VIE_ESTATE, "no grid");
         VIE_REQUIRE(nrhs >= 1 && e_t && x && e, VIE_EINVAL, "bad arguments");
-        VIE_REQUIRE(e != x, VIE_EINVAL, "e and x must not overlap");
+        const size_t bytes = (size_t)nrhs * c.nc * c.V * sizeof(double2);
+        VIE_REQUIRE(!overlaps(e, bytes, x, bytes) && !overlaps(e, bytes, e_t, bytes), VIE_EINVAL,
+                    "e must not overlap x or e_t (it receives N x before e_t is read)");
         apply_op<double>(c, OP_N, nrhs, static_cast<const double2*>(x), static_cast<double2*>(e), nullptr);
         const double dv = c.D[0] * c.D[1] * c.D[2];
         const double gram[4] = {dv, dv / 12, dv / 12, dv / 12};

@@ -3,6 +3,7 @@
 
 #include <map>
 #include <memory>
+#include <string>
 #include <vector>
 
 #include "vie.h"
@@ -207,8 +208,31 @@ void make_twiddles(int n, std::vector<double2>& tw);
 
 // operator products (apply.cpp)
 enum { OP_PREC = 0, OP_A = 1, OP_N = 2, OP_RESID = 3 };
+// ws_ext: caller-owned workspace of ws_cap bytes for the FFT intermediates
+// (VIE_EINVAL when the product needs more); nullptr: the context's own,
+// grown on demand
 template <typename R>
-void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs);
+void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs, void* ws_ext = nullptr,
+              size_t ws_cap = 0);
+size_t apply_workspace_bytes(const Ctx& c, int nrhs, size_t es);
+
+// status-code guard of the C entry points (capi.cpp): runs f, turns an
+// exception into its status and keeps the message for vie_last_error
+extern thread_local std::string g_err;
+template <typename F>
+int guarded(F&& f) {
+    try {
+        g_err.clear();
+        f();
+        return VIE_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return VIE_EDEVICE;
+    }
+}
 
 // autotuner (tune.cpp): fastest launch shapes for (precision, nrhs)
 Tune autotune(Ctx& c, int precision, int nrhs, double* best_ms);
@@ -217,3 +241,8 @@ Tune autotune(Ctx& c, int precision, int nrhs, double* best_ms);
 int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2* x, vie_solve_stats* st);
 
 }  // namespace vie
+
+// the opaque handle of the C ABI
+struct vie_ctx {
+    vie::Ctx c;
+};

@@ -20,9 +20,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 template <typename T> __device__ __forceinline__ double2 to_d2(T v) { return make_double2((double)v.x, (double)v.y); }
 
-// 16-byte units: a pair of complex64 or one complex128
-template <typename R> struct Unit;
-template <> struct Unit<float> {
+// Load units of the Gram-Schmidt kernels: 16 bytes (a pair of complex64, or
+// one complex128) when every vector start is 16-byte aligned, i.e. the
+// vector length and all strides are even in complex64; a single complex64
+// otherwise (odd lengths occur with the PWC basis, 3 V unknowns).
+template <typename R, bool PAIR> struct Unit;
+template <> struct Unit<float, true> {
     using T = float4;
     static constexpr int per = 2;
     __device__ static double2 get(const T& u, int h) { return h ? make_double2(u.z, u.w) : make_double2(u.x, u.y); }
@@ -30,22 +33,37 @@ template <> struct Unit<float> {
         if (h) { u.z = (float)v.x; u.w = (float)v.y; } else { u.x = (float)v.x; u.y = (float)v.y; }
     }
 };
-template <> struct Unit<double> {
+template <> struct Unit<float, false> {
+    using T = float2;
+    static constexpr int per = 1;
+    __device__ static double2 get(const T& u, int) { return make_double2(u.x, u.y); }
+    __device__ static void set(T& u, int, double2 v) { u.x = (float)v.x; u.y = (float)v.y; }
+};
+template <bool PAIR> struct Unit<double, PAIR> {
     using T = double2;
     static constexpr int per = 1;
     __device__ static double2 get(const T& u, int) { return u; }
     __device__ static void set(T& u, int, double2 v) { u = v; }
 };
 
+// true when 16-byte units cover every vector exactly: complex128, or
+// complex64 with an even length, even strides and 16-byte aligned bases
+template <typename R>
+static bool pair_units(const void* a, const void* b, long long n, long long s1, long long s2, long long s3) {
+    if (sizeof(R) == 8) return true;
+    return ((n | s1 | s2 | s3) & 1) == 0 && ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0;
+}
+
 // One group of G basis vectors (G compile-time, so that the G + 1 loads of an
 // element are issued together with no guard between them): FP64 sums of
 // conj(V_i) w over this thread's elements, reduced over the workgroup and
 // written to partial[(r * nvec + i) * nblocks + block].
-template <typename R, int G>
-__device__ __forceinline__ void dot_group(double2* __restrict__ partial, const typename Unit<R>::T* __restrict__ V,
-                                          const typename Unit<R>::T* __restrict__ wr, long long ldu, long long nu,
-                                          int i0, int nvec, int r, double (*red)[2 * kGroup]) {
-    using U = Unit<R>;
+template <typename R, bool PAIR, int G>
+__device__ __forceinline__ void dot_group(double2* __restrict__ partial,
+                                          const typename Unit<R, PAIR>::T* __restrict__ V,
+                                          const typename Unit<R, PAIR>::T* __restrict__ wr, long long ldu,
+                                          long long nu, int i0, int nvec, int r, double (*red)[2 * kGroup]) {
+    using U = Unit<R, PAIR>;
     using T = typename U::T;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long stride = (long long)gridDim.x * kTpb;
@@ -84,13 +102,13 @@ __device__ __forceinline__ void dot_group(double2* __restrict__ partial, const t
 
 // partial sums of conj(V_i) w for i < nvec: workgroup (b, r, g) takes group g
 // of kGroup basis vectors (the last group may hold fewer) over its share of
-// the elements, so the groups stream side by side (vectors read in 16-byte
-// units; n a multiple of the unit)
-template <typename R>
+// the elements, so the groups stream side by side (vectors read in units of
+// Unit<R, PAIR>; n and the strides multiples of the unit)
+template <typename R, bool PAIR>
 __global__ void __launch_bounds__(kTpb) k_multidot(double2* __restrict__ partial, const C<R>* __restrict__ Vb,
                                                    long long ldv, int nvec, const C<R>* __restrict__ w, long long n,
                                                    long long rsv, long long rsw) {
-    using U = Unit<R>;
+    using U = Unit<R, PAIR>;
     using T = typename U::T;
     __shared__ double red[kTpb / 64][2 * kGroup];
     const int r = blockIdx.y;
@@ -101,7 +119,7 @@ __global__ void __launch_bounds__(kTpb) k_multidot(double2* __restrict__ partial
     const int i0 = blockIdx.z * kGroup;
     switch (min(kGroup, nvec - i0)) {   // uniform over the workgroup
 #define VIE_DOT_G(g_) \
-    case g_: dot_group<R, g_>(partial, V, wr, ldu, nu, i0, nvec, r, red); break;
+    case g_: dot_group<R, PAIR, g_>(partial, V, wr, ldu, nu, i0, nvec, r, red); break;
         VIE_DOT_G(1) VIE_DOT_G(2) VIE_DOT_G(3) VIE_DOT_G(4) VIE_DOT_G(5) VIE_DOT_G(6) VIE_DOT_G(7) VIE_DOT_G(8)
 #undef VIE_DOT_G
         default: break;
@@ -112,8 +130,12 @@ template <typename R>
 void launch_multidot(double2* partial, const C<R>* Vb, long long ldv, int nvec, const C<R>* w, long long n,
                      long long rsv, long long rsw, int nrhs, int nblocks, hipStream_t s) {
     const unsigned ngroups = (unsigned)((nvec + kGroup - 1) / kGroup);
-    hipLaunchKernelGGL(k_multidot<R>, dim3(nblocks, nrhs, ngroups), dim3(kTpb), 0, s, partial, Vb, ldv, nvec, w, n,
-                       rsv, rsw);
+    if (pair_units<R>(Vb, w, n, ldv, rsv, rsw))
+        hipLaunchKernelGGL((k_multidot<R, true>), dim3(nblocks, nrhs, ngroups), dim3(kTpb), 0, s, partial, Vb, ldv,
+                           nvec, w, n, rsv, rsw);
+    else
+        hipLaunchKernelGGL((k_multidot<R, false>), dim3(nblocks, nrhs, ngroups), dim3(kTpb), 0, s, partial, Vb, ldv,
+                           nvec, w, n, rsv, rsw);
     VIE_HIP(hipGetLastError());
 }
 
@@ -151,12 +173,12 @@ void launch_reduce_partials(double2* h, double2* coef, const double2* partial, i
 
 // w = sw w - sum_i c_i u_i (FP64 arithmetic; sw = ivn[jw], or 1 for jw < 0),
 // and partial sums of |w|^2 of the stored values
-template <typename R>
+template <typename R, bool PAIR>
 __global__ void __launch_bounds__(kTpb) k_update(C<R>* __restrict__ w, const C<R>* __restrict__ Vb, long long ldv,
                                                  int nvec, const double2* __restrict__ h, long long n, long long rsv,
                                                  long long rsw, double* __restrict__ norm_partial,
                                                  const double* __restrict__ ivn, long long ivn_ld, int jw) {
-    using U = Unit<R>;
+    using U = Unit<R, PAIR>;
     using T = typename U::T;
     __shared__ double red[kTpb / 64];
     const int r = blockIdx.y;
@@ -226,8 +248,12 @@ template <typename R>
 void launch_update(C<R>* w, const C<R>* Vb, long long ldv, int nvec, const double2* h, long long n, long long rsv,
                    long long rsw, double* norm_partial, const double* ivn, long long ivn_ld, int jw, int nrhs,
                    int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_update<R>, dim3(nblocks, nrhs), dim3(kTpb), 0, s, w, Vb, ldv, nvec, h, n, rsv, rsw,
-                       norm_partial, ivn, ivn_ld, jw);
+    if (pair_units<R>(Vb, w, n, ldv, rsv, rsw))
+        hipLaunchKernelGGL((k_update<R, true>), dim3(nblocks, nrhs), dim3(kTpb), 0, s, w, Vb, ldv, nvec, h, n, rsv,
+                           rsw, norm_partial, ivn, ivn_ld, jw);
+    else
+        hipLaunchKernelGGL((k_update<R, false>), dim3(nblocks, nrhs), dim3(kTpb), 0, s, w, Vb, ldv, nvec, h, n, rsv,
+                           rsw, norm_partial, ivn, ivn_ld, jw);
     VIE_HIP(hipGetLastError());
 }
 

@@ -4,11 +4,16 @@
 // Requests wait in arrival order.  A request is admitted when a worker slot
 // is free and its device footprint fits the remaining memory budget; while
 // the head of the queue does not fit, later requests that do fit may go
-// first (backfill), so small solves are not held behind a large one.  Each
-// admitted request runs on its own worker thread (and, in the GPU executor,
-// its own stream), so the work of all admitted requests overlaps on the
-// device.  Finished requests release their slot and memory, and the queue is
-// re-examined at once.  Latency = completion - arrival (queueing included).
+// first (backfill), so small solves are not held behind a large one.
+// Backfill is bounded: once the head has been passed over max_bypass times,
+// nothing more is admitted ahead of it, so the running requests drain until
+// it fits (no request waits forever behind a stream of smaller ones).  A
+// fixed pool of `slots` worker threads runs the admitted requests (in the GPU
+// executor each on its own stream), so the work of all admitted requests
+// overlaps on the device.  Finished requests release their slot and memory,
+// and the queue is re-examined at once.  Latency = completion - arrival
+// (queueing included); the statistics also give the age of the oldest
+// request still queued, which completed-request percentiles cannot show.
 #pragma once
 
 #include <algorithm>
@@ -39,9 +44,13 @@ class Scheduler {
   public:
     using RunFn = std::function<int(SchedJob&)>;
 
-    Scheduler(size_t budget, int slots, RunFn run)
-        : budget_(budget), slots_(std::max(1, slots)), run_(std::move(run)), t0_(clock::now()) {
-        dispatcher_ = std::thread([this] { dispatch_loop(); });
+    static constexpr int kDefaultMaxBypass = 8;
+
+    Scheduler(size_t budget, int slots, RunFn run, int max_bypass = kDefaultMaxBypass)
+        : budget_(budget), slots_(std::max(1, slots)), max_bypass_(std::max(0, max_bypass)), run_(std::move(run)),
+          t0_(clock::now()) {
+        workers_.reserve(slots_);
+        for (int i = 0; i < slots_; ++i) workers_.emplace_back([this] { worker_loop(); });
     }
 
     ~Scheduler() {
@@ -50,9 +59,7 @@ class Scheduler {
             stop_ = true;
         }
         cv_.notify_all();
-        dispatcher_.join();
-        for (auto& t : workers_)
-            if (t.joinable()) t.join();
+        for (auto& t : workers_) t.join();
     }
 
     double now() const { return std::chrono::duration<double>(clock::now() - t0_).count(); }
@@ -92,6 +99,7 @@ class Scheduler {
         size_t in_use = 0, peak_in_use = 0;
         int peak_running = 0;
         double p50 = 0, p99 = 0, mean = 0, makespan = 0;
+        double oldest_queued = 0;   // age of the oldest request still waiting (s)
     };
 
     // latency statistics over completed jobs with id >= first_id
@@ -113,6 +121,8 @@ class Scheduler {
         s.in_use = in_use_;
         s.peak_in_use = peak_in_use_;
         s.peak_running = peak_running_;
+        const double t = now();
+        for (auto& j : queue_) s.oldest_queued = std::max(s.oldest_queued, t - j->t_arrival);
         if (!lat.empty()) {
             std::sort(lat.begin(), lat.end());
             auto pct = [&](double p) {
@@ -134,57 +144,57 @@ class Scheduler {
   private:
     using clock = std::chrono::steady_clock;
 
-    void dispatch_loop() {
+    // each worker admits the next request that may start, runs it, releases
+    // its slot and memory, and looks again; it leaves once stop_ is set
+    // (queued requests that never started are dropped)
+    void worker_loop() {
         std::unique_lock<std::mutex> lk(m_);
         for (;;) {
-            cv_.wait(lk, [this] { return stop_ || admissible(); });
-            if (stop_) break;   // queued requests that never started are dropped
-            while (admissible()) {
-                auto it = pick();
-                std::shared_ptr<SchedJob> j = *it;
-                queue_.erase(it);
-                in_use_ += j->footprint;
-                running_ += 1;
-                peak_in_use_ = std::max(peak_in_use_, in_use_);
-                peak_running_ = std::max(peak_running_, running_);
-                j->t_start = now();
-                workers_.emplace_back([this, j] { work(j); });   // joined at destruction
+            cv_.wait(lk, [this] { return stop_ || pick() != queue_.end(); });
+            if (stop_) break;
+            auto it = pick();
+            std::shared_ptr<SchedJob> j = *it;
+            if (it != queue_.begin()) head_bypass_ += 1;   // backfilled past the head
+            else head_bypass_ = 0;                          // the head itself starts
+            queue_.erase(it);
+            in_use_ += j->footprint;
+            running_ += 1;
+            peak_in_use_ = std::max(peak_in_use_, in_use_);
+            peak_running_ = std::max(peak_running_, running_);
+            j->t_start = now();
+            lk.unlock();
+            int st = 0;
+            try {
+                st = run_(*j);
+            } catch (...) {
+                st = -3;
             }
+            lk.lock();
+            j->status = st;
+            j->t_end = now();
+            j->done = true;
+            in_use_ -= j->footprint;
+            running_ -= 1;
+            cv_.notify_all();
         }
     }
 
-    // queue non-empty, a slot free, and some queued job fits
-    bool admissible() {
-        if (queue_.empty() || running_ >= slots_) return false;
-        for (auto& j : queue_)
-            if (in_use_ + j->footprint <= budget_) return true;
-        return false;
-    }
-
+    // the request that may start now: the head when it fits; otherwise the
+    // first later request that fits, unless the head has been passed over
+    // max_bypass_ times already; end() when none (a free slot is implied:
+    // a worker only asks when it is idle)
     std::deque<std::shared_ptr<SchedJob>>::iterator pick() {
-        for (auto it = queue_.begin(); it != queue_.end(); ++it)
+        if (queue_.empty()) return queue_.end();
+        if (in_use_ + queue_.front()->footprint <= budget_) return queue_.begin();
+        if (head_bypass_ >= max_bypass_) return queue_.end();
+        for (auto it = queue_.begin() + 1; it != queue_.end(); ++it)
             if (in_use_ + (*it)->footprint <= budget_) return it;
         return queue_.end();
     }
 
-    void work(std::shared_ptr<SchedJob> j) {
-        int st = 0;
-        try {
-            st = run_(*j);
-        } catch (...) {
-            st = -3;
-        }
-        std::lock_guard<std::mutex> g(m_);
-        j->status = st;
-        j->t_end = now();
-        j->done = true;
-        in_use_ -= j->footprint;
-        running_ -= 1;
-        cv_.notify_all();
-    }
-
     size_t budget_;
     int slots_;
+    int max_bypass_;
     RunFn run_;
     clock::time_point t0_;
     std::mutex m_;
@@ -192,8 +202,8 @@ class Scheduler {
     std::deque<std::shared_ptr<SchedJob>> queue_;
     std::map<long long, std::shared_ptr<SchedJob>> jobs_;
     std::vector<std::thread> workers_;
-    std::thread dispatcher_;
     long long next_id_ = 0;
+    int head_bypass_ = 0;   // admissions past the current head of the queue
     size_t in_use_ = 0, peak_in_use_ = 0;
     int running_ = 0, peak_running_ = 0;
     bool stop_ = false;

@@ -249,6 +249,7 @@ int vie_server_stats(vie_server* s, long long first_id, vie_serving_stats* out) 
     out->mean_s = st.mean;
     out->makespan_s = st.makespan;
     out->peak_bytes = st.peak_in_use;
+    out->oldest_queued_s = st.oldest_queued;
     {
         std::lock_guard<std::mutex> g(s->cache.m);
         out->operator_hits = (long long)s->cache.hits;

@@ -73,7 +73,9 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
     std::vector<double> last_rel(nrhs, 1.0);
     int status = VIE_ENOCONV;
     const int rchunk = std::max(1, std::min(nrhs, 4));
-    for (int cycle = 0; cycle <= o.max_outer; ++cycle) {
+    // each cycle of the refinement mode is one refinement step
+    const int max_cycles = ir ? std::min(o.max_outer, o.max_refine) : o.max_outer;
+    for (int cycle = 0; cycle <= max_cycles; ++cycle) {
         // true residual, complex128
         for (int r0 = 0; r0 < nrhs; r0 += rchunk) {
             const int k = std::min(rchunk, nrhs - r0);
@@ -94,7 +96,7 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
             status = VIE_OK;
             break;
         }
-        if (cycle == o.max_outer) break;
+        if (cycle == max_cycles) break;
         const int na = (int)active.size();
         const long long ldv = (long long)na * n + vpad;
         // V_0 = r / ||r|| for the active right-hand sides (compacted)

@@ -59,6 +59,12 @@ static Tune tune_t(Ctx& c, int nrhs, double* best_ms) {
     Tune best;
     double bms = 1e30;
     const int reps = c.V * nrhs > 4000000 ? 2 : 5;
+    // candidates are installed one by one while they are timed; a failure
+    // puts back what was installed before
+    const auto key = std::make_pair(key0, nrhs);
+    const auto prev = c.tune.find(key);
+    const bool had = prev != c.tune.end();
+    const Tune saved = had ? prev->second : Tune{};
     try {
         for (const Tune& t : cands) {
             c.tune[{key0, nrhs}] = t;
@@ -69,6 +75,8 @@ static Tune tune_t(Ctx& c, int nrhs, double* best_ms) {
             }
         }
     } catch (...) {
+        if (had) c.tune[key] = saved;
+        else c.tune.erase(key);
         (void)hipFree(x);
         (void)hipFree(y);
         throw;

@@ -99,6 +99,25 @@ int main() {
         CHECK(jb.t_start >= ja.t_end - 1e-3); // b waited for a's memory
         std::printf("ok backfill\n");
     }
+    {   // bounded backfill: after max_bypass admissions past a head that does
+        // not fit, later requests wait behind it; the oldest queued age shows
+        Scheduler s(20, 4, fake_run(), 2);
+        long long a = s.submit(10, job(150));
+        std::this_thread::sleep_for(std::chrono::milliseconds(30));   // a is running
+        long long b = s.submit(15, job(10));                          // waits for a's memory
+        std::vector<long long> c;
+        for (int i = 0; i < 4; ++i) c.push_back(s.submit(2, job(150)));
+        std::this_thread::sleep_for(std::chrono::milliseconds(40));
+        auto mid = s.stats();
+        CHECK(mid.queued == 3 && mid.oldest_queued >= 0.035);         // b, c[2], c[3] wait
+        s.wait_all();
+        auto ja = get(s, a), jb = get(s, b);
+        CHECK(get(s, c[0]).t_start < ja.t_end && get(s, c[1]).t_start < ja.t_end);   // two bypasses
+        CHECK(get(s, c[2]).t_start >= ja.t_end - 1e-3);                              // then b's turn
+        CHECK(jb.t_start <= get(s, c[2]).t_start && jb.t_start <= get(s, c[3]).t_start);
+        CHECK(s.stats().oldest_queued == 0.0);
+        std::printf("ok aging\n");
+    }
     {   // FIFO among requests that fit
         Scheduler s(100, 1, fake_run());
         std::vector<long long> ids;

@@ -11,7 +11,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1902_02196_amd", "csrc")
-CASES = ("oversize", "slots", "budget", "backfill", "fifo", "status", "percentiles", "shutdown")
+CASES = ("oversize", "slots", "budget", "backfill", "aging", "fifo", "status", "percentiles", "shutdown")
 
 
 def _gxx():
