@@ -15,6 +15,9 @@ Fields in MRI", IEEE TAP 2020):
 * ``toeplitz``  - Galerkin blocks of the N operator for the PWL basis
                   (Sec. III-A/B/C, eq. 19-26, 32-34, 42-43)
 * ``unreduced`` - brute-force 6-D quadrature of the dyadic kernel (pin only)
+* ``gaussian``  - the same blocks by a second route (power series of g and
+                  the Gaussian representation of 1/R, exact 1-D factors), the
+                  pin of ``toeplitz`` at touching and coincident voxels
 * ``matvec``    - direct voxel-pair sum, preconditioned operator (eq. 16-17,
                   24), circulant FFT product (Sec. IV-A)
 * ``incident``  - tested incident fields (eq. 27, 30-31)
@@ -26,7 +29,9 @@ Fields in MRI", IEEE TAP 2020):
                   against (Sec. V: 3 unknowns per voxel, 6 unique tensors),
                   as the l = 1 restriction of the PWL system
 
-Parity status: every function is pinned by a ``-m "not gpu"`` test except the
-absolute accuracy of the discretisation against Mie, which the paper only
-shows in a figure that is not available ("parity unpinned" for that trend).
+Parity status: every function is pinned by a ``-m "not gpu"`` test
+(closed forms, brute force, invariants, an independent second route, hand-
+worked values) except the absolute accuracy of the discretisation against
+Mie, which the paper only shows in a figure that is not available ("parity
+unpinned" for that trend).
 """
