@@ -24,6 +24,11 @@ Fields in MRI", IEEE TAP 2020):
 * ``solve``     - dense LU and restarted GMRES (Sec. V, GMRES(50))
 * ``post``      - fields, absorbed power, error metrics (Sec. IV-C, eq. 44,
                   Sec. V-C error definitions)
+* ``magnetic``  - magnetic field h_tot = h_inc + K j with the curl operator
+                  K = curl S (eq. 8b, 'tot_fields' b, 25b), b1+, magnetic
+                  energy and the errors of Sec. V-D; the K blocks come from
+                  ``toeplitz`` (part 'K'), pinned by ``gaussian`` and
+                  ``unreduced``
 * ``mie``       - Mie series absorbed power for a homogeneous sphere (Sec. V-A)
 * ``pwc``       - the piecewise-constant discretisation the paper compares
                   against (Sec. V: 3 unknowns per voxel, 6 unique tensors),

@@ -308,6 +308,47 @@ def axis_integral(axes, k0, wt, nmax):
     return total
 
 
+def curl_axis_integral(axes, k, k0, t, wt, nmax):
+    """int int N^l(u) N^l'(v) d_k g(c + u - v) with the derivative left on
+    the kernel (no integration by parts):
+        d_k g = -(w_k / 4 pi) sum_n c_n R^(n - 3),
+        c_n = (-i k0)^n (1 - n) / n!   (exp(-i k0 R) (1 + i k0 R) in powers of R),
+    R^-3 through 1 / R^3 = (4 / sqrt(pi)) int_0^inf t^2 exp(-t^2 R^2) dt, odd
+    powers through R^(2m) / R as above, even powers as polynomials; axis k
+    carries the extra factor w_k (odd moments)."""
+    total = 0.0 + 0.0j
+    odd = [1 if i == k else 0 for i in range(3)]
+    for n in range(nmax + 1):
+        cn = (-1j * k0) ** n * (1 - n) / math.factorial(n)
+        if cn == 0:
+            continue
+        e = n - 3
+        if e == -3:
+            integrand = axes[0].gauss(odd[0]) * axes[1].gauss(odd[1]) * axes[2].gauss(odd[2])
+            val = (4.0 / math.sqrt(math.pi)) * float(np.dot(integrand * t * t, wt))
+        elif e % 2 == 0:
+            val = 0.0
+            for (a, b, c), mult in _compositions(e // 2):
+                val += mult * (axes[0].poly(2 * a + odd[0]) * axes[1].poly(2 * b + odd[1]) *
+                               axes[2].poly(2 * c + odd[2]))
+        else:
+            integrand = 0.0
+            for (a, b, c), mult in _compositions((e + 1) // 2):
+                integrand = integrand + mult * (axes[0].gauss(2 * a + odd[0]) * axes[1].gauss(2 * b + odd[1]) *
+                                                 axes[2].gauss(2 * c + odd[2]))
+            val = (2.0 / math.sqrt(math.pi)) * float(np.dot(integrand, wt))
+        total += -cn * val / (4.0 * math.pi)
+    return total
+
+
+def _levi(p, k, q):
+    if (p, k, q) in ((0, 1, 2), (1, 2, 0), (2, 0, 1)):
+        return 1.0
+    if (p, k, q) in ((0, 2, 1), (2, 1, 0), (1, 0, 2)):
+        return -1.0
+    return 0.0
+
+
 def _gram_1d(l, lp, axis, Delta):
     """int over the voxel of the product of the two 1-D factors."""
     h = 0.5 * Delta
@@ -321,7 +362,11 @@ def blocks(dlist, Delta, k0, step=0.05, part='N'):
     """T(d) [n, 12, 12] for integer offsets d (rows of dlist) by the Gaussian
     route.  part = 'N': the whole block (the Gram term of the identity
     included at d = 0); 'S': the scalar blocks <N^l, S N^l'> as [n, 4, 4];
-    'C': the charge blocks <D_p N^l, S D_q N^l'> as [n, 12, 12]."""
+    'C': the charge blocks <D_p N^l, S D_q N^l'> as [n, 12, 12]; 'K': the
+    blocks <f^{pl}, curl S f^{ql'}> of the magnetic operator (eq. 8b, 25b),
+    sum_k eps_pkq <N^l, S D_k N^l'> (derivative moved onto the basis);
+    'Kcurl': the same blocks with the derivative of g kept on the kernel
+    (no integration by parts, so no face terms)."""
     dlist = np.atleast_2d(np.asarray(dlist, dtype=np.int64))
     Delta = tuple(float(v) for v in Delta)
     L = max(Delta)
@@ -338,6 +383,26 @@ def blocks(dlist, Delta, k0, step=0.05, part='N'):
                     for i in range(3)]
             return axis_integral(axes, float(k0), wt, nmax)
 
+        if part in ('K', 'Kcurl'):
+            blk = np.zeros((12, 12), dtype=np.complex128)
+            Q = {}
+            for p in range(3):
+                for q in range(3):
+                    if p == q:
+                        continue
+                    k = 3 - p - q
+                    for l in range(1, 5):
+                        for lp in range(1, 5):
+                            if (k, l, lp) not in Q:
+                                if part == 'K':
+                                    Q[(k, l, lp)] = integral(-1, l, k, lp)
+                                else:
+                                    axes = [_Axis(_factor_key(False, l, i), _factor_key(False, lp, i), d[i],
+                                                  Delta[i], tgrid) for i in range(3)]
+                                    Q[(k, l, lp)] = curl_axis_integral(axes, k, float(k0), t, wt, nmax + 1)
+                            blk[4 * p + l - 1, 4 * q + lp - 1] = _levi(p, k, q) * Q[(k, l, lp)]
+            out.append(blk)
+            continue
         if part == 'S':
             S = np.zeros((4, 4), dtype=np.complex128)
             for l in range(1, 5):

@@ -137,7 +137,10 @@ def _entry_terms(Delta, k0, part='N'):
 
     part = 'N': k0^2 delta_pq S - C (the Gram term is added separately);
     part = 'S': S^{ll'} alone, stored in the p = q = x entries;
-    part = 'C': C^{pl,ql'} alone.
+    part = 'C': C^{pl,ql'} alone;
+    part = 'K': the curl operator, < f^{pl}, curl S f^{ql'} > =
+    sum_k eps_{pkq} < N^l, S D_k N^{l'} > (the derivative of g moved onto the
+    basis function by parts; eps the Levi-Civita symbol).
     Returns dict geom -> list of (entry, coef, atoms) with entry = 12 a + b,
     geom a 3-tuple of per-axis geometries and atoms the per-axis density keys
     or point weights (floats).
@@ -165,6 +168,13 @@ def _entry_terms(Delta, k0, part='N'):
                         kt[p] = 'D' + kt[p]
                         kb[q] = 'D' + kb[q]
                         terms.append((-1.0 if part == 'N' else 1.0, kt, kb))
+                    if part == 'K' and p != q:
+                        k = 3 - p - q                       # the third axis
+                        eps = 1.0 if (p, k, q) in ((0, 1, 2), (1, 2, 0), (2, 0, 1)) else -1.0
+                        kt = [_scalar_kind(l, i) for i in range(3)]
+                        kb = [_scalar_kind(lp, i) for i in range(3)]
+                        kb[k] = 'D' + kb[k]
+                        terms.append((eps, kt, kb))
                     for coef, kt, kb in terms:
                         per_axis = [_correlate(_measure(kt[i], Delta[i]), _measure(kb[i], Delta[i]), Delta[i])
                                     for i in range(3)]
@@ -281,7 +291,9 @@ def galerkin_blocks(dlist, Delta, k0, duffy_order=14, order_scale=1.0, part='N')
     complex128 (Sec. III-B/C, eq. 25a, 26, 33, 42).
 
     Delta = (dx, dy, dz) in metres, k0 in 1/m.  part = 'S' returns the scalar
-    blocks S^{ll'} as [n, 4, 4]; part = 'C' the charge blocks C as [n, 12, 12].
+    blocks S^{ll'} as [n, 4, 4]; part = 'C' the charge blocks C as [n, 12, 12];
+    part = 'K' the blocks K^{pl,ql'}(d) = < f_m^{pl}, curl S f_n^{ql'} > of
+    the magnetic operator (eq. 8b, 25b) as [n, 12, 12].
     """
     dlist = np.atleast_2d(np.asarray(dlist, dtype=np.int64))
     Delta = tuple(float(v) for v in Delta)
