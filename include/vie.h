@@ -189,6 +189,29 @@ int vie_rhs_prec(vie_ctx* ctx, int nrhs, const void* e_t, void* rhs);
  * intermediates live in a context workspace that grows on demand. */
 int vie_apply(vie_ctx* ctx, int op, int precision, int nrhs, const void* x, void* y);
 
+/* -- operator product without device allocation ----------------------------- */
+
+/* Fixed size of the per-device workspace of vie_apply_noalloc: 64 MiB. */
+#define VIE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid it): the same product as
+ * vie_apply (same arguments, kernels and launch shapes, so the same result
+ * bit for bit), with the FFT intermediates in a fixed per-device workspace of
+ * VIE_NOALLOC_SCRATCH_BYTES that the library holds from load until the
+ * process ends, instead of the context's growing one.  It calls no device
+ * allocation or free.  The intermediates take
+ *     nrhs * es * (sR1 + sR2) bytes,  es = 8 (VIE_C64) or 16 (VIE_C128),
+ *     sR1 = M_z (N_y nc N_x + 32) + 96,  sR2 = M_z (M_y nc N_x + 32) + 96,
+ * with nc unknowns per voxel and the fft sizes M of vie_fft_size (e.g. one
+ * complex64 PWL vector on 48^3 voxels, or one complex128 on 36^3); larger
+ * requests return VIE_EINVAL before any launch.  The workspace is shared by
+ * every call on one GPU and keeps the last call's contents: calls on one GPU
+ * that overlap in time (other contexts or streams) race and must be ordered
+ * by the caller.  The context must have been set up (vie_set_grid, and
+ * vie_set_contrast for OP_PREC/OP_A); launch profiling is not applied. */
+int vie_apply_noalloc(vie_ctx* ctx, int op, int precision, int nrhs, const void* x, void* y);
+
 /* -- solve (Sec. IV-B, V: GMRES(50), left preconditioner P = M_eps G) ------- */
 
 void vie_default_opts(vie_solve_opts* opts);

@@ -82,6 +82,7 @@ _sig = {
     "vie_incident_dipoles": (_i, [_vp, _i, _dp, _dp, _i, _vp]),
     "vie_rhs_prec": (_i, [_vp, _i, _vp, _vp]),
     "vie_apply": (_i, [_vp, _i, _i, _i, _vp, _vp]),
+    "vie_apply_noalloc": (_i, [_vp, _i, _i, _i, _vp, _vp]),
     "vie_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
     "vie_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _i, _vp, _vp, ctypes.POINTER(SolveStats)]),
     "vie_fields": (_i, [_vp, _i, _vp, _vp]),
@@ -280,6 +281,15 @@ class Context:
         n = x.shape[0]
         _check(_lib.vie_apply(self._h, op, prec, n, _tensor_ptr(x, x.dtype, self.vec_shape(n)),
                               _tensor_ptr(y, x.dtype, self.vec_shape(n))))
+
+    def apply_noalloc(self, x, y, op=OP_PREC):
+        """As apply, with the intermediates in the library's fixed per-device
+        workspace (vie_apply_noalloc: no device allocation)."""
+        import torch
+        prec = {torch.complex64: C64, torch.complex128: C128}[x.dtype]
+        n = x.shape[0]
+        _check(_lib.vie_apply_noalloc(self._h, op, prec, n, _tensor_ptr(x, x.dtype, self.vec_shape(n)),
+                                      _tensor_ptr(y, x.dtype, self.vec_shape(n))))
 
     def solve(self, e_t, x, opts=None, **kw):
         import torch

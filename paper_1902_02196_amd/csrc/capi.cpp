@@ -71,6 +71,7 @@ int vie_create(vie_ctx** out, int device, void* stream) {
         ctx->c.stream = static_cast<hipStream_t>(stream);
         try {
             set_device(ctx->c);
+            noalloc_init(device);
             VIE_HIP(hipMalloc(&ctx->c.flag, sizeof(int)));
         } catch (...) {
             delete ctx;

@@ -216,6 +216,10 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs,
               size_t ws_cap = 0);
 size_t apply_workspace_bytes(const Ctx& c, int nrhs, size_t es);
 
+// fixed per-device workspace of vie_apply_noalloc (noalloc.hip): looked up
+// once per device by vie_create with that device current
+void noalloc_init(int device);
+
 // status-code guard of the C entry points (capi.cpp): runs f, turns an
 // exception into its status and keeps the message for vie_last_error
 extern thread_local std::string g_err;
