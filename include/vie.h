@@ -248,6 +248,50 @@ int vie_absorbed_power(vie_ctx* ctx, int nrhs, const void* x, double* p_abs_host
  * FP64 device array [nrhs][Nz][Ny][Nx], from field coefficients e. */
 int vie_power_density(vie_ctx* ctx, int nrhs, const void* e, double* p_dev);
 
+/* -- magnetic field and MRI quantities (Sec. II eq. 8b, 'tot_fields' b;
+ *    Sec. III eq. 25b; Sec. V-D) ------------------------------------------- */
+
+/* Tested incident magnetic field of the plane wave of vie_incident_planewave
+ * with the same arguments: H = (1/eta0) dir x E, i.e. amp / eta0 along
+ * dir x pol (eta0 = sqrt(mu0 / eps0)); into h_t (device, complex128,
+ * [nc][Nz][Ny][Nx]). */
+int vie_incident_planewave_h(vie_ctx* ctx, const double pol[3], const double dir[3], double amp, void* h_t);
+
+/* Tested incident magnetic fields of nrhs Hertzian dipoles (arguments as for
+ * vie_incident_dipoles): H = curl (g I l) = (1 + i k0 R) exp(-i k0 R) /
+ * (4 pi R^2) (I l x R_hat), by nq^3-point Gauss quadrature on every voxel
+ * (the sources must lie outside the voxels), into h_t (device, complex128,
+ * [nrhs][nc][Nz][Ny][Nx]).  Requires vie_set_grid. */
+int vie_incident_dipoles_h(vie_ctx* ctx, int nrhs, const double* pos, const double* moment, int nq, void* h_t);
+
+/* Total magnetic field h_tot = h_inc + K j (eq. 'tot_fields' b), K = curl S
+ * (eq. 8b) discretised on the PWL basis (eq. 25b): the coefficients
+ * h = G^-1 (h_t + K x) everywhere in the box, from the tested incident
+ * magnetic field h_t and the current coefficients x (device, complex128, x
+ * layout, nrhs vectors; h must not overlap x, it may alias h_t).  The 30
+ * unique tensors of K (Sec. III-C) are assembled and transformed on the
+ * first call for a grid (and kept with the grid's operator).  PWL basis and
+ * fft lengths along x up to 256 only (VIE_EINVAL otherwise). */
+int vie_magnetic_field(vie_ctx* ctx, int nrhs, const void* h_t, const void* x, void* h);
+
+/* b1+ = mu0 (h_x + i h_y) (Sec. V-D) as PWL coefficients: b[r][l][v] =
+ * mu0 (h^{x,l} + i h^{y,l}) for l = 1..4; h complex128 [nrhs][12][V],
+ * b complex128 [nrhs][4][Nz][Ny][Nx] (device). */
+int vie_b1plus(vie_ctx* ctx, int nrhs, const void* h, void* b);
+
+/* Magnetic energy (Sec. V-D): the density w_m = 1/4 mu0 |h|^2 averaged over
+ * each voxel into w_dev (device, FP64 [nrhs][Nz][Ny][Nx], may be NULL) and
+ * W_m = 1/4 int mu0 |h|^2 dV over the voxels with chi != 0 into W_host[nrhs]
+ * (J; may be NULL).  Requires vie_set_contrast. */
+int vie_magnetic_energy(vie_ctx* ctx, int nrhs, const void* h, double* w_dev, double* W_host);
+
+/* Copy the curl operator's 30 unique block tensors Q_k^{ll'}(d), d >= 0,
+ * [30][Nz][Ny][Nx] complex128, entry 10 k + ll (k = x, y, z; ll over the
+ * pairs l <= l' as for vie_set_toeplitz), to host memory; K^{pl,ql'} =
+ * eps_pkq Q_k^{ll'}, and Q_k^{l'l} = -Q_k^{ll'} when exactly one of l, l' is
+ * the pulse.  Builds the curl operator if needed. */
+int vie_get_curl_toeplitz(vie_ctx* ctx, double* T_host);
+
 /* -- utilities -------------------------------------------------------------- */
 
 /* Device copy of n complex128 values (src, dst device pointers, not

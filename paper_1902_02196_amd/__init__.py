@@ -90,6 +90,12 @@ _sig = {
     "vie_absorbed_power": (_i, [_vp, _i, _vp, _dp]),
     "vie_power_density": (_i, [_vp, _i, _vp, _vp]),
     "vie_copy": (_i, [_vp, _vp, _vp, ctypes.c_longlong]),
+    "vie_incident_planewave_h": (_i, [_vp, _dp, _dp, _d, _vp]),
+    "vie_incident_dipoles_h": (_i, [_vp, _i, _dp, _dp, _i, _vp]),
+    "vie_magnetic_field": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "vie_b1plus": (_i, [_vp, _i, _vp, _vp]),
+    "vie_magnetic_energy": (_i, [_vp, _i, _vp, _vp, _dp]),
+    "vie_get_curl_toeplitz": (_i, [_vp, _dp]),
     "vie_autotune": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _dp]),
     "vie_set_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(_i)]),
     "vie_fft_size": (_i, [_vp, ctypes.POINTER(_i)]),
@@ -315,6 +321,54 @@ class Context:
         _check(_lib.vie_total_field(self._h, n, _tensor_ptr(e_t, torch.complex128, self.vec_shape(n)),
                                     _tensor_ptr(x, torch.complex128, self.vec_shape(n)),
                                     _tensor_ptr(out, torch.complex128, self.vec_shape(n))))
+
+    def incident_planewave_h(self, out, pol=(1.0, 0.0, 0.0), direction=(0.0, 0.0, 1.0), amp=1.0):
+        """Tested incident magnetic field of the plane wave (1 / eta0 dir x E)."""
+        import torch
+        p = np.asarray(pol, dtype=np.float64)
+        d = np.asarray(direction, dtype=np.float64)
+        _check(_lib.vie_incident_planewave_h(self._h, _dptr(p), _dptr(d), float(amp),
+                                             _tensor_ptr(out, torch.complex128, self.vec_shape(1))))
+
+    def incident_dipoles_h(self, out, positions, moments, nq=4):
+        import torch
+        pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
+        mom = np.ascontiguousarray(moments, dtype=np.float64).reshape(-1, 3)
+        n = pos.shape[0]
+        _check(_lib.vie_incident_dipoles_h(self._h, n, _dptr(pos), _dptr(mom), int(nq),
+                                           _tensor_ptr(out, torch.complex128, self.vec_shape(n))))
+
+    def magnetic_field(self, h_t, x, out):
+        """h = G^-1 (h_t + K x): total magnetic field coefficients (curl operator)."""
+        import torch
+        n = x.shape[0]
+        _check(_lib.vie_magnetic_field(self._h, n, _tensor_ptr(h_t, torch.complex128, self.vec_shape(n)),
+                                       _tensor_ptr(x, torch.complex128, self.vec_shape(n)),
+                                       _tensor_ptr(out, torch.complex128, self.vec_shape(n))))
+
+    def b1plus(self, h, out):
+        """b1+ = mu0 (h_x + i h_y) per scalar basis: out (nrhs, 4, Nz, Ny, Nx)."""
+        import torch
+        n = h.shape[0]
+        _check(_lib.vie_b1plus(self._h, n, _tensor_ptr(h, torch.complex128, self.vec_shape(n)),
+                               _tensor_ptr(out, torch.complex128, (n, 4, self.N[2], self.N[1], self.N[0]))))
+
+    def magnetic_energy(self, h, density_out=None):
+        """W_m over the body per right-hand side (host array); the voxel
+        energy density into density_out (nrhs, Nz, Ny, Nx) float64 if given."""
+        import torch
+        n = h.shape[0]
+        W = np.zeros(n)
+        dens = None if density_out is None else ctypes.cast(
+            _tensor_ptr(density_out, torch.float64, (n, self.N[2], self.N[1], self.N[0])), _vp)
+        _check(_lib.vie_magnetic_energy(self._h, n, _tensor_ptr(h, torch.complex128, self.vec_shape(n)), dens,
+                                        _dptr(W)))
+        return W
+
+    def get_curl_toeplitz(self):
+        a = np.zeros((30, self.N[2], self.N[1], self.N[0]), dtype=np.complex128)
+        _check(_lib.vie_get_curl_toeplitz(self._h, a.view(np.float64).ctypes.data_as(_dp)))
+        return a
 
     def absorbed_power(self, x):
         import torch

@@ -47,7 +47,12 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs,
         if (it != c.tune.end()) tn = it->second;
     }
     VIE_REQUIRE(c.has_grid, VIE_ESTATE, "vie_apply before vie_set_grid");
-    if (op != OP_N) VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "operator needs vie_set_contrast");
+    if (op != OP_N && op != OP_CURL) VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "operator needs vie_set_contrast");
+    if (op == OP_CURL) {
+        VIE_REQUIRE(sizeof(R) == 8 && c.nc == 12, VIE_EINVAL,
+                    "the magnetic product is complex128 and PWL (12 unknowns per voxel) only");
+        VIE_REQUIRE(c.op && c.op->UK128, VIE_ESTATE, "curl operator not built");
+    }
     const int Nx = c.N[0], Ny = c.N[1], Nz = c.N[2];
     const int Mx = c.M[0], My = c.M[1], Mz = c.M[2];
     const int nc = c.nc;
@@ -137,7 +142,23 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs,
     p3.s_y = row;
     p3.u_e = c.O[0];
     p3.pitch = Mx;
-    if (nc == 3) {
+    if (op == OP_CURL) {
+        // curl operator: staged x pass (any length up to 256) on its 30
+        // unique tensors
+        if constexpr (sizeof(R) == 8) {
+            const int nt = p3_threads<R>();
+            const size_t ul = 30 * (size_t)c.O[0] * es;
+            int g = 4;
+            while (g > 1 && (ul + (size_t)lds_pad(g * 12 * Mx) * es > 80 * 1024 || !rows_fit(p3.plan, g * 12, nt) ||
+                             2 * g * Mx > nt))
+                --g;
+            p3.groups = g;
+            p3.variant = 0;
+            p3.sib_blocks = 1;
+            KernelTiming kt(c.prof, VIE_K_BLOCK, 2 * bA2 + 30.0 * c.Osz * es);
+            launch_p3_curl(A2, c.op->UK128, p3, twid<R>(c.ax[0]), s);
+        }
+    } else if (nc == 3) {
         // PWC: 6 of the operator's unique tensors per frequency
         VIE_REQUIRE(p3_ct_supported(Mx), VIE_EINVAL,
                     "the PWC x pass needs an fft length along x of 8, 16, 32, 64, 96, 128, 160, 192, 256, 320, 384 "
@@ -250,6 +271,13 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs,
                 ep.b = tau;
                 ep.gb[l] = R(scale / G[l]);
                 ep.rhs = rhs;
+                break;
+            case OP_CURL:   // h = (h_t + K x) / G, h_t in the epilogue's x slot
+                ep.x = rhs;
+                ep.a_const = 1;
+                ep.ga[l] = R(1.0 / G[l]);
+                ep.b_const = 1;
+                ep.gb[l] = R(scale / G[l]);
                 break;
         }
     }

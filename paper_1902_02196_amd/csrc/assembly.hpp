@@ -1,5 +1,10 @@
 // Tables for the on-device assembly of the Galerkin blocks (Sec. III-C).
 //
+// The curl operator K = curl S (eq. 8b, 25b) is assembled by the same code
+// from its own table: unique entry Q_k^{ll'}(d) = <N^l, S D_k N^{l'}>
+// (the derivative of g moved onto the basis function by parts), from which
+// K^{pl,ql'} = sum_k eps_pkq Q_k^{ll'}.
+//
 // Each entry N^{pl,ql'}(d) = delta_{d0} Gram + k0^2 delta_pq S^{ll'}(d) - C^{pl,ql'}(d)
 // (curl curl S = k0^2 S + grad div S + I, with grad div moved onto the test
 // and basis functions by parts).  Both S and C are 6-D integrals of
@@ -30,6 +35,7 @@ constexpr int kMaxGauss = 16;
 
 struct AssemblyTables {
     AxisKernel ker[48];
+    int nent;          // unique entries: 60 for N, 30 for the curl operator K
     EntryTerms ent[60];
     double gl_x[kMaxGauss + 1][kMaxGauss];   // Gauss-Legendre on [0, 1]
     double gl_w[kMaxGauss + 1][kMaxGauss];
@@ -63,6 +69,7 @@ struct FarBand {
 
 struct FarTables {
     FarBand band[kFarBands];
+    int nent;                      // unique entries (60 N, 30 K)
     int nterm;                     // flattened (entry, term) list
     int term_kx[kFarTerms];        // axis-kernel pair along x
     int term_pair[kFarTerms];      // index into the (ky, kz) pair list

@@ -288,6 +288,8 @@ static int axis_of(const double v[3]) {
     return (nz == 1 && std::fabs(std::fabs(v[ax]) - 1.0) < 1e-12) ? ax : -1;
 }
 
+static double sign_of(double v) { return v < 0 ? -1.0 : 1.0; }
+
 int vie_incident_planewave(vie_ctx* ctx, const double pol[3], const double dir[3], double amp, void* e_t) {
     return guarded([&] {
         check_ctx(ctx);
@@ -299,7 +301,7 @@ int vie_incident_planewave(vie_ctx* ctx, const double pol[3], const double dir[3
         VIE_REQUIRE(pa >= 0 && da >= 0 && pa != da, VIE_EINVAL,
                     "pol and dir must be distinct unit vectors along coordinate axes");
         launch_planewave(static_cast<double2*>(e_t), c.N[0], c.N[1], c.N[2], c.D, c.k0, pa, da, dir[da] > 0 ? 1.0 : -1.0,
-                         amp, c.nc, c.stream);
+                         amp * sign_of(pol[pa]), c.nc, c.stream);
     });
 }
 

@@ -119,6 +119,21 @@ constexpr __host__ __device__ __forceinline__ int unique_sign(int a, int b) {
     return (l > lp && lp == 1) ? -1 : 1;
 }
 
+// curl operator K = curl S: K^{(p,l),(q,l')} = eps_{pkq} Q_k^{ll'}, zero for
+// p = q, with the 30 unique tensors Q_k^{ll'} (l <= l') stored as 10 k + ll;
+// Q_k^{l'l} = s(l) s(l') Q_k^{ll'} (exchanging the two functions reflects w)
+constexpr __host__ __device__ __forceinline__ int levi(int p, int k, int q) {
+    return (p == k || k == q || p == q) ? 0 : (((k - p + 3) % 3 == 1) ? 1 : -1);
+}
+constexpr __host__ __device__ __forceinline__ int curl_unique_index(int a, int b) {
+    const int p = a >> 2, q = b >> 2;
+    return p == q ? -1 : 10 * (3 - p - q) + ll_index((a & 3) + 1, (b & 3) + 1);
+}
+constexpr __host__ __device__ __forceinline__ int curl_unique_sign(int a, int b) {
+    const int p = a >> 2, q = b >> 2;
+    return p == q ? 0 : levi(p, 3 - p - q, q) * unique_sign(a, b);
+}
+
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------

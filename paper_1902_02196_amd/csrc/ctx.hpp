@@ -3,6 +3,7 @@
 
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -28,6 +29,12 @@ struct OperatorData {
     double2* T = nullptr;
     double2* U128 = nullptr;
     float2* U64 = nullptr;
+    // curl operator K (eq. 8b, 25b), built on first use by a magnetic-field
+    // call: 30 unique tensors [30][V] and their octant [Oz][Oy][30][Ox],
+    // complex128
+    double2* TK = nullptr;
+    double2* UK128 = nullptr;
+    std::mutex curl_m;
     size_t bytes = 0;
     ~OperatorData() {
         for (auto& a : ax) {
@@ -37,6 +44,8 @@ struct OperatorData {
         if (T) (void)hipFree(T);
         if (U128) (void)hipFree(U128);
         if (U64) (void)hipFree(U64);
+        if (TK) (void)hipFree(TK);
+        if (UK128) (void)hipFree(UK128);
     }
 };
 
@@ -206,8 +215,9 @@ FftPlan make_plan(int n);
 bool smooth235(int n);
 void make_twiddles(int n, std::vector<double2>& tw);
 
-// operator products (apply.cpp)
-enum { OP_PREC = 0, OP_A = 1, OP_N = 2, OP_RESID = 3 };
+// operator products (apply.cpp); OP_CURL: h = G^-1 (h_t + K x) with the
+// curl operator, h_t passed as rhs (complex128, PWL basis)
+enum { OP_PREC = 0, OP_A = 1, OP_N = 2, OP_RESID = 3, OP_CURL = 4 };
 // ws_ext: caller-owned workspace of ws_cap bytes for the FFT intermediates
 // (VIE_EINVAL when the product needs more); nullptr: the context's own,
 // grown on demand
@@ -215,6 +225,10 @@ template <typename R>
 void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs, void* ws_ext = nullptr,
               size_t ws_cap = 0);
 size_t apply_workspace_bytes(const Ctx& c, int nrhs, size_t es);
+
+// build the curl operator of the context's grid if it is not there yet
+// (magnetic.cpp); shared operators build it once
+void ensure_curl(Ctx& c);
 
 // fixed per-device workspace of vie_apply_noalloc (noalloc.hip): looked up
 // once per device by vie_create with that device current

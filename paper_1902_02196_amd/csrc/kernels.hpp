@@ -33,6 +33,8 @@ void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStr
 // x pass of the PWC basis (3 component rows per pencil, compiled lengths only)
 template <typename R>
 void launch_p3_pwc(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s);
+// x pass of the curl operator K (complex128; U the [Oz][Oy][30][Ox] octant)
+void launch_p3_curl(double2* A, const double2* U, const P3Params& p, const double2* tw, hipStream_t s);
 bool p3_ct_supported(int n);
 int p3_ct_groups(int es, int n);
 bool p3_ct_fits(int es, int n);
@@ -51,10 +53,16 @@ void launch_rows(bool fwd, C<R>* data, long long nrows, const FftPlan& plan, con
 
 // operator.hip
 AssemblyTables build_assembly_tables(const double D[3], double k0);
+AssemblyTables build_curl_tables(const double D[3], double k0);
+// T.nent unique tensors [nent][Nz][Ny][Nx] for offsets d >= 0
 void assemble_blocks(double2* out, const AssemblyTables& T, int Nx, int Ny, int Nz, hipStream_t s);
 int unique_refl_sign(int e, int axis);
+int curl_refl_sign(int e, int axis);
+// circulant embedding, 3-D FFT and octant [Oz][Oy][nent][Ox] of the 60 N
+// tensors, or of the 30 curl tensors (curl = true; U64 may be null)
 void embed_and_transform(double2* U128, float2* U64, const double2* T, double2* circ, int Nx, int Ny, int Nz,
-                         int Mx, int My, int Mz, const FftPlan plans[3], const double2* const tw[3], hipStream_t s);
+                         int Mx, int My, int Mz, const FftPlan plans[3], const double2* const tw[3], hipStream_t s,
+                         bool curl = false);
 
 // setup.hip: materials, excitation, post-processing
 struct Materials {
@@ -70,9 +78,13 @@ void launch_materials(const double* eps_re, const double* sigma, double omega_ep
 // nc: unknowns per voxel (12 PWL, 3 PWC)
 void launch_planewave(double2* et, int Nx, int Ny, int Nz, const double D[3], double k0, int pol, int dir,
                       double sgn, double amp, int nc, hipStream_t s);
+// magnetic = 1: the dipoles' magnetic field, tested on every voxel
 void launch_dipoles(double2* et, int nrhs, const double* pos_dev, const double* mom_dev, int nq,
                     const double* glx, const double* glw, const double2* chi, int Nx, int Ny, int Nz,
-                    const double D[3], double k0, double omega_eps0, int nc, hipStream_t s);
+                    const double D[3], double k0, double omega_eps0, int nc, hipStream_t s, int magnetic = 0);
+void launch_b1plus(double2* b, const double2* h, double mu0, long long V, int nrhs, hipStream_t s);
+void launch_magnetic_energy(double* w, double* partial, const double2* h, const double2* chi, double mu0, double dv,
+                            long long V, int nrhs, int nblocks, hipStream_t s);
 void launch_rhs_prec(double2* rhs, const double2* et, const double2* tau, const double ginv[4], double2 ce,
                      long long V, int nrhs, int nc, hipStream_t s);
 void launch_fields(double2* e, const double2* x, const double2* chi, double2 ce, long long V, int nrhs, int nc,

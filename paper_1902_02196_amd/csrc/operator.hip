@@ -127,6 +127,28 @@ AssemblyTables build_assembly_tables(const double D[3], double k0) {
     T.k0 = k0;
     T.order_near = 14;
     T.order_duffy = 12;
+    T.nent = 60;
+    return T;
+}
+
+// the 30 unique tensors of the curl operator: entry 10 k + ll is
+// Q_k^{ll'}(d) = <N^l, S D_k N^{l'}> (l <= l'), one term, no Gram part
+AssemblyTables build_curl_tables(const double D[3], double k0) {
+    AssemblyTables T = build_assembly_tables(D, k0);
+    static const int L[10] = {1, 1, 1, 1, 2, 2, 2, 3, 3, 4}, LP[10] = {1, 2, 3, 4, 2, 3, 4, 3, 4, 4};
+    for (int k = 0; k < 3; ++k)
+        for (int ll = 0; ll < 10; ++ll) {
+            EntryTerms& e = T.ent[10 * k + ll];
+            e.nterm = 1;
+            e.coef[0] = 1.0;
+            for (int ax = 0; ax < 3; ++ax) {
+                const int kt = (L[ll] == ax + 2) ? 1 : 0;
+                const int kb = ((LP[ll] == ax + 2) ? 1 : 0) + (ax == k ? 2 : 0);
+                e.ker[0][ax] = ax * 16 + kt * 4 + kb;
+            }
+            e.gram_l = -1;
+        }
+    T.nent = 30;
     return T;
 }
 
@@ -336,7 +358,8 @@ FarTables build_far_tables(const AssemblyTables& T) {
     }
     F.nterm = 0;
     F.npair = 0;
-    for (int e = 0; e < 60; ++e) {
+    F.nent = T.nent;
+    for (int e = 0; e < T.nent; ++e) {
         const EntryTerms& E = T.ent[e];
         F.ent_first[e] = F.nterm;
         F.ent_count[e] = E.nterm;
@@ -397,7 +420,7 @@ void assemble_far_serial(const FarTables& F, const AssemblyTables& T, int b, con
             S[t].y += wx * t2[F.term_pair[t]].y;
         }
     }
-    for (int e = 0; e < 60; ++e) {
+    for (int e = 0; e < F.nent; ++e) {
         double2 a = make_double2(0, 0);
         for (int t = F.ent_first[e]; t < F.ent_first[e] + F.ent_count[e]; ++t) {
             a.x += F.term_coef[t] * S[t].x;
@@ -488,7 +511,7 @@ __global__ void __launch_bounds__(64) k_assemble_far(double2* __restrict__ out, 
         if (tid < nterm) t2[tid] = s0;
         if (tid + 64 < nterm) t2[tid + 64] = s1;
         __syncthreads();
-        if (tid < 60) {
+        if (tid < F.nent) {
             double2 a = make_double2(0, 0);
             for (int t = F.ent_first[tid]; t < F.ent_first[tid] + F.ent_count[tid]; ++t) {
                 a.x += F.term_coef[t] * t2[t].x;
@@ -572,7 +595,7 @@ __global__ void k_embed(double2* __restrict__ circ, const double2* __restrict__ 
 // keep the octant xi_i <= M_i / 2 of a transformed circulant, stored as
 // U[oz][oy][e][ox] (the 60 entries of one (oz, oy) row together)
 __global__ void k_octant(double2* __restrict__ U128, float2* __restrict__ U64, const double2* __restrict__ circ,
-                         int e, int Mx, int My, int Ox, int Oy, int Oz) {
+                         int e, int nent, int Mx, int My, int Ox, int Oy, int Oz) {
     const long long O = (long long)Ox * Oy * Oz;
     const long long o = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (o >= O) return;
@@ -580,9 +603,9 @@ __global__ void k_octant(double2* __restrict__ U128, float2* __restrict__ U64, c
     const long long row = o / Ox;   // oz * Oy + oy
     const int oy = int(row % Oy), oz = int(row / Oy);
     const double2 v = circ[((long long)oz * My + oy) * Mx + ox];
-    const long long dst = (row * 60 + e) * Ox + ox;
+    const long long dst = (row * nent + e) * Ox + ox;
     U128[dst] = v;
-    U64[dst] = make_float2((float)v.x, (float)v.y);
+    if (U64) U64[dst] = make_float2((float)v.x, (float)v.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -598,7 +621,7 @@ void assemble_blocks(double2* out, const AssemblyTables& T, int Nx, int Ny, int 
     VIE_HIP(hipMemcpyAsync(dT, &T, sizeof(AssemblyTables), hipMemcpyHostToDevice, s));
     VIE_HIP(hipMemcpyAsync(dF, &F, sizeof(FarTables), hipMemcpyHostToDevice, s));
     const long long V = (long long)Nx * Ny * Nz;
-    hipLaunchKernelGGL(k_assemble_near, dim3(60), dim3(64), 0, s, out, dT, Nx, Ny, Nz);
+    hipLaunchKernelGGL(k_assemble_near, dim3(T.nent), dim3(64), 0, s, out, dT, Nx, Ny, Nz);
     VIE_HIP(hipGetLastError());
     const int dmax = std::max(Nx, std::max(Ny, Nz)) - 1;
     for (int b = 0; b < kFarBands; ++b) {
@@ -641,16 +664,32 @@ int unique_refl_sign(int e, int axis) {
     return refl_sign(axis, a) * refl_sign(axis, b);
 }
 
+// reflection sign of curl tensor e = 10 k + ll along an axis: the linear
+// functions along the axis change sign, and d_k g is odd along k, so
+// K(.., -d_i, ..) = -sigma_i(a) sigma_i(b) K(.., d_i, ..)
+int curl_refl_sign(int e, int axis) {
+    static const int L[10] = {1, 1, 1, 1, 2, 2, 2, 3, 3, 4}, LP[10] = {1, 2, 3, 4, 2, 3, 4, 3, 4, 4};
+    const int k = e / 10, ll = e % 10;
+    int s = 1;
+    if (L[ll] == axis + 2) s = -s;
+    if (LP[ll] == axis + 2) s = -s;
+    if (k == axis) s = -s;
+    return s;
+}
+
 void embed_and_transform(double2* U128, float2* U64, const double2* T, double2* circ, int Nx, int Ny, int Nz,
                          int Mx, int My, int Mz, const FftPlan plans[3], const double2* const tw[3],
-                         hipStream_t s) {
+                         hipStream_t s, bool curl) {
     const long long V = (long long)Nx * Ny * Nz;
     const long long M = (long long)Mx * My * Mz;
     const int Ox = Mx / 2 + 1, Oy = My / 2 + 1, Oz = Mz / 2 + 1;
     const long long O = (long long)Ox * Oy * Oz;
-    for (int e = 0; e < 60; ++e) {
+    const int nent = curl ? 30 : 60;
+    for (int e = 0; e < nent; ++e) {
+        int sg[3];
+        for (int ax = 0; ax < 3; ++ax) sg[ax] = curl ? curl_refl_sign(e, ax) : unique_refl_sign(e, ax);
         hipLaunchKernelGGL(k_embed, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, circ, T + e * V, Nx, Ny, Nz,
-                           Mx, My, Mz, unique_refl_sign(e, 0), unique_refl_sign(e, 1), unique_refl_sign(e, 2));
+                           Mx, My, Mz, sg[0], sg[1], sg[2]);
         VIE_HIP(hipGetLastError());
         // z pass: pencils along z, inner x (full length)
         StridedPass pz{};
@@ -676,8 +715,8 @@ void embed_and_transform(double2* U128, float2* U64, const double2* T, double2* 
         py.in_sk = py.out_sk = Mx;
         launch_strided<double>(true, circ, circ, py, Mz, 1, tw[1], nullptr, s);
         launch_rows<double>(true, circ, (long long)My * Mz, plans[0], tw[0], s);
-        hipLaunchKernelGGL(k_octant, dim3((unsigned)((O + 255) / 256)), dim3(256), 0, s, U128, U64, circ, e, Mx, My,
-                           Ox, Oy, Oz);
+        hipLaunchKernelGGL(k_octant, dim3((unsigned)((O + 255) / 256)), dim3(256), 0, s, U128, U64, circ, e, nent,
+                           Mx, My, Ox, Oy, Oz);
         VIE_HIP(hipGetLastError());
     }
 }

@@ -92,45 +92,63 @@ __device__ __forceinline__ void row_dot(C<R>& y, const C<R>* xv, const C<R>* Uro
     if constexpr (B + 1 < 12) row_dot<R, A, B + 1>(y, xv, Urow, ue, ox);
 }
 
+// the same row of the curl operator's block (30 unique tensors; the
+// entries with p = q are zero and skipped)
+template <typename R, int A, int B>
+__device__ __forceinline__ void row_dot_curl(C<R>& y, const C<R>* xv, const C<R>* Urow, long long ue, int ox) {
+    constexpr int e = curl_unique_index(A, B);
+    constexpr int sg = curl_unique_sign(A, B);
+    if constexpr (sg != 0) {
+        const C<R> u = Urow[e * ue + ox];
+        if constexpr (sg > 0) cfma(y, u, xv[B]);
+        else cfma(y, mk<R>(-u.x, -u.y), xv[B]);
+    }
+    if constexpr (B + 1 < 12) row_dot_curl<R, A, B + 1>(y, xv, Urow, ue, ox);
+}
+
 // rows [A, AEND) of the 12 x 12 block product into yv[A - A0]
-template <typename R, int A0, int A, int AEND>
+template <typename R, bool CURL, int A0, int A, int AEND>
 __device__ __forceinline__ void rows_product(C<R>* yv, const C<R>* xv, const C<R>* Urow, long long ue, int ox) {
     if constexpr (A < AEND) {
         C<R> y = mk<R>(0, 0);
-        row_dot<R, A, 0>(y, xv, Urow, ue, ox);
+        if constexpr (CURL) row_dot_curl<R, A, 0>(y, xv, Urow, ue, ox);
+        else row_dot<R, A, 0>(y, xv, Urow, ue, ox);
         yv[A - A0] = y;
-        rows_product<R, A0, A + 1, AEND>(yv, xv, Urow, ue, ox);
+        rows_product<R, CURL, A0, A + 1, AEND>(yv, xv, Urow, ue, ox);
     }
 }
 
 // rows [6 h, 6 h + 6) (split 2) or [3 h, 3 h + 3) (split 4)
-template <typename R, int SPLIT>
+template <typename R, int SPLIT, bool CURL = false>
 __device__ __forceinline__ void part_product(int h, C<R>* yv, const C<R>* xv, const C<R>* Urow, long long ue,
                                              int ox) {
     if constexpr (SPLIT == 2) {
-        if (h == 0) rows_product<R, 0, 0, 6>(yv, xv, Urow, ue, ox);
-        else rows_product<R, 6, 6, 12>(yv, xv, Urow, ue, ox);
+        if (h == 0) rows_product<R, CURL, 0, 0, 6>(yv, xv, Urow, ue, ox);
+        else rows_product<R, CURL, 6, 6, 12>(yv, xv, Urow, ue, ox);
     } else {
-        if (h == 0) rows_product<R, 0, 0, 3>(yv, xv, Urow, ue, ox);
-        else if (h == 1) rows_product<R, 3, 3, 6>(yv, xv, Urow, ue, ox);
-        else if (h == 2) rows_product<R, 6, 6, 9>(yv, xv, Urow, ue, ox);
-        else rows_product<R, 9, 9, 12>(yv, xv, Urow, ue, ox);
+        if (h == 0) rows_product<R, CURL, 0, 0, 3>(yv, xv, Urow, ue, ox);
+        else if (h == 1) rows_product<R, CURL, 3, 3, 6>(yv, xv, Urow, ue, ox);
+        else if (h == 2) rows_product<R, CURL, 6, 6, 9>(yv, xv, Urow, ue, ox);
+        else rows_product<R, CURL, 9, 9, 12>(yv, xv, Urow, ue, ox);
     }
 }
 
 // One workgroup per octant row (xi_z', xi_y'): the up to four pencils
 // (+-xi_y, +-xi_z) that share it, for every right-hand side.  The operator
-// row (60 unique entries x Ox frequencies) is staged in LDS once.  `groups`
+// row (NE unique entries x Ox frequencies) is staged in LDS once.  `groups`
 // pencil groups (12 component rows each) then go through LDS together:
 // load (zero-padded from Nx to Mx), forward FFT in place, block product per
 // frequency (SPLIT threads per column, each a slice of the 12 output rows),
-// inverse FFT, store the first Nx.
-template <typename R, int SPLIT>
+// inverse FFT, store the first Nx.  CURL selects the curl operator (30
+// unique tensors); its spectrum changes sign under each octant fold on top
+// of the component signs (the curl is odd under reflection).
+template <typename R, int SPLIT, bool CURL = false>
 __global__ void __launch_bounds__(p3_threads<R>()) k_p3(C<R>* __restrict__ A, const C<R>* __restrict__ U,
                                                         P3Params p, const C<R>* __restrict__ tw) {
+    constexpr int NE = CURL ? 30 : 60;
     extern __shared__ unsigned char smem_raw[];
     C<R>* Ul = reinterpret_cast<C<R>*>(smem_raw);
-    C<R>* buf = Ul + 60 * p.Ox;
+    C<R>* buf = Ul + NE * p.Ox;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int Mx = p.plan.n;
     const int row = blockIdx.x;
@@ -140,8 +158,8 @@ __global__ void __launch_bounds__(p3_threads<R>()) k_p3(C<R>* __restrict__ A, co
     const int nsib = ny_sib * nz_sib;
     const int nwork = nsib * p.nrhs;
     {
-        const C<R>* Urow = U + (long long)(oz * p.Oy + oy) * 60 * p.Ox;
-        for (int idx = tid; idx < 60 * p.Ox; idx += nthr) {
+        const C<R>* Urow = U + (long long)(oz * p.Oy + oy) * NE * p.Ox;
+        for (int idx = tid; idx < NE * p.Ox; idx += nthr) {
             const int e = idx / p.Ox, ox = idx - e * p.Ox;
             Ul[idx] = Urow[e * p.u_e + ox];
         }
@@ -167,7 +185,7 @@ __global__ void __launch_bounds__(p3_threads<R>()) k_p3(C<R>* __restrict__ A, co
             const int h = tid / ncol, col = tid - h * ncol;
             const int g = col / Mx, xi = col - g * Mx;
             C<R> xv[12], yv[RP];
-            unsigned mask = 0;
+            unsigned mask = 0, omask = 0;
             int ox = 0;
             if (act) {
                 const int wk = w0 + g, sib = wk % nsib;
@@ -175,6 +193,7 @@ __global__ void __launch_bounds__(p3_threads<R>()) k_p3(C<R>* __restrict__ A, co
                 const int fx = 2 * xi > Mx;
                 ox = fx ? Mx - xi : xi;
                 mask = fold_mask(fx, sy, sz);
+                omask = (CURL && ((fx + sy + sz) & 1)) ? (mask ^ 0xFFFu) : mask;
 #pragma unroll
                 for (int a = 0; a < 12; ++a) {
                     C<R> v = buf[lds_pad((g * 12 + a) * p.pitch + xi)];
@@ -184,12 +203,12 @@ __global__ void __launch_bounds__(p3_threads<R>()) k_p3(C<R>* __restrict__ A, co
             }
             __syncthreads();
             if (act) {
-                part_product<R, SPLIT>(h, yv, xv, Ul, p.Ox, ox);
+                part_product<R, SPLIT, CURL>(h, yv, xv, Ul, p.Ox, ox);
 #pragma unroll
                 for (int i = 0; i < RP; ++i) {
                     const int a = RP * h + i;
                     C<R> v = yv[i];
-                    if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                    if (omask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
                     buf[lds_pad((g * 12 + a) * p.pitch + xi)] = v;
                 }
             }
@@ -1025,6 +1044,29 @@ void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStr
     });
     if (split4) timed_launch(k_p3<R, 4>, dim3(p.Oy * p.Oz), dim3(nt), (unsigned)lds, s, A, U, p, tw);
     else timed_launch(k_p3<R, 2>, dim3(p.Oy * p.Oz), dim3(nt), (unsigned)lds, s, A, U, p, tw);
+    VIE_HIP(hipGetLastError());
+}
+
+// x pass of the curl operator (complex128, the staged kernel for any length
+// whose rows fit; a post-processing product, not on the solver's path)
+void launch_p3_curl(double2* A, const double2* U, const P3Params& p, const double2* tw, hipStream_t s) {
+    using R = double;
+    const int nt = p3_threads<R>();
+    VIE_REQUIRE(rows_fit(p.plan, p.groups * 12, nt) && 2 * p.groups * p.plan.n <= nt, -1,
+                "magnetic product: fft length along x above 256");
+    const size_t lds = (30 * (size_t)p.Ox + lds_pad(p.groups * 12 * p.pitch) + 2) * sizeof(C<R>);
+    VIE_REQUIRE(lds <= 150 * 1024, -1, "magnetic product: x rows do not fit LDS");
+    const bool split4 = 4 * p.groups * p.plan.n <= nt;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        (void)hipFuncSetAttribute((const void*)k_p3<R, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  150 * 1024);
+        (void)hipFuncSetAttribute((const void*)k_p3<R, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  150 * 1024);
+        (void)hipGetLastError();
+    });
+    if (split4) timed_launch(k_p3<R, 4, true>, dim3(p.Oy * p.Oz), dim3(nt), (unsigned)lds, s, A, U, p, tw);
+    else timed_launch(k_p3<R, 2, true>, dim3(p.Oy * p.Oz), dim3(nt), (unsigned)lds, s, A, U, p, tw);
     VIE_HIP(hipGetLastError());
 }
 

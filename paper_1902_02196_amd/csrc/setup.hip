@@ -79,17 +79,21 @@ void launch_planewave(double2* et, int Nx, int Ny, int Nz, const double D[3], do
 
 // Hertzian dipole of current moment m at r0:
 // E = (1/c_e) exp(-i k R)/(4 pi R^3) [(k^2 R^2 - i k R - 1) m + (3 + 3 i k R - k^2 R^2)(R_hat . m) R_hat]
+// and (magnetic = 1) H = curl (g m) = (1 + i k R) exp(-i k R)/(4 pi R^2) (m x R_hat), the
+// h = K j of eq. 'tot_fields' b for a point current.  The electric field is
+// tested on voxels with chi != 0 (chi may be null: every voxel), the magnetic
+// one on every voxel.
 __global__ void k_dipoles(double2* __restrict__ et, const double* __restrict__ pos, const double* __restrict__ mom,
                           int nq, const double* __restrict__ glx, const double* __restrict__ glw,
                           const double2* __restrict__ chi, int Nx, int Ny, int Nz, double Dx, double Dy, double Dz,
-                          double k0, double weps0, int nc) {
+                          double k0, double weps0, int nc, int magnetic) {
     const long long V = (long long)Nx * Ny * Nz;
     const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     if (v >= V) return;
     double2* out = et + (long long)r * nc * V;
-    const double2 ch = chi[v];
-    if (ch.x == 0.0 && ch.y == 0.0) {
+    const double2 ch = chi ? chi[v] : make_double2(1.0, 0.0);
+    if (!magnetic && ch.x == 0.0 && ch.y == 0.0) {
         for (int a = 0; a < nc; ++a) out[a * V + v] = make_double2(0, 0);
         return;
     }
@@ -113,16 +117,25 @@ __global__ void k_dipoles(double2* __restrict__ et, const double* __restrict__ p
                 const double kr = k0 * R;
                 double s, c;
                 sincos(kr, &s, &c);
-                // pre = exp(-i k R)/(4 pi R^3) / (i w eps0) = exp(-i k R) * (-i) / (4 pi R^3 w eps0)
-                const double amp = 1.0 / (4.0 * M_PI * R * R * R * weps0);
-                const double2 pre = make_double2(-s * amp, -c * amp);   // (c - i s)(-i) amp
-                const double2 A = make_double2(kr * kr - 1.0, -kr);      // k^2R^2 - i kR - 1
-                const double hm = hx * mx + hy * my + hz * mz;
-                const double2 B = make_double2((3.0 - kr * kr) * hm, 3.0 * kr * hm);
-                const double E[3][2] = {
-                    {A.x * mx + B.x * hx, A.y * mx + B.y * hx},
-                    {A.x * my + B.x * hy, A.y * my + B.y * hy},
-                    {A.x * mz + B.x * hz, A.y * mz + B.y * hz}};
+                double2 pre;
+                double E[3][2];
+                if (magnetic) {
+                    // (1 + i kR)(c - i s) / (4 pi R^2), times m x R_hat (real)
+                    const double amp = 1.0 / (4.0 * M_PI * R * R);
+                    pre = make_double2((c + kr * s) * amp, (kr * c - s) * amp);
+                    const double cr[3] = {my * hz - mz * hy, mz * hx - mx * hz, mx * hy - my * hx};
+                    for (int p = 0; p < 3; ++p) { E[p][0] = cr[p]; E[p][1] = 0.0; }
+                } else {
+                    // pre = exp(-i k R)/(4 pi R^3) / (i w eps0) = exp(-i k R) * (-i) / (4 pi R^3 w eps0)
+                    const double amp = 1.0 / (4.0 * M_PI * R * R * R * weps0);
+                    pre = make_double2(-s * amp, -c * amp);                  // (c - i s)(-i) amp
+                    const double2 A = make_double2(kr * kr - 1.0, -kr);      // k^2R^2 - i kR - 1
+                    const double hm = hx * mx + hy * my + hz * mz;
+                    const double2 B = make_double2((3.0 - kr * kr) * hm, 3.0 * kr * hm);
+                    E[0][0] = A.x * mx + B.x * hx; E[0][1] = A.y * mx + B.y * hx;
+                    E[1][0] = A.x * my + B.x * hy; E[1][1] = A.y * my + B.y * hy;
+                    E[2][0] = A.x * mz + B.x * hz; E[2][1] = A.y * mz + B.y * hz;
+                }
                 const double nl[4] = {1.0, tx, ty, tz};
                 for (int p = 0; p < 3; ++p) {
                     const double er = pre.x * E[p][0] - pre.y * E[p][1];
@@ -143,10 +156,64 @@ __global__ void k_dipoles(double2* __restrict__ et, const double* __restrict__ p
 
 void launch_dipoles(double2* et, int nrhs, const double* pos, const double* mom, int nq, const double* glx,
                     const double* glw, const double2* chi, int Nx, int Ny, int Nz, const double D[3], double k0,
-                    double weps0, int nc, hipStream_t s) {
+                    double weps0, int nc, hipStream_t s, int magnetic) {
     const long long V = (long long)Nx * Ny * Nz;
     hipLaunchKernelGGL(k_dipoles, dim3((unsigned)((V + 127) / 128), nrhs), dim3(128), 0, s, et, pos, mom, nq, glx,
-                       glw, chi, Nx, Ny, Nz, D[0], D[1], D[2], k0, weps0, nc);
+                       glw, chi, Nx, Ny, Nz, D[0], D[1], D[2], k0, weps0, nc, magnetic);
+    VIE_HIP(hipGetLastError());
+}
+
+// b1+ = mu0 (h_x + i h_y) per scalar basis (Sec. V-D): b[r][l][v] from the
+// PWL coefficients h^{x,l}, h^{y,l}
+__global__ void k_b1plus(double2* __restrict__ b, const double2* __restrict__ h, double mu0, long long V, int nrhs) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= 4 * V * nrhs) return;
+    const long long r = i / (4 * V), rem = i - r * 4 * V;      // rem = l V + v
+    const double2 hx = h[r * 12 * V + rem], hy = h[r * 12 * V + 4 * V + rem];
+    b[i] = make_double2(mu0 * (hx.x - hy.y), mu0 * (hx.y + hy.x));
+}
+
+void launch_b1plus(double2* b, const double2* h, double mu0, long long V, int nrhs, hipStream_t s) {
+    const long long n = 4 * V * nrhs;
+    hipLaunchKernelGGL(k_b1plus, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b, h, mu0, V, nrhs);
+    VIE_HIP(hipGetLastError());
+}
+
+// magnetic energy density w_m = 1/4 mu0 |h|^2 averaged over each voxel (Sec.
+// V-D; Gram weights 1 and 1/12), into w (may be null), and per-block partial
+// sums of w_m dV over the voxels with chi != 0 (W_m inside the body)
+__global__ void __launch_bounds__(256) k_magnetic_energy(double* __restrict__ w, double* __restrict__ partial,
+                                                         const double2* __restrict__ h,
+                                                         const double2* __restrict__ chi, double mu0, double dv,
+                                                         long long V) {
+    __shared__ double red[256];
+    const int r = blockIdx.y;
+    const double2* hr = h + (long long)r * 12 * V;
+    double acc = 0.0;
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < V;
+         v += (long long)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int a = 0; a < 12; ++a) {
+            const double2 z = hr[a * V + v];
+            s += ((a & 3) == 0 ? 1.0 : 1.0 / 12.0) * (z.x * z.x + z.y * z.y);
+        }
+        const double wm = 0.25 * mu0 * s;
+        if (w) w[(long long)r * V + v] = wm;
+        const double2 ch = chi[v];
+        if (ch.x != 0.0 || ch.y != 0.0) acc += wm * dv;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[r * gridDim.x + blockIdx.x] = red[0];
+}
+
+void launch_magnetic_energy(double* w, double* partial, const double2* h, const double2* chi, double mu0, double dv,
+                            long long V, int nrhs, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_magnetic_energy, dim3(nblocks, nrhs), dim3(256), 0, s, w, partial, h, chi, mu0, dv, V);
     VIE_HIP(hipGetLastError());
 }
 
