@@ -29,6 +29,7 @@ __host__ __device__ constexpr int ct_radix(int n, int s) {
 // HOUT: only the lower half of each row is used afterwards (a cropped inverse
 // transform, last pass only): the upper half is neither stored nor, once the
 // compiler drops the dead arithmetic, computed.
+// Rows are pitch = N elements apart before padding (every caller).
 template <typename R, bool FWD, int N, int RAD, int NS, int NTHR, int MAXROWS, bool HIN = false,
           bool HOUT = false>
 __device__ __forceinline__ void ct_pass(C<R>* buf, const C<R>* twl, int rows, int pitch, int tid) {
@@ -37,6 +38,17 @@ __device__ __forceinline__ void ct_pass(C<R>* buf, const C<R>* twl, int rows, in
     constexpr int nb = N / RAD;
     constexpr int NB = (MAXROWS * nb + NTHR - 1) / NTHR;
     constexpr int twstep = N / (NS * RAD);
+    // Padded addresses lds_pad(t N + c) of a row made of whole 16-element
+    // blocks (N % 16 == 0; rows are N apart): t (N + N / 16) + c + (c >> 4).
+    // For the c a butterfly touches, c = c0 + i S with stride S, the block
+    // term splits into a per-thread part and a compile-time part when S is
+    // a multiple of 16, or S divides 16 and c0's position keeps c0 + i S in
+    // the block of i S (every pass below): then the address is one per-thread
+    // base plus constant offsets, with no per-element index arithmetic.
+    constexpr int RB = N + N / 16;
+    constexpr bool AFF_IN = N % 16 == 0 && (nb % 16 == 0 || 16 % nb == 0);
+    constexpr bool AFF_OUT = N % 16 == 0 && (NS % 16 == 0 ||
+                                             (16 % NS == 0 && ((NS * RAD) % 16 == 0 || 16 % (NS * RAD) == 0)));
     const int total = rows * nb;
     C<R> v[NB][RAD];
 #pragma unroll
@@ -44,9 +56,15 @@ __device__ __forceinline__ void ct_pass(C<R>* buf, const C<R>* twl, int rows, in
         const int idx = tid + q * NTHR;
         if (idx < total) {
             const int t = idx / nb, j = idx - t * nb;
-            const int rb = t * pitch + j;
+            if constexpr (AFF_IN) {
+                const C<R>* src = buf + (t * RB + j + (j >> 4));
 #pragma unroll
-            for (int i = 0; i < (HIN ? RAD / 2 : RAD); ++i) v[q][i] = buf[lds_pad(rb + i * nb)];
+                for (int i = 0; i < (HIN ? RAD / 2 : RAD); ++i) v[q][i] = src[i * nb + ((i * nb) >> 4)];
+            } else {
+                const int rb = t * pitch + j;
+#pragma unroll
+                for (int i = 0; i < (HIN ? RAD / 2 : RAD); ++i) v[q][i] = buf[lds_pad(rb + i * nb)];
+            }
         }
     }
     __syncthreads();
@@ -66,9 +84,16 @@ __device__ __forceinline__ void ct_pass(C<R>* buf, const C<R>* twl, int rows, in
             }
             if constexpr (HIN) dft_r_halfin<R, FWD, RAD>(v[q]);
             else dft_r<R, FWD, RAD>(v[q]);
-            const int rb = t * pitch + (j - k) * RAD + k;
+            if constexpr (AFF_OUT) {
+                const int b0 = (j - k) * RAD + k;
+                C<R>* dst = buf + (t * RB + b0 + (b0 >> 4));
 #pragma unroll
-            for (int i = 0; i < (HOUT ? RAD / 2 : RAD); ++i) buf[lds_pad(rb + i * NS)] = v[q][i];
+                for (int i = 0; i < (HOUT ? RAD / 2 : RAD); ++i) dst[i * NS + ((i * NS) >> 4)] = v[q][i];
+            } else {
+                const int rb = t * pitch + (j - k) * RAD + k;
+#pragma unroll
+                for (int i = 0; i < (HOUT ? RAD / 2 : RAD); ++i) buf[lds_pad(rb + i * NS)] = v[q][i];
+            }
         }
     }
     __syncthreads();
