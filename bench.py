@@ -268,6 +268,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--reorth", type=int, default=0, help="second Gram-Schmidt pass (1) or not (0)")
     ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--graph", type=int, default=1, help="replay the Arnoldi steps from HIP graphs (1) or not (0)")
+    ap.add_argument("--sync-steps", type=int, default=0,
+                    help="Arnoldi steps per host check of the convergence flag (0: automatic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -344,8 +347,9 @@ def main():
     log("setup: grid+operator %.2f s" % t_grid)
 
     opts_ir = vie.default_opts(mode=vie.SOLVE_FP32_IR, tol=1e-6, restart=args.restart, inner_tol=1e-5,
-                               reorth=args.reorth)
-    opts_64 = vie.default_opts(mode=vie.SOLVE_FP64, tol=1e-6, restart=args.restart, reorth=args.reorth)
+                               reorth=args.reorth, graph=args.graph, sync_steps=args.sync_steps)
+    opts_64 = vie.default_opts(mode=vie.SOLVE_FP64, tol=1e-6, restart=args.restart, reorth=args.reorth,
+                               graph=args.graph, sync_steps=args.sync_steps)
     for i in range(args.warmup):
         code, st = solve_all(opts_ir)
         log("warmup %d: %s" % (i, st[0]))

@@ -81,6 +81,17 @@ typedef struct {
                             cycles run                                        */
     int reorth;          /* 1: second Gram-Schmidt pass per Arnoldi step      */
     int use_x0;          /* 1: x holds the initial guess, 0: start from zero  */
+    int graph;           /* 1: replay the Arnoldi steps from HIP graphs (a
+                            run of steps is captured the second time the
+                            solver reaches it with the same shapes and
+                            buffers), 0: launch every kernel; the results
+                            are the same bits either way                      */
+    int sync_steps;      /* Arnoldi steps per host check of the device-side
+                            convergence flag (the Givens rotations and the
+                            residual estimate run on the device); 0: chosen
+                            from the vector size.  Larger values cost fewer
+                            host round trips and up to 2 sync_steps - 1
+                            steps computed past convergence                   */
 } vie_solve_opts;
 
 typedef struct {

@@ -27,6 +27,7 @@ Ctx::~Ctx() {
 }
 
 void Ctx::free_grid() {
+    graphs.clear();
     op.reset();   // frees the operator unless another context shares it
     for (auto& a : ax) a = FftAxis{};
     T = nullptr;
@@ -36,6 +37,7 @@ void Ctx::free_grid() {
 }
 
 void Ctx::free_contrast() {
+    graphs.clear();
     void* ps[] = {mat.eps_r, mat.chi, mat.tau, mat.tau64, mat.epsr64, mat.chi64, sigma};
     for (void* p : ps)
         if (p) (void)hipFree(p);
@@ -378,6 +380,8 @@ void vie_default_opts(vie_solve_opts* o) {
     o->max_refine = 400;
     o->reorth = 0;
     o->use_x0 = 0;
+    o->graph = 1;
+    o->sync_steps = 0;
 }
 
 int vie_solve(vie_ctx* ctx, const vie_solve_opts* opts, int nrhs, const void* e_t, void* x, vie_solve_stats* stats) {
@@ -395,6 +399,7 @@ int vie_solve(vie_ctx* ctx, const vie_solve_opts* opts, int nrhs, const void* e_
         VIE_REQUIRE(o.max_outer >= 1 && o.tol > 0 && o.tol < 1, VIE_EINVAL, "bad tolerance or max_outer");
         VIE_REQUIRE(o.mode == VIE_SOLVE_FP64 || o.mode == VIE_SOLVE_FP32_IR, VIE_EINVAL, "unknown mode");
         VIE_REQUIRE(o.mode != VIE_SOLVE_FP32_IR || o.max_refine >= 1, VIE_EINVAL, "max_refine must be >= 1");
+        VIE_REQUIRE(o.sync_steps >= 0, VIE_EINVAL, "sync_steps must be >= 0");
         rc = solve(c, o, nrhs, static_cast<const double2*>(e_t), static_cast<double2*>(x), stats);
         if (rc == VIE_ENOCONV) g_err = "solver stopped before reaching the tolerance";
         if (rc == VIE_ENAN) g_err = "non-finite residual";
@@ -502,6 +507,7 @@ int vie_set_basis(vie_ctx* ctx, int ncomp) {
         Ctx& c = ctx->c;
         c.nc = ncomp;
         c.tune.clear();
+        c.graphs.clear();
     });
 }
 
@@ -541,6 +547,7 @@ int vie_set_tuning(vie_ctx* ctx, int precision, int nrhs, const int* choice) {
                     VIE_EINVAL, "workgroups per row must be 1 (or 2, 4 for variant 0)");
         VIE_REQUIRE(strided_tile_ok(es, c.M[2], t.tile_z) && strided_tile_ok(es, c.M[1], t.tile_y), VIE_EINVAL,
                     "tile not available for this fft size (8 or 16, or 32 with a compiled length)");
+        c.graphs.clear();
         c.tune[{precision == VIE_C64 ? 0 : 1, nrhs}] = t;
     });
 }

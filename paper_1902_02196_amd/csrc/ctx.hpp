@@ -161,6 +161,27 @@ struct KernelTiming {
     }
 };
 
+// Captured runs of Arnoldi steps (solver.cpp), by their launch key: shapes,
+// step range and the buffers the launches name.  A key seen for the first
+// time runs uncaptured (which also sizes every lazily grown buffer); the
+// second time it is captured on a private stream and instantiated; later
+// uses replay it.  Cleared whenever the grid, materials, basis or launch
+// shapes change.
+struct GraphCache {
+    std::map<std::vector<long long>, hipGraphExec_t> execs;
+    hipStream_t cap = nullptr;   // capture stream (the context's may be the null stream)
+    static constexpr size_t kMax = 512;
+    void clear() {
+        for (auto& kv : execs)
+            if (kv.second) (void)hipGraphExecDestroy(kv.second);
+        execs.clear();
+    }
+    ~GraphCache() {
+        clear();
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
 // launch shapes of the operator product, chosen per (precision, nrhs) by
 // the autotuner; zeros mean the built-in defaults
 struct Tune {
@@ -204,6 +225,7 @@ struct Ctx {
 
     Profiler prof;
     std::map<std::pair<int, int>, Tune> tune;   // (precision, nrhs) -> shapes
+    GraphCache graphs;
 
     ~Ctx();
     void free_grid();

@@ -21,7 +21,8 @@ template <typename F, typename... Args>
 inline void timed_launch(F kernel, const dim3& grid, const dim3& block, unsigned lds, hipStream_t s, Args... args) {
     const LaunchTiming t = g_launch_timing;
     g_launch_timing = LaunchTiming{};
-    hipExtLaunchKernelGGL(kernel, grid, block, lds, s, t.start, t.stop, 0, args...);
+    if (t.start || t.stop) hipExtLaunchKernelGGL(kernel, grid, block, lds, s, t.start, t.stop, 0, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
 }
 
 // passes.hip
@@ -120,6 +121,31 @@ void launch_combine(double2* x, const C<R>* Vb, long long ldv, int nvec, const d
 template <typename R>
 void launch_norm_partials(double* partial, const C<R>* v, long long n, long long rstride, int nrhs, int nblocks,
                           hipStream_t s);
+// Least-squares side of one GMRES restart cycle on the device, FP64, per
+// slot s of na right-hand sides (Sec. V: restarted GMRES): the rotated
+// Hessenberg matrix (column-major, column j at H + (s m + j)(m + 1)), the
+// Givens rotations of the columns so far, and the rotated ||r|| e_1.
+struct ArnoldiState {
+    double2* H;            // [na][m][m + 1]
+    double2* cs;           // [na][m]
+    double2* sn;           // [na][m]
+    double2* g;            // [na][m + 1]
+    const double2* slot;   // [na]: (||r||, target of |g_{j+1}| / ||r||)
+    int* status;           // [0] columns folded in, [1] every slot has met its
+                           // target, [2] a non-finite estimate was seen
+    int m;
+};
+// zero the status, g_0 = ||r||, ivn of the first basis vector = 1
+void launch_arnoldi_init(ArnoldiState st, double* ivn, long long ivn_ld, int na, hipStream_t s);
+// fold Hessenberg column j (h1 (+ h2 with a second pass) above the diagonal,
+// nrm below) into the rotations and the residual estimate; a no-op once
+// status[1] or status[2] is set
+void launch_givens(ArnoldiState st, const double2* h1, const double2* h2, const double* nrm, int j, int na,
+                   hipStream_t s);
+// y = R^-1 g over the first nvec columns, scaled by the basis vectors'
+// reciprocal norms (the coefficients of the stored vectors), y [na][nvec]
+void launch_backsolve(ArnoldiState st, const double* ivn, long long ivn_ld, double2* y, int nvec, int na,
+                      hipStream_t s);
 void launch_cast_down(float2* dst, const double2* src, const double* scale, long long n, int nrhs, hipStream_t s);
 void launch_cast_up(double2* dst, const float2* src, long long n, hipStream_t s);
 void launch_copy_c128(double2* dst, const double2* src, long long n, hipStream_t s);

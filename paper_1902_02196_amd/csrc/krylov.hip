@@ -3,6 +3,7 @@
 // in a fixed order (per-thread, wave, workgroup, then a separate pass over
 // workgroups), so results are bitwise reproducible.
 #include "kernels.hpp"
+#include "vie.h"
 
 namespace vie {
 
@@ -360,6 +361,140 @@ void launch_combine(double2* x, const C<R>* Vb, long long ldv, int nvec, const d
 }
 
 // dst (complex64) = src * scale[r]
+// ---- least-squares side of the restart cycle (FP64, one thread per slot) ----
+
+__global__ void k_arnoldi_init(ArnoldiState st, double* __restrict__ ivn, long long ivn_ld, int na) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 4) st.status[t] = 0;
+    if (t < na) {
+        st.g[(long long)t * (st.m + 1)] = make_double2(st.slot[t].x, 0.0);
+        ivn[t * ivn_ld] = 1.0;
+    }
+}
+
+void launch_arnoldi_init(ArnoldiState st, double* ivn, long long ivn_ld, int na, hipStream_t s) {
+    const int n = na > 4 ? na : 4;
+    hipLaunchKernelGGL(k_arnoldi_init, dim3((n + 255) / 256), dim3(256), 0, s, st, ivn, ivn_ld, na);
+    VIE_HIP(hipGetLastError());
+}
+
+// One workgroup: thread s < na takes slot s.  Column j of the Hessenberg
+// matrix is h_i (i <= j) from the Gram-Schmidt pass(es) and h_{j+1} = ||w||;
+// the earlier rotations are applied to it, a new rotation zeroes h_{j+1},
+// and g picks up the same rotation, so |g_{j+1}| is the residual norm of the
+// least-squares problem after j + 1 steps.
+__global__ void __launch_bounds__(256) k_givens(ArnoldiState st, const double2* __restrict__ h1,
+                                                const double2* __restrict__ h2, const double* __restrict__ nrm,
+                                                int j, int na) {
+    __shared__ int open, bad;
+    if (st.status[1] | st.status[2]) return;   // uniform: stopped at an earlier column
+    if (threadIdx.x == 0) {
+        open = 0;
+        bad = 0;
+    }
+    __syncthreads();
+    const int m = st.m, nvec = j + 1;
+    for (int s = threadIdx.x; s < na; s += blockDim.x) {
+        double2* Hc = st.H + ((long long)s * m + j) * (m + 1);
+        const double2* cs = st.cs + (long long)s * m;
+        const double2* sn = st.sn + (long long)s * m;
+        double2* g = st.g + (long long)s * (m + 1);
+        auto hin = [&](int i) {
+            double2 v = h1[(long long)s * nvec + i];
+            if (h2) v = cadd(v, h2[(long long)s * nvec + i]);
+            return v;
+        };
+        const double hn = nrm[s];
+        // earlier rotations: (a, b) <- (c a + s b, -conj(s) a + conj(c) b)
+        double2 a = hin(0);
+        for (int i = 0; i < j; ++i) {
+            const double2 b = hin(i + 1);
+            const double2 c = cs[i], z = sn[i];
+            Hc[i] = cadd(cmul(c, a), cmul(z, b));
+            a = csub(cmulc(c, b), cmulc(z, a));
+        }
+        const double den = sqrt(a.x * a.x + a.y * a.y + hn * hn);
+        double2 c, z;
+        if (den == 0.0) {
+            c = make_double2(1.0, 0.0);
+            z = make_double2(0.0, 0.0);
+        } else {
+            c = make_double2(a.x / den, -a.y / den);   // conj(a) / den
+            z = make_double2(hn / den, 0.0);
+        }
+        st.cs[(long long)s * m + j] = c;
+        st.sn[(long long)s * m + j] = z;
+        Hc[j] = make_double2(den, 0.0);
+        Hc[j + 1] = make_double2(0.0, 0.0);
+        const double2 gj = g[j];
+        g[j + 1] = make_double2(-(z.x * gj.x + z.y * gj.y), -(z.x * gj.y - z.y * gj.x));   // -conj(z) g_j
+        g[j] = cmul(c, gj);
+        const double est = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y) / st.slot[s].x;
+        if (!isfinite(est)) atomicOr(&bad, 1);
+        if (!(est <= st.slot[s].y) && hn > 0.0) atomicOr(&open, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st.status[0] = nvec;
+        if (bad) st.status[2] = 1;
+        if (!open) st.status[1] = 1;
+    }
+}
+
+void launch_givens(ArnoldiState st, const double2* h1, const double2* h2, const double* nrm, int j, int na,
+                   hipStream_t s) {
+    const int nt = na <= 64 ? 64 : 256;
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(nt), 0, s, st, h1, h2, nrm, j, na);
+    VIE_HIP(hipGetLastError());
+}
+
+// Back substitution R y = g for one slot per workgroup of one wave: lane l
+// keeps the right-hand side rows l, l + 64, ... (nvec <= 256); column i of R
+// updates the rows above i once y_i is known.
+constexpr int kBackRows = 4;   // rows per lane
+
+__global__ void __launch_bounds__(64) k_backsolve(ArnoldiState st, const double* __restrict__ ivn,
+                                                  long long ivn_ld, double2* __restrict__ y, int nvec) {
+    __shared__ double2 yl[64 * kBackRows];
+    const int s = blockIdx.x, lane = threadIdx.x, m = st.m;
+    const double2* H = st.H + (long long)s * m * (m + 1);
+    const double2* g = st.g + (long long)s * (m + 1);
+    double2 b[kBackRows];
+#pragma unroll
+    for (int q = 0; q < kBackRows; ++q) {
+        const int k = lane + 64 * q;
+        b[q] = k < nvec ? g[k] : make_double2(0.0, 0.0);
+    }
+    for (int i = nvec - 1; i >= 0; --i) {
+        const double2* Hi = H + (long long)i * (m + 1);
+        if (lane == (i & 63)) {
+            double2 bi = b[0];
+#pragma unroll
+            for (int q = 1; q < kBackRows; ++q)
+                if (q == (i >> 6)) bi = b[q];
+            const double2 d = Hi[i];
+            const double dd = d.x * d.x + d.y * d.y;
+            yl[i] = dd == 0.0 ? make_double2(0.0, 0.0) : cscale(cmulc(d, bi), 1.0 / dd);   // bi / d
+        }
+        __syncthreads();
+        const double2 yi = yl[i];
+#pragma unroll
+        for (int q = 0; q < kBackRows; ++q) {
+            const int k = lane + 64 * q;
+            if (k < i) b[q] = csub(b[q], cmul(Hi[k], yi));
+        }
+    }
+    __syncthreads();
+    for (int i = lane; i < nvec; i += 64) y[(long long)s * nvec + i] = cscale(yl[i], ivn[s * ivn_ld + i]);
+}
+
+void launch_backsolve(ArnoldiState st, const double* ivn, long long ivn_ld, double2* y, int nvec, int na,
+                      hipStream_t s) {
+    VIE_REQUIRE(nvec >= 1 && nvec <= 64 * kBackRows, VIE_EINVAL, "back substitution of 1..256 columns");
+    hipLaunchKernelGGL(k_backsolve, dim3(na), dim3(64), 0, s, st, ivn, ivn_ld, y, nvec);
+    VIE_HIP(hipGetLastError());
+}
+
 __global__ void k_cast_down(float2* __restrict__ dst, const double2* __restrict__ src, const double* __restrict__ sc,
                             long long n) {
     const int r = blockIdx.y;

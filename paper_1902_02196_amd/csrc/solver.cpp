@@ -8,21 +8,21 @@
 // iterative refinement, the complex64 Krylov solve of P^-1 A d = r / ||r||
 // followed by x += ||r|| d in FP64.  Orthogonalisation is classical
 // Gram-Schmidt (optionally twice) with FP64 inner products; the Hessenberg
-// matrix, Givens rotations and the small triangular solve are FP64 on the
-// host.  Basis vectors after the first are stored unnormalised, each with its
+// columns, Givens rotations, residual estimate and the small triangular
+// solve are FP64 on the device, so the host only reads a convergence flag
+// every few steps, and a run of steps can be replayed from a HIP graph.
+// Basis vectors after the first are stored unnormalised, each with its
 // reciprocal norm beside it: the normalisation is folded into the
 // Gram-Schmidt coefficients and the solution update instead of taking a pass
 // over the vector of its own.
 #include <chrono>
 #include <cmath>
-#include <complex>
+#include <cstdint>
 #include <vector>
 
 #include "ctx.hpp"
 
 namespace vie {
-
-using cd = std::complex<double>;
 
 // workgroups of the update and norm kernels: up to 1024, at least 1024
 // elements each, so that vectors of a few MB (PWC basis, small grids) still
@@ -54,7 +54,18 @@ static void norms(Ctx& c, const C<R>* v, long long n, int nrhs, double* partial,
 struct Layout {
     double2 *rhs, *r, *partial, *h1, *h2, *coef, *y;
     double *nrm, *npart, *inv, *bn, *rn, *ivn;
+    double2 *H, *cs, *sn, *g, *slot;   // least-squares state (ArnoldiState)
+    int* stat;
 };
+
+// Arnoldi steps between host checks of the convergence flag: several while
+// a step is short enough for the host round trip to show, one once a step
+// streams tens of MB
+static int auto_sync_steps(long long vec_bytes) {
+    if (vec_bytes <= (2LL << 20)) return 4;
+    if (vec_bytes <= (16LL << 20)) return 2;
+    return 1;
+}
 
 template <typename R>
 static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layout& L, vie_solve_stats* st,
@@ -111,98 +122,32 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
                 launch_scale_into<double>(reinterpret_cast<double2*>(Vb) + s * n, L.r + active[s] * n,
                                           L.rn + active[s], n, n, n, 1, c.stream);
         }
-        // reciprocal norms of the stored basis vectors: 1 for V_0, the rest
-        // written by the device after each step (and kept on the host for
-        // the solution update)
-        std::vector<double> ivn0((size_t)na * (m + 1), 0.0);
-        for (int s = 0; s < na; ++s) ivn0[(size_t)s * (m + 1)] = 1.0;
-        VIE_HIP(hipMemcpyAsync(L.ivn, ivn0.data(), ivn0.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
-        std::vector<std::vector<double>> ivh(na, std::vector<double>(m + 1, 0.0));
-        for (int s = 0; s < na; ++s) ivh[s][0] = 1.0;
-        // per-slot Hessenberg / Givens state
-        std::vector<std::vector<cd>> H(na, std::vector<cd>((size_t)(m + 1) * m));
-        std::vector<std::vector<cd>> cs(na, std::vector<cd>(m)), sn(na, std::vector<cd>(m)),
-            g(na, std::vector<cd>(m + 1));
-        std::vector<double> target(na);
-        std::vector<int> done(na, 0);
+        // least-squares state on the device: g_0 = ||r||, the target of each
+        // slot's residual estimate, reciprocal norm 1 for V_0
+        std::vector<double2> slot(na);
         for (int s = 0; s < na; ++s) {
-            g[s][0] = rnorm[active[s]];
             const double need = o.tol * bnorm[active[s]] / rnorm[active[s]];
-            target[s] = ir ? std::max(o.inner_tol, need) : need;
+            slot[s] = make_double2(rnorm[active[s]], ir ? std::max(o.inner_tol, need) : need);
         }
-        // The Arnoldi steps do not depend on the Givens rotations, so the
-        // host lags the device by one step: it enqueues step j, then waits
-        // for the Hessenberg column of step j - 1 (copied into page-locked
-        // memory behind it on the stream) and updates the rotations and the
-        // residual estimate.  A convergence found at step j - 1 leaves step j
-        // computed but unused.
-        int jdone = 0;
-        const size_t colsz = (size_t)na * (m + 1);
-        double* pin = static_cast<double*>(c.hpin.get(2 * (2 * colsz * sizeof(double2) + na * sizeof(double))));
-        auto slot_h1 = [&](int sl) { return reinterpret_cast<double2*>(pin) + (size_t)sl * 2 * colsz; };
-        auto slot_h2 = [&](int sl) { return slot_h1(sl) + colsz; };
-        auto slot_nrm = [&](int sl) { return pin + (size_t)2 * 2 * colsz * 2 + (size_t)sl * na; };
-        for (auto& e : c.col_ev)
-            if (!e) VIE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        // Givens update for column j; true when every slot has converged
-        auto process = [&](int j) -> int {
-            const int sl = j & 1;
-            VIE_HIP(hipEventSynchronize(c.col_ev[sl]));
-            const int nvec = j + 1;
-            const double2* h1 = slot_h1(sl);
-            const double2* h2 = slot_h2(sl);
-            const double* nrm = slot_nrm(sl);
-            bool all = true;
-            for (int s = 0; s < na; ++s) {
-                cd* Hc = &H[s][(size_t)j * (m + 1)];   // column j, rows 0..j+1
-                for (int i = 0; i <= j; ++i) {
-                    Hc[i] = cd(h1[(size_t)s * nvec + i].x, h1[(size_t)s * nvec + i].y);
-                    if (o.reorth) Hc[i] += cd(h2[(size_t)s * nvec + i].x, h2[(size_t)s * nvec + i].y);
-                }
-                Hc[j + 1] = nrm[s];
-                ivh[s][j + 1] = nrm[s] > 0 ? 1.0 / nrm[s] : 0.0;
-                for (int i = 0; i < j; ++i) {   // previous rotations
-                    const cd t = cs[s][i] * Hc[i] + sn[s][i] * Hc[i + 1];
-                    Hc[i + 1] = -std::conj(sn[s][i]) * Hc[i] + std::conj(cs[s][i]) * Hc[i + 1];
-                    Hc[i] = t;
-                }
-                const double den = std::sqrt(std::norm(Hc[j]) + std::norm(Hc[j + 1]));
-                if (den == 0.0) {
-                    cs[s][j] = 1.0;
-                    sn[s][j] = 0.0;
-                } else {
-                    cs[s][j] = std::conj(Hc[j]) / den;
-                    sn[s][j] = std::conj(Hc[j + 1]) / den;
-                }
-                Hc[j] = den;
-                Hc[j + 1] = 0.0;
-                g[s][j + 1] = -std::conj(sn[s][j]) * g[s][j];
-                g[s][j] = cs[s][j] * g[s][j];
-                const double est = std::abs(g[s][j + 1]) / rnorm[active[s]];
-                if (st) {
-                    st[active[s]].iterations += 1;
-                    if (ir) st[active[s]].matvecs_c64 += 1;
-                    else st[active[s]].matvecs_c128 += 1;
-                }
-                if (!std::isfinite(est)) return -1;
-                if (!(est <= target[s]) && nrm[s] > 0.0) all = false;
-            }
-            return all ? 1 : 0;
-        };
-        int launched = 0, stop = 0;
-        for (int j = 0; j < m && !stop; ++j) {
+        VIE_HIP(hipMemcpyAsync(L.slot, slot.data(), na * sizeof(double2), hipMemcpyHostToDevice, c.stream));
+        const ArnoldiState as{L.H, L.cs, L.sn, L.g, L.slot, L.stat, m};
+        const long long ivld = m + 1;
+        launch_arnoldi_init(as, L.ivn, ivld, na, c.stream);
+
+        // Arnoldi step j: w = P^-1 A u_j, Gram-Schmidt against u_0..u_j
+        // (w left unnormalised, its reciprocal norm in ivn[j + 1]), and the
+        // Givens update of column j on the device
+        auto step = [&](int j) {
             C<R>* vj = Vb + (long long)j * ldv;
             C<R>* w = Vb + (long long)(j + 1) * ldv;
             apply_op<R>(c, OP_PREC, na, vj, w, nullptr);
             const int nvec = j + 1;
-            // Gram-Schmidt, per pass: the dot kernel reads the j + 1 basis
-            // vectors and w (w once per group of 8 basis vectors); the
-            // update reads them again, reads and writes w, and leaves w
-            // unnormalised with its reciprocal norm in ivn[j + 1]
+            // per pass the dot kernel reads the j + 1 basis vectors and w (w
+            // once per group of 8 basis vectors); the update reads them
+            // again and reads and writes w
             const double vb = (double)na * n * sizeof(C<R>);
             const double dot_bytes = vb * (nvec + (nvec + 7) / 8);
             const double upd_bytes = vb * (nvec + 2);
-            const long long ivld = m + 1;
             for (int pass = 0; pass < (o.reorth ? 2 : 1); ++pass) {
                 double2* hp = pass ? L.h2 : L.h1;
                 const int jw = pass ? -1 : j;
@@ -218,48 +163,92 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
                         launch_reduce_norm(L.nrm, L.npart, nb, na, c.stream, L.ivn + (j + 1), ivld);
                 }
             }
-            // the column's slot was last read by the host for step j - 2,
-            // which process() finished before this step was enqueued
-            const int sl = j & 1;
-            VIE_HIP(hipMemcpyAsync(slot_h1(sl), L.h1, (size_t)na * nvec * sizeof(double2), hipMemcpyDeviceToHost,
-                                   c.stream));
-            if (o.reorth)
-                VIE_HIP(hipMemcpyAsync(slot_h2(sl), L.h2, (size_t)na * nvec * sizeof(double2),
-                                       hipMemcpyDeviceToHost, c.stream));
-            VIE_HIP(hipMemcpyAsync(slot_nrm(sl), L.nrm, na * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-            VIE_HIP(hipEventRecord(c.col_ev[sl], c.stream));
-            launched = j + 1;
-            if (j >= 1) {
-                const int rc = process(j - 1);
-                if (rc < 0) return VIE_ENAN;
-                jdone = j;
-                if (rc > 0) stop = 1;
+            launch_givens(as, L.h1, o.reorth ? L.h2 : nullptr, L.nrm, j, na, c.stream);
+        };
+
+        // steps [j0, j1): launched one by one, or replayed from a graph
+        // (the product's workspace is grown first, so that no step
+        // reallocates it under a capture)
+        const bool use_graph = o.graph && !c.prof.on;
+        if (use_graph) c.ws.get(apply_workspace_bytes(c, na, sizeof(C<R>)));
+        auto enqueue = [&](int j0, int j1) {
+            if (!use_graph) {
+                for (int j = j0; j < j1; ++j) step(j);
+                return;
             }
-        }
-        if (!stop && launched > jdone) {
-            const int rc = process(launched - 1);
-            if (rc < 0) return VIE_ENAN;
-            jdone = launched;
-        }
-        // x += V y with y from the triangular system (FP64)
-        std::vector<double2> yh((size_t)na * jdone);
-        for (int s = 0; s < na; ++s) {
-            std::vector<cd> yv(jdone);
-            for (int i = jdone - 1; i >= 0; --i) {
-                cd acc = g[s][i];
-                for (int k = i + 1; k < jdone; ++k) acc -= H[s][(size_t)k * (m + 1) + i] * yv[k];
-                const cd d = H[s][(size_t)i * (m + 1) + i];
-                yv[i] = (d == 0.0) ? cd(0) : acc / d;
+            const std::vector<long long> key{(long long)sizeof(R), na, m, o.reorth, j0, j1, n,
+                                             (long long)reinterpret_cast<uintptr_t>(Vb), ldv,
+                                             (long long)reinterpret_cast<uintptr_t>(L.rhs),
+                                             (long long)reinterpret_cast<uintptr_t>(c.ws.p)};
+            auto it = c.graphs.execs.find(key);
+            if (it == c.graphs.execs.end()) {
+                for (int j = j0; j < j1; ++j) step(j);
+                if (c.graphs.execs.size() >= GraphCache::kMax) c.graphs.clear();
+                c.graphs.execs.emplace(key, nullptr);
+                return;
             }
-            // V y = sum_i (y_i ivn_i) u_i over the stored vectors
-            for (int i = 0; i < jdone; ++i)
-                yh[(size_t)s * jdone + i] = make_double2(yv[i].real() * ivh[s][i], yv[i].imag() * ivh[s][i]);
+            if (!it->second) {
+                if (!c.graphs.cap) VIE_HIP(hipStreamCreateWithFlags(&c.graphs.cap, hipStreamNonBlocking));
+                const hipStream_t own = c.stream;
+                hipGraph_t gr = nullptr;
+                c.stream = c.graphs.cap;
+                VIE_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+                try {
+                    for (int j = j0; j < j1; ++j) step(j);
+                } catch (...) {
+                    (void)hipStreamEndCapture(c.stream, &gr);
+                    if (gr) (void)hipGraphDestroy(gr);
+                    c.stream = own;
+                    throw;
+                }
+                const hipError_t e = hipStreamEndCapture(c.stream, &gr);
+                c.stream = own;
+                VIE_HIP(e);
+                hipGraphExec_t ex = nullptr;
+                const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                VIE_HIP(ei);
+                it->second = ex;
+            }
+            VIE_HIP(hipGraphLaunch(it->second, c.stream));
+        };
+
+        // The host checks the device's convergence flag once per chunk of S
+        // steps and keeps one chunk queued ahead of the one it waits for, so
+        // the device does not idle on the round trip; a chunk queued behind
+        // the converged one runs with its Givens updates turned off.
+        const int S = o.sync_steps > 0 ? o.sync_steps : auto_sync_steps(na * n * (long long)sizeof(C<R>));
+        const int nch = (m + S - 1) / S;
+        int* pin = static_cast<int*>(c.hpin.get(2 * 4 * sizeof(int)));
+        for (auto& e : c.col_ev)
+            if (!e) VIE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        auto launch_chunk = [&](int k) {
+            enqueue(k * S, std::min(m, (k + 1) * S));
+            VIE_HIP(hipMemcpyAsync(pin + 4 * (k & 1), L.stat, 4 * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+            VIE_HIP(hipEventRecord(c.col_ev[k & 1], c.stream));
+        };
+        int launched = 0, checked = 0, jdone = 0;
+        bool stop = false;
+        launch_chunk(launched++);
+        while (checked < launched && !stop) {
+            if (launched < nch) launch_chunk(launched++);
+            VIE_HIP(hipEventSynchronize(c.col_ev[checked & 1]));
+            const int* sv = pin + 4 * (checked & 1);
+            ++checked;
+            jdone = sv[0];
+            if (sv[2]) return VIE_ENAN;
+            if (sv[1]) stop = true;
         }
-        VIE_HIP(hipMemcpyAsync(L.y, yh.data(), yh.size() * sizeof(double2), hipMemcpyHostToDevice, c.stream));
+
+        // x += V y with y = R^-1 g (FP64, on the device)
+        launch_backsolve(as, L.ivn, ivld, L.y, jdone, na, c.stream);
         for (int s = 0; s < na; ++s) {
             launch_combine<R>(x + (long long)active[s] * n, Vb + (long long)s * n, ldv, jdone,
                               L.y + (size_t)s * jdone, n, n, 1, c.stream);
             if (st) {
+                st[active[s]].iterations += jdone;
+                if (ir) st[active[s]].matvecs_c64 += jdone;
+                else st[active[s]].matvecs_c128 += jdone;
                 st[active[s]].restarts += 1;
                 if (ir) st[active[s]].refinements += 1;
             }
@@ -293,6 +282,9 @@ int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2*
     const size_t o_y = take((size_t)nrhs * m * 16);
     const size_t o_nrm = take(nrhs * 8), o_np = take((size_t)nrhs * nb * 8), o_inv = take(nrhs * 8);
     const size_t o_bn = take(nrhs * 8), o_rn = take(nrhs * 8);
+    const size_t o_H = take((size_t)nrhs * m * (m + 1) * 16), o_cs = take((size_t)nrhs * m * 16);
+    const size_t o_sn = take((size_t)nrhs * m * 16), o_g = take((size_t)nrhs * (m + 1) * 16);
+    const size_t o_slot = take((size_t)nrhs * 16), o_stat = take(4 * sizeof(int));
     char* base = static_cast<char*>(c.vecs.get(off));
     Layout L{};
     L.rhs = reinterpret_cast<double2*>(base + o_rhs);
@@ -308,6 +300,12 @@ int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2*
     L.inv = reinterpret_cast<double*>(base + o_inv);
     L.bn = reinterpret_cast<double*>(base + o_bn);
     L.rn = reinterpret_cast<double*>(base + o_rn);
+    L.H = reinterpret_cast<double2*>(base + o_H);
+    L.cs = reinterpret_cast<double2*>(base + o_cs);
+    L.sn = reinterpret_cast<double2*>(base + o_sn);
+    L.g = reinterpret_cast<double2*>(base + o_g);
+    L.slot = reinterpret_cast<double2*>(base + o_slot);
+    L.stat = reinterpret_cast<int*>(base + o_stat);
     if (st)
         for (int r = 0; r < nrhs; ++r) st[r] = vie_solve_stats{};
 

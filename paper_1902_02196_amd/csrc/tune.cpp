@@ -56,6 +56,7 @@ static Tune tune_t(Ctx& c, int nrhs, double* best_ms) {
                     cands.push_back(t);
                 }
         }
+    c.graphs.clear();   // captured products name the launch shapes
     Tune best;
     double bms = 1e30;
     const int reps = c.V * nrhs > 4000000 ? 2 : 5;

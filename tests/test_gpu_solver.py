@@ -10,7 +10,10 @@
 * a stop before the tolerance (VIE_ENOCONV with the last iterate, its true
   residual), resuming from it (use_x0), and the refinement-step bound;
 * PWC solves in complex64 + refinement on a grid with an odd number of
-  unknowns per vector (3 V, V odd).
+  unknowns per vector (3 V, V odd);
+* the Arnoldi steps replayed from HIP graphs, and other intervals between
+  host checks of the device-side convergence flag, give the same bits as
+  launching every kernel and checking after every step.
 """
 import functools
 import sys
@@ -103,6 +106,49 @@ def test_batched_pwl_solve_with_compaction(vie, torch, mode, tol, bound):
         assert err < bound
         pr = post.absorbed_power(xrefs[r], chi, D, F)
         assert abs(P[r] - pr) / abs(pr) < 10 * bound
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_graph_replay_and_sync_interval_keep_bits(vie, torch, mode):
+    """The batched solve of the compaction test with every kernel launched
+    one by one and the host checking convergence after every step, against
+    graph replay (a run of steps is captured the second time the solver
+    reaches it, replayed from the third) and other check intervals: the
+    device does the same arithmetic, so solutions and statistics are the
+    same bits, and every one matches dense LU.  The solves run back to back
+    with host copies and synchronisations in between, so each replay is
+    checked after the solver's own uncaptured work."""
+    N, D = (6, 5, 4), (0.005, 0.006, 0.005)
+    _say("graph replay mode %d" % mode)
+    T = _blocks(N, D)
+    e, s = vi.ellipsoid_phantom(N, D, 71)
+    tau, chi = physics.tau(e, s, F), physics.chi(e, s, F)
+    pos = np.array([[0.0, 0.0, 0.012], [0.02, 0.0, -0.004], [0.0, 0.06, 0.0]])
+    mom = np.array([[0.0, 0.0, 1.0], [0.0, 1.0, 0.0], [1.0, 0.0, 0.0]])
+    ets = list(incident.dipoles_tested(N, D, F, pos, mom, chi != 0, nq=6))
+    A = solve.dense_prec_matrix(T, tau, D)
+    xrefs = [np.linalg.solve(A, matvec.rhs_prec(et, tau, D, F).reshape(-1)).reshape(et.shape) for et in ets]
+    c = vie.Context(0)
+    c.set_grid(N, D, F)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    etd = _dev_batch(torch, ets)
+    tol = 1e-11 if mode == 0 else 1e-10
+    x0 = torch.empty_like(etd)
+    code, st0 = c.solve(etd, x0, mode=mode, tol=tol, restart=6, graph=0, sync_steps=1)
+    assert code == vie.VIE_OK
+    for r in range(3):
+        assert relerr(_host(x0, r), xrefs[r]) < (1e-8 if mode == 0 else 1e-7)
+    ref = x0.cpu()
+    runs = [(1, 0), (1, 0), (1, 0), (1, 3), (1, 3), (1, 3), (0, 4), (1, 100)]
+    for graph, sync in runs:
+        x = torch.empty_like(etd)
+        code, st = c.solve(etd, x, mode=mode, tol=tol, restart=6, graph=graph, sync_steps=sync)
+        torch.cuda.synchronize()
+        same = torch.equal(x.cpu(), ref)
+        _say("  graph %d sync %d: same bits %s, %s" % (graph, sync, same, [s_["iterations"] for s_ in st]))
+        assert code == vie.VIE_OK and same
+        for a, b in zip(st, st0):
+            assert {k: v for k, v in a.items() if k != "seconds"} == {k: v for k, v in b.items() if k != "seconds"}
 
 
 @functools.lru_cache(None)
