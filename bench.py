@@ -268,7 +268,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--reorth", type=int, default=0, help="second Gram-Schmidt pass (1) or not (0)")
     ap.add_argument("--restart", type=int, default=50)
-    ap.add_argument("--graph", type=int, default=1, help="replay the Arnoldi steps from HIP graphs (1) or not (0)")
+    ap.add_argument("--graph", type=int, default=0, help="replay the Arnoldi steps from HIP graphs (1) or not (0)")
     ap.add_argument("--sync-steps", type=int, default=0,
                     help="Arnoldi steps per host check of the convergence flag (0: automatic)")
     args = ap.parse_args()

@@ -137,11 +137,13 @@ struct ArnoldiState {
 };
 // zero the status, g_0 = ||r||, ivn of the first basis vector = 1
 void launch_arnoldi_init(ArnoldiState st, double* ivn, long long ivn_ld, int na, hipStream_t s);
+// sum the norm partials of the new vector w (npart [na][nblocks]) into
+// nrm[s] and its reciprocal ivn_next[s * ivn_ld] (0 for a zero vector), then
 // fold Hessenberg column j (h1 (+ h2 with a second pass) above the diagonal,
-// nrm below) into the rotations and the residual estimate; a no-op once
-// status[1] or status[2] is set
-void launch_givens(ArnoldiState st, const double2* h1, const double2* h2, const double* nrm, int j, int na,
-                   hipStream_t s);
+// ||w|| below) into the rotations and the residual estimate; the rotations
+// are left alone once status[1] or status[2] is set
+void launch_givens(ArnoldiState st, const double2* h1, const double2* h2, const double* npart, int nblocks,
+                   double* nrm, double* ivn_next, long long ivn_ld, int j, int na, hipStream_t s);
 // y = R^-1 g over the first nvec columns, scaled by the basis vectors'
 // reciprocal norms (the coefficients of the stored vectors), y [na][nvec]
 void launch_backsolve(ArnoldiState st, const double* ivn, long long ivn_ld, double2* y, int nvec, int na,

@@ -378,73 +378,101 @@ void launch_arnoldi_init(ArnoldiState st, double* ivn, long long ivn_ld, int na,
     VIE_HIP(hipGetLastError());
 }
 
-// One workgroup: thread s < na takes slot s.  Column j of the Hessenberg
-// matrix is h_i (i <= j) from the Gram-Schmidt pass(es) and h_{j+1} = ||w||;
-// the earlier rotations are applied to it, a new rotation zeroes h_{j+1},
-// and g picks up the same rotation, so |g_{j+1}| is the residual norm of the
-// least-squares problem after j + 1 steps.
-__global__ void __launch_bounds__(256) k_givens(ArnoldiState st, const double2* __restrict__ h1,
-                                                const double2* __restrict__ h2, const double* __restrict__ nrm,
-                                                int j, int na) {
+// One workgroup of kGivWaves waves; wave w takes slots w, w + kGivWaves, ...
+// For slot s it sums the norm partials of w into ||w|| (lane-strided, the
+// order of k_reduce_norm) and the reciprocal norm of the new basis vector,
+// stages column j of the Hessenberg matrix (h_i, i <= j, from the
+// Gram-Schmidt pass(es); h_{j+1} = ||w||) and the earlier rotations in LDS,
+// and lane 0 applies the rotations, forms the new one that zeroes h_{j+1}
+// and rotates g, so |g_{j+1}| is the least-squares residual after j + 1
+// steps.
+constexpr int kGivWaves = 4;
+constexpr int kGivRows = 201;   // restart <= 200
+
+__global__ void __launch_bounds__(64 * kGivWaves) k_givens(ArnoldiState st, const double2* __restrict__ h1,
+                                                           const double2* __restrict__ h2,
+                                                           const double* __restrict__ npart, int nblocks,
+                                                           double* __restrict__ nrm, double* __restrict__ ivn_next,
+                                                           long long ivn_ld, int j, int na) {
+    __shared__ double2 lh[kGivWaves][kGivRows], lc[kGivWaves][kGivRows], ls[kGivWaves][kGivRows];
+    __shared__ double lhn[kGivWaves];
     __shared__ int open, bad;
-    if (st.status[1] | st.status[2]) return;   // uniform: stopped at an earlier column
+    const bool stopped = st.status[1] | st.status[2];   // uniform: stopped at an earlier column
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, m = st.m, nvec = j + 1;
     if (threadIdx.x == 0) {
         open = 0;
         bad = 0;
     }
-    __syncthreads();
-    const int m = st.m, nvec = j + 1;
-    for (int s = threadIdx.x; s < na; s += blockDim.x) {
-        double2* Hc = st.H + ((long long)s * m + j) * (m + 1);
-        const double2* cs = st.cs + (long long)s * m;
-        const double2* sn = st.sn + (long long)s * m;
-        double2* g = st.g + (long long)s * (m + 1);
-        auto hin = [&](int i) {
-            double2 v = h1[(long long)s * nvec + i];
-            if (h2) v = cadd(v, h2[(long long)s * nvec + i]);
-            return v;
-        };
-        const double hn = nrm[s];
-        // earlier rotations: (a, b) <- (c a + s b, -conj(s) a + conj(c) b)
-        double2 a = hin(0);
-        for (int i = 0; i < j; ++i) {
-            const double2 b = hin(i + 1);
-            const double2 c = cs[i], z = sn[i];
-            Hc[i] = cadd(cmul(c, a), cmul(z, b));
-            a = csub(cmulc(c, b), cmulc(z, a));
+    for (int base = 0; base < na; base += kGivWaves) {   // the same trip count in every wave
+        const int s = base + wv;
+        if (s < na) {
+            double q = 0;
+            for (int b = lane; b < nblocks; b += 64) q += npart[(long long)s * nblocks + b];
+            q = wave_sum(q);
+            if (lane == 0) {
+                const double nv = sqrt(q);
+                nrm[s] = nv;
+                ivn_next[s * ivn_ld] = nv > 0 ? 1.0 / nv : 0.0;
+                lhn[wv] = nv;
+            }
+            if (!stopped)
+                for (int i = lane; i <= j; i += 64) {
+                    double2 v = h1[(long long)s * nvec + i];
+                    if (h2) v = cadd(v, h2[(long long)s * nvec + i]);
+                    lh[wv][i] = v;
+                    if (i < j) {
+                        lc[wv][i] = st.cs[(long long)s * m + i];
+                        ls[wv][i] = st.sn[(long long)s * m + i];
+                    }
+                }
         }
-        const double den = sqrt(a.x * a.x + a.y * a.y + hn * hn);
-        double2 c, z;
-        if (den == 0.0) {
-            c = make_double2(1.0, 0.0);
-            z = make_double2(0.0, 0.0);
-        } else {
-            c = make_double2(a.x / den, -a.y / den);   // conj(a) / den
-            z = make_double2(hn / den, 0.0);
+        __syncthreads();
+        if (!stopped && s < na && lane == 0) {
+            const double hn = lhn[wv];
+            double2* Hc = st.H + ((long long)s * m + j) * (m + 1);
+            double2* g = st.g + (long long)s * (m + 1);
+            // earlier rotations: (a, b) <- (c a + z b, conj(c) b - conj(z) a)
+            double2 a = lh[wv][0];
+            for (int i = 0; i < j; ++i) {
+                const double2 b = lh[wv][i + 1], c = lc[wv][i], z = ls[wv][i];
+                Hc[i] = cadd(cmul(c, a), cmul(z, b));
+                a = csub(cmulc(c, b), cmulc(z, a));
+            }
+            const double den = sqrt(a.x * a.x + a.y * a.y + hn * hn);
+            double2 c, z;
+            if (den == 0.0) {
+                c = make_double2(1.0, 0.0);
+                z = make_double2(0.0, 0.0);
+            } else {
+                c = make_double2(a.x / den, -a.y / den);   // conj(a) / den
+                z = make_double2(hn / den, 0.0);
+            }
+            st.cs[(long long)s * m + j] = c;
+            st.sn[(long long)s * m + j] = z;
+            Hc[j] = make_double2(den, 0.0);
+            Hc[j + 1] = make_double2(0.0, 0.0);
+            const double2 gj = g[j];
+            const double2 gn = make_double2(-(z.x * gj.x + z.y * gj.y), -(z.x * gj.y - z.y * gj.x));   // -conj(z) g_j
+            g[j + 1] = gn;
+            g[j] = cmul(c, gj);
+            const double est = sqrt(gn.x * gn.x + gn.y * gn.y) / st.slot[s].x;
+            if (!isfinite(est)) atomicOr(&bad, 1);
+            if (!(est <= st.slot[s].y) && hn > 0.0) atomicOr(&open, 1);
         }
-        st.cs[(long long)s * m + j] = c;
-        st.sn[(long long)s * m + j] = z;
-        Hc[j] = make_double2(den, 0.0);
-        Hc[j + 1] = make_double2(0.0, 0.0);
-        const double2 gj = g[j];
-        g[j + 1] = make_double2(-(z.x * gj.x + z.y * gj.y), -(z.x * gj.y - z.y * gj.x));   // -conj(z) g_j
-        g[j] = cmul(c, gj);
-        const double est = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y) / st.slot[s].x;
-        if (!isfinite(est)) atomicOr(&bad, 1);
-        if (!(est <= st.slot[s].y) && hn > 0.0) atomicOr(&open, 1);
+        __syncthreads();   // the LDS rows are reused by the next round
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && !stopped) {
         st.status[0] = nvec;
         if (bad) st.status[2] = 1;
         if (!open) st.status[1] = 1;
     }
 }
 
-void launch_givens(ArnoldiState st, const double2* h1, const double2* h2, const double* nrm, int j, int na,
-                   hipStream_t s) {
-    const int nt = na <= 64 ? 64 : 256;
-    hipLaunchKernelGGL(k_givens, dim3(1), dim3(nt), 0, s, st, h1, h2, nrm, j, na);
+void launch_givens(ArnoldiState st, const double2* h1, const double2* h2, const double* npart, int nblocks,
+                   double* nrm, double* ivn_next, long long ivn_ld, int j, int na, hipStream_t s) {
+    VIE_REQUIRE(j >= 0 && j + 1 < kGivRows && j < st.m, VIE_EINVAL, "Givens column beyond restart 200");
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(64 * kGivWaves), 0, s, st, h1, h2, npart, nblocks, nrm, ivn_next,
+                       ivn_ld, j, na);
     VIE_HIP(hipGetLastError());
 }
 

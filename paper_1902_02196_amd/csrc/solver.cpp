@@ -24,18 +24,19 @@
 
 namespace vie {
 
-// workgroups of the update and norm kernels: up to 1024, at least 1024
-// elements each, so that vectors of a few MB (PWC basis, small grids) still
-// spread over all CUs
+// workgroups of the update and norm kernels: up to 1024, at least 512
+// elements (one 16-byte unit per thread in complex64) each, so that small
+// vectors spread over as many CUs as they can: their kernels are bound by
+// load latency, not by bandwidth
 static int blocks_for(long long n) {
-    long long b = (n + 1024 - 1) / 1024;
+    long long b = (n + 512 - 1) / 512;
     return (int)std::max(1LL, std::min(1024LL, b));
 }
 
 // workgroups per group of basis vectors of the dot kernel (whose groups run
-// side by side): up to 1024, at least 2048 elements each
+// side by side): up to 1024, at least 512 elements each
 static int dot_blocks_for(long long n) {
-    long long b = (n + 2048 - 1) / 2048;
+    long long b = (n + 512 - 1) / 512;
     return (int)std::max(1LL, std::min(1024LL, b));
 }
 
@@ -159,11 +160,11 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
                 {
                     ProfScope ps(c.prof, c.stream, VIE_K_GS_UPDATE, upd_bytes);
                     launch_update<R>(w, Vb, ldv, nvec, L.coef, n, n, n, L.npart, L.ivn, ivld, jw, na, nb, c.stream);
-                    if (pass == (o.reorth ? 1 : 0))
-                        launch_reduce_norm(L.nrm, L.npart, nb, na, c.stream, L.ivn + (j + 1), ivld);
                 }
             }
-            launch_givens(as, L.h1, o.reorth ? L.h2 : nullptr, L.nrm, j, na, c.stream);
+            // ||w|| from the last pass's partials, then column j into the rotations
+            launch_givens(as, L.h1, o.reorth ? L.h2 : nullptr, L.npart, nb, L.nrm, L.ivn + (j + 1), ivld, j, na,
+                          c.stream);
         };
 
         // steps [j0, j1): launched one by one, or replayed from a graph

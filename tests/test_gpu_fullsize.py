@@ -211,10 +211,10 @@ def test_sphere16_solution_matches_oracle(vie, torch):
         code, st = c.solve(et, x, mode=mode, tol=1e-10, graph=0, sync_steps=1)
         assert code == vie.VIE_OK and st[0]["converged"]
         # graph replay (captured on the second pass over a run of steps) and
-        # the default check interval: the same bits
+        # the automatic check interval: the same bits
         for rep in range(3):
             xg = torch.empty_like(et)
-            code_g, st_g = c.solve(et, xg, mode=mode, tol=1e-10)
+            code_g, st_g = c.solve(et, xg, mode=mode, tol=1e-10, graph=1)
             assert code_g == vie.VIE_OK and torch.equal(xg.cpu(), x.cpu()), rep
             assert st_g[0]["iterations"] == st[0]["iterations"]
         err = relerr(vec_from_lib(x[0].cpu().numpy()), xref)
