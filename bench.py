@@ -271,6 +271,9 @@ def main():
     ap.add_argument("--graph", type=int, default=0, help="replay the Arnoldi steps from HIP graphs (1) or not (0)")
     ap.add_argument("--sync-steps", type=int, default=0,
                     help="Arnoldi steps per host check of the convergence flag (0: automatic)")
+    ap.add_argument("--products", type=int, default=0,
+                    help="counter runs: after set-up and autotuning, time this many complex64 operator products "
+                         "of one batch, run the 256 MiB calibration copy, print one JSON line and stop (no solves)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -326,6 +329,36 @@ def main():
         ctx.incident_dipoles(et, pos, mom)
         excitation = "%d z-directed Hertzian dipoles on a %.0f cm cylinder, one batched solve" % (nrhs, W["cyl"] * 100)
     group = W.get("group", nrhs)
+
+    if args.products > 0:
+        # the operator product alone at the batch the solves use, each pass
+        # timed by the events its launch stamps, then the calibration copy
+        xv = torch.randn(ctx.vec_shape(group), dtype=torch.complex64, device=dev)
+        yv = torch.empty_like(xv)
+        ctx.apply(xv, yv, op=vie.OP_PREC)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(args.products):
+            ctx.apply(xv, yv, op=vie.OP_PREC)
+        torch.cuda.synchronize()
+        t_mv = (time.perf_counter() - t0) / args.products
+        mvprof = {k: v for k, v in ctx.profile_read().items() if v[1] > 0 and v[0] > 0}
+        ctx.profile(False)
+        cbuf = torch.empty(16 * 1024 * 1024, dtype=torch.complex128, device=dev)
+        cdst = torch.empty_like(cbuf)
+        ctx.copy(cbuf, cdst)
+        torch.cuda.synchronize()
+        passes = {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1], "MB_per_launch": round(v[2] / v[1] / 1e6, 2),
+                      "GBps_algorithmic": round(v[2] / (v[0] * 1e-3) / 1e9, 1)} for k, v in mvprof.items()}
+        dev_ms = sum(v[0] for v in mvprof.values()) / args.products
+        by = sum(v[2] for v in mvprof.values()) / args.products
+        print(json.dumps({"workload": args.workload, "products": args.products, "nrhs": group, "fft_size": ctx.fft_size,
+                          "autotune_c64": tune64, "product_ms": round(t_mv * 1e3, 4),
+                          "product_device_ms": round(dev_ms, 4), "product_MB_algorithmic": round(by / 1e6, 1),
+                          "product_GBps_algorithmic": round(by / (dev_ms * 1e-3) / 1e9, 1), "passes": passes,
+                          "source_hash": kernel_source_hash()}), flush=True)
+        return
 
     def solve_all(opts):
         """Solve every right-hand side, `group` at a time; returns the status

@@ -134,6 +134,17 @@ constexpr __host__ __device__ __forceinline__ int curl_unique_sign(int a, int b)
     return p == q ? 0 : levi(p, 3 - p - q, q) * unique_sign(a, b);
 }
 
+// The dispatcher deals workgroups to the 8 XCDs round-robin by linear
+// index.  This maps a linear hardware index h < n to a logical index such
+// that each XCD receives one contiguous range of logical indices, taken in
+// order: workgroups with neighbouring logical indices run on the same XCD at
+// about the same time and share its L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ unsigned xcd_contiguous(unsigned h, unsigned n) {
+    const unsigned q = n / kXcds, r = n % kXcds, x = h % kXcds, k = h / kXcds;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------

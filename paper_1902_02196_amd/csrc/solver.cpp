@@ -24,21 +24,21 @@
 
 namespace vie {
 
-// workgroups of the update and norm kernels: up to 1024, at least 512
-// elements (one 16-byte unit per thread in complex64) each, so that small
-// vectors spread over as many CUs as they can: their kernels are bound by
-// load latency, not by bandwidth
-static int blocks_for(long long n) {
-    long long b = (n + 512 - 1) / 512;
+// Workgroup counts of the Gram-Schmidt kernels: per_wg elements per
+// workgroup, up to 1024 workgroups, and for short vectors at least
+// min(n / 512, 256) of them (one 16-byte unit per thread in complex64), so
+// that a vector of a few hundred kB still spreads over the CUs: there the
+// kernels are bound by load latency, not bandwidth.
+static int gs_blocks(long long n, long long per_wg) {
+    const long long floor_ = std::min((n + 511) / 512, 256LL);
+    const long long b = std::max((n + per_wg - 1) / per_wg, floor_);
     return (int)std::max(1LL, std::min(1024LL, b));
 }
-
-// workgroups per group of basis vectors of the dot kernel (whose groups run
-// side by side): up to 1024, at least 512 elements each
-static int dot_blocks_for(long long n) {
-    long long b = (n + 512 - 1) / 512;
-    return (int)std::max(1LL, std::min(1024LL, b));
-}
+// update and norm kernels: 1024 elements per workgroup
+static int blocks_for(long long n) { return gs_blocks(n, 1024); }
+// dot kernel, per group of 8 basis vectors (the groups run side by side):
+// 2048 elements per workgroup
+static int dot_blocks_for(long long n) { return gs_blocks(n, 2048); }
 
 // FP64 norms of nrhs vectors of length n (device result in out_dev, host copy in out)
 template <typename R>

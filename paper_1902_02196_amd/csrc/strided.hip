@@ -6,12 +6,20 @@
 #include "fft_ct.hpp"
 #include "kernels.hpp"
 #include "passes.hpp"
+#include "vie.h"
 
 namespace vie {
 
 // Compile-time-length strided pass: the tile's T pencils are held as T rows
 // of N in LDS (one buffer, padded) and transformed in place by the unrolled
 // Stockham passes; loads and stores run along t, T consecutive elements.
+//
+// Workgroup order: the (tile, row, component array) of a workgroup is taken
+// from its logical index (xcd_contiguous), tiles fastest, so that
+// neighbouring tiles run on one XCD together: with tiles of 8 complex64 (64
+// bytes, the long lengths, where 16 would leave one workgroup per CU) the
+// two tiles of each 128-byte line are then read through the same L2 instead
+// of twice, once per XCD.
 template <typename R, bool FWD, bool EPI, int N, int T>
 __global__ void __launch_bounds__(256) k_strided_ct(const C<R>* in, C<R>* out, StridedPass p,
                                                     const C<R>* __restrict__ tw, Epilogue<R> ep) {
@@ -20,9 +28,12 @@ __global__ void __launch_bounds__(256) k_strided_ct(const C<R>* in, C<R>* out, S
     C<R>* twl = reinterpret_cast<C<R>*>(smem_raw);
     C<R>* buf = twl + N;
     const int tid = threadIdx.x;
-    const int t0 = blockIdx.x * T;
-    const long long o2 = blockIdx.y;
-    const int o1 = blockIdx.z, rr = o1 / p.nc, cc = o1 - p.nc * rr;
+    const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+    const unsigned lid = xcd_contiguous(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gz);
+    const unsigned bx = lid % gx, by = (lid / gx) % gy, bz = lid / gx / gy;
+    const int t0 = bx * T;
+    const long long o2 = by;
+    const int o1 = bz, rr = o1 / p.nc, cc = o1 - p.nc * rr;
     const int tw_n = min(T, p.n_inner - t0);
     const C<R>* src = in + rr * p.in_s1 + cc * p.in_sc + o2 * p.in_s2 + t0;
     for (int m = tid; m < N; m += NT) twl[m] = tw[m];
@@ -81,6 +92,8 @@ static void launch_strided_ct_nt(const C<R>* in, C<R>* out, const StridedPass& p
         (void)hipGetLastError();
     });
     dim3 grid((p.n_inner + T - 1) / T, (unsigned)n_o2, (unsigned)n_o1);
+    VIE_REQUIRE((unsigned long long)grid.x * grid.y * grid.z < (1ULL << 32), VIE_EINVAL,
+                "strided pass grid above 2^32 workgroups");
     timed_launch(k_strided_ct<R, FWD, EPI, N, T>, grid, dim3(256), (unsigned)lds, s, in, out, p, tw, ep);
     VIE_HIP(hipGetLastError());
 }
