@@ -268,9 +268,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--reorth", type=int, default=0, help="second Gram-Schmidt pass (1) or not (0)")
     ap.add_argument("--restart", type=int, default=50)
-    ap.add_argument("--graph", type=int, default=0, help="replay the Arnoldi steps from HIP graphs (1) or not (0)")
+    ap.add_argument("--graph", type=int, default=-1,
+                    help="replay the Arnoldi steps from HIP graphs (1), not (0), or when the vectors are small (-1)")
     ap.add_argument("--sync-steps", type=int, default=0,
                     help="Arnoldi steps per host check of the convergence flag (0: automatic)")
+    ap.add_argument("--profile-every", type=int, default=PROFILE_EVERY,
+                    help="time one launch in this many of each kernel class by its own events inside the timed "
+                         "solves (0: none there; the classes are then timed in one more solve after the timed "
+                         "region); graph replay implies 0, since a replayed launch carries no events")
     ap.add_argument("--products", type=int, default=0,
                     help="counter runs: after set-up and autotuning, time this many complex64 operator products "
                          "of one batch, run the 256 MiB calibration copy, print one JSON line and stop (no solves)")
@@ -387,10 +392,12 @@ def main():
         code, st = solve_all(opts_ir)
         log("warmup %d: %s" % (i, st[0]))
 
-    # timed region: K full solves; one launch in PROFILE_EVERY of each kernel
+    every = 0 if args.graph > 0 else args.profile_every
+    # timed region: K full solves; one launch in `every` of each kernel
     # class is bracketed by HIP events (average launch durations)
     torch.cuda.synchronize()
-    ctx.profile(True, every=PROFILE_EVERY)
+    if every:
+        ctx.profile(True, every=every)
     t0 = time.perf_counter()
     stats = []
     for i in range(args.steps):
@@ -399,8 +406,17 @@ def main():
         log("step %d: %s" % (i, stats[-1]))
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
-    prof = ctx.profile_read()
-    ctx.profile(False)
+    if every:
+        prof = ctx.profile_read()
+        ctx.profile(False)
+    else:
+        # the kernel classes timed in one more solve, launched one by one
+        ctx.profile(True, every=PROFILE_EVERY)
+        solve_all(vie.default_opts(mode=vie.SOLVE_FP32_IR, tol=1e-6, restart=args.restart, inner_tol=1e-5,
+                                   reorth=args.reorth, graph=0, sync_steps=args.sync_steps))
+        torch.cuda.synchronize()
+        prof = ctx.profile_read()
+        ctx.profile(False)
     assert code == vie.VIE_OK, "IR solve did not converge: %s" % stats[-1]
     n64 = min(nrhs, W.get("fp64_rhs", nrhs))
     x_ir = x[:n64].clone()
@@ -414,7 +430,8 @@ def main():
     code64, st64 = ctx.solve(et64, x64, opts_64)
     log("fp64 warmup: %s" % st64[0])
     torch.cuda.synchronize()
-    ctx.profile(True, every=PROFILE_EVERY)
+    if every:
+        ctx.profile(True, every=every)
     t0 = time.perf_counter()
     for i in range(args.steps):
         code64, st64 = ctx.solve(et64, x64, opts_64)
@@ -480,7 +497,8 @@ def main():
     hbm_achieved = (by / nl) / avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": dom,
-                "launches_timed": nl, "avg_launch_us": round(avg_s * 1e6, 2), "bytes_per_launch": by / nl}
+                "launches_timed": nl, "avg_launch_us": round(avg_s * 1e6, 2), "bytes_per_launch": by / nl,
+                "timed_in": "the timed solves" if every else "one more solve after the timed region"}
     if dom == "block":
         fl = block_flops(ctx.fft_size, group, nc)
         achieved = fl / avg_s / 1e12
@@ -533,6 +551,7 @@ def main():
         "matvec_c64_GBps_algorithmic": round(mv_bytes / (mv_dev_ms * 1e-3) / 1e9, 1),
         "setup_s": round(t_grid, 3),
         "autotune": {"c64": tune64[0], "c128": tune128[0], "seconds": round(t_tune, 2)},
+        "solver": {"graph": args.graph, "sync_steps": args.sync_steps, "profile_every": every},
         "kernel_source_hash": kernel_source_hash(),
         "kernels": kernels,
         "roofline": roofline,

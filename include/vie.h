@@ -84,8 +84,9 @@ typedef struct {
     int graph;           /* 1: replay the Arnoldi steps from HIP graphs (a
                             run of steps is captured the second time the
                             solver reaches it with the same shapes and
-                            buffers), 0 (default): launch every kernel; the
-                            results are the same bits either way              */
+                            buffers), 0: launch every kernel, -1 (default):
+                            replay when a batch of vectors is at most 2 MB;
+                            the results are the same bits either way          */
     int sync_steps;      /* Arnoldi steps per host check of the device-side
                             convergence flag (the Givens rotations and the
                             residual estimate run on the device); 0: chosen

@@ -380,7 +380,7 @@ void vie_default_opts(vie_solve_opts* o) {
     o->max_refine = 400;
     o->reorth = 0;
     o->use_x0 = 0;
-    o->graph = 0;
+    o->graph = -1;
     o->sync_steps = 0;
 }
 

@@ -62,6 +62,11 @@ struct Layout {
 // Arnoldi steps between host checks of the convergence flag: several while
 // a step is short enough for the host round trip to show, one once a step
 // streams tens of MB
+// graph replay by default up to this many bytes per batch of vectors: there
+// the launches of a step are a visible part of it (16^3 sphere: +2.7%
+// solves/s replayed), above it replay measured slower (64^3: -1.9%)
+constexpr long long kGraphAutoBytes = 2LL << 20;
+
 static int auto_sync_steps(long long vec_bytes) {
     if (vec_bytes <= (2LL << 20)) return 4;
     if (vec_bytes <= (16LL << 20)) return 2;
@@ -170,7 +175,8 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
         // steps [j0, j1): launched one by one, or replayed from a graph
         // (the product's workspace is grown first, so that no step
         // reallocates it under a capture)
-        const bool use_graph = o.graph && !c.prof.on;
+        const long long vec_bytes = na * n * (long long)sizeof(C<R>);
+        const bool use_graph = (o.graph > 0 || (o.graph < 0 && vec_bytes <= kGraphAutoBytes)) && !c.prof.on;
         if (use_graph) c.ws.get(apply_workspace_bytes(c, na, sizeof(C<R>)));
         auto enqueue = [&](int j0, int j1) {
             if (!use_graph) {
@@ -218,7 +224,7 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
         // steps and keeps one chunk queued ahead of the one it waits for, so
         // the device does not idle on the round trip; a chunk queued behind
         // the converged one runs with its Givens updates turned off.
-        const int S = o.sync_steps > 0 ? o.sync_steps : auto_sync_steps(na * n * (long long)sizeof(C<R>));
+        const int S = o.sync_steps > 0 ? o.sync_steps : auto_sync_steps(vec_bytes);
         const int nch = (m + S - 1) / S;
         int* pin = static_cast<int*>(c.hpin.get(2 * 4 * sizeof(int)));
         for (auto& e : c.col_ev)

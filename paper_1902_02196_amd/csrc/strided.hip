@@ -102,6 +102,10 @@ template <typename R, bool FWD, bool EPI, int N>
 static void launch_strided_ct_n(const C<R>* in, C<R>* out, const StridedPass& p, long long n_o2, long long n_o1,
                                 const C<R>* tw, const Epilogue<R>& ep, hipStream_t s) {
     if constexpr (N >= 512) {
+        if (p.tile == 4) {
+            launch_strided_ct_nt<R, FWD, EPI, N, 4>(in, out, p, n_o2, n_o1, tw, ep, s);
+            return;
+        }
         if (p.tile == 8) {
             launch_strided_ct_nt<R, FWD, EPI, N, 8>(in, out, p, n_o2, n_o1, tw, ep, s);
             return;
@@ -111,12 +115,12 @@ static void launch_strided_ct_n(const C<R>* in, C<R>* out, const StridedPass& p,
     else launch_strided_ct_nt<R, FWD, EPI, N, 32>(in, out, p, n_o2, n_o1, tw, ep, s);
 }
 
-// compiled strided lengths (tiles of 16 or 32 pencils; also 8 from 512 up,
-// where a larger tile would hold one workgroup per CU)
+// compiled strided lengths (tiles of 16 or 32 pencils; also 8 and 4 from 512
+// up, where a larger tile would hold one workgroup per CU)
 #define VIE_STRIDED_LENGTHS(X) X(8) X(16) X(32) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512) X(768)
 
 bool strided_ct_fits(int es, int n, int tile) {
-    if (tile != 16 && tile != 32 && !(tile == 8 && n >= 512)) return false;
+    if (tile != 16 && tile != 32 && !((tile == 8 || tile == 4) && n >= 512)) return false;
     switch (n) {
 #define CASE(n_) case n_:
         VIE_STRIDED_LENGTHS(CASE)

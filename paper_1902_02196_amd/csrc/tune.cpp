@@ -4,27 +4,48 @@
 // the PWC basis, only the strided passes' tiles); the
 // staged x-pass variant adds the terms of the block product in another order
 // than the other two, so results agree to rounding.
+#include <algorithm>
 #include <vector>
 
 #include "ctx.hpp"
 
 namespace vie {
 
+// Milliseconds per product of the installed shape: one warm-up product,
+// one timed product to size the sample, then the best of up to three
+// trials of enough products for about 3 ms each (a single trial of two
+// products once a product takes 2 ms or more), so that products of a few
+// tens of microseconds are not ranked by timer noise.
 template <typename R>
-static double time_apply(Ctx& c, int nrhs, const C<R>* x, C<R>* y, int reps) {
+static double time_apply(Ctx& c, int nrhs, const C<R>* x, C<R>* y) {
     hipEvent_t a, b;
     VIE_HIP(hipEventCreate(&a));
     VIE_HIP(hipEventCreate(&b));
-    apply_op<R>(c, OP_N, nrhs, x, y, nullptr);   // warm up this shape
-    VIE_HIP(hipEventRecord(a, c.stream));
-    for (int i = 0; i < reps; ++i) apply_op<R>(c, OP_N, nrhs, x, y, nullptr);
-    VIE_HIP(hipEventRecord(b, c.stream));
-    VIE_HIP(hipEventSynchronize(b));
-    float ms = 0;
-    VIE_HIP(hipEventElapsedTime(&ms, a, b));
+    auto timed = [&](int reps) {
+        VIE_HIP(hipEventRecord(a, c.stream));
+        for (int i = 0; i < reps; ++i) apply_op<R>(c, OP_N, nrhs, x, y, nullptr);
+        VIE_HIP(hipEventRecord(b, c.stream));
+        VIE_HIP(hipEventSynchronize(b));
+        float ms = 0;
+        VIE_HIP(hipEventElapsedTime(&ms, a, b));
+        return (double)ms / reps;
+    };
+    double best = 0;
+    try {
+        apply_op<R>(c, OP_N, nrhs, x, y, nullptr);   // warm up this shape
+        const double t1 = timed(1);
+        const bool shortp = t1 < 2.0;
+        const int reps = shortp ? std::max(2, std::min(64, (int)(3.0 / std::max(t1, 1e-3)))) : 2;
+        best = timed(reps);
+        for (int trial = 1; shortp && trial < 3; ++trial) best = std::min(best, timed(reps));
+    } catch (...) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        throw;
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    return ms / reps;
+    return best;
 }
 
 template <typename R>
@@ -59,7 +80,6 @@ static Tune tune_t(Ctx& c, int nrhs, double* best_ms) {
     c.graphs.clear();   // captured products name the launch shapes
     Tune best;
     double bms = 1e30;
-    const int reps = c.V * nrhs > 4000000 ? 2 : 5;
     // candidates are installed one by one while they are timed; a failure
     // puts back what was installed before
     const auto key = std::make_pair(key0, nrhs);
@@ -69,7 +89,7 @@ static Tune tune_t(Ctx& c, int nrhs, double* best_ms) {
     try {
         for (const Tune& t : cands) {
             c.tune[{key0, nrhs}] = t;
-            const double ms = time_apply<R>(c, nrhs, x, y, reps);
+            const double ms = time_apply<R>(c, nrhs, x, y);
             if (ms < bms) {
                 bms = ms;
                 best = t;

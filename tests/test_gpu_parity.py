@@ -332,6 +332,41 @@ def test_every_launch_shape_matches_oracle(vie, torch, N):
     assert ran >= 8
 
 
+@pytest.mark.parametrize("N", [(4, 4, 384), (4, 256, 4)])
+def test_long_strided_tiles_match_oracle(vie, torch, N):
+    """Strided passes of length 768 (z) and 512 (y), where tiles of 4 and 8
+    pencils (32 and 64 bytes in complex64, less than a cache line) are
+    compiled beside 16 and 32: every tile, installed explicitly, gives the
+    oracle's FFT product in both precisions."""
+    D = (0.005, 0.004, 0.006)
+    _say("long strided tiles %s" % (N,))
+    c = _ctx(vie, torch, N, D)
+    Toct = toeplitz.toeplitz_octant(N, D, K)
+    c.set_toeplitz(unique_from_octant(Toct))
+    T = matvec.full_from_octant(Toct)
+    xs = [vi.complex_normal(60 + r, (12,) + N) for r in range(2)]
+    Ch = matvec.circulant_spectrum(T, tuple(2 * n for n in N))
+    ref = [matvec.fft_N(Ch, x) for x in xs]
+    x = torch.from_numpy(np.stack([vec_to_lib(v) for v in xs]))
+    ran = 0
+    for dtype, prec, tol in ((torch.complex64, vie.C64, 1e-5), (torch.complex128, vie.C128, 1e-11)):
+        xd = x.to("cuda", dtype)
+        for tz in (4, 8, 16, 32):
+            for ty in (4, 8, 16, 32):
+                try:
+                    c.set_tuning(dict(variant=1, sib_blocks=1, tile_z=tz, tile_y=ty), prec, 2)
+                except vie.VieError:
+                    continue   # tile not available for this length or precision
+                y = torch.empty_like(xd)
+                c.apply(xd, y, op=vie.OP_N)
+                for r in range(2):
+                    err = relerr(_from_dev(y[r:r + 1]), ref[r])
+                    assert err < tol, (dtype, tz, ty, r, err)
+                ran += 1
+    _say("  %d tile pairs checked" % ran)
+    assert ran >= 16
+
+
 def test_shared_grid_matches_own_assembly(vie, torch):
     """A context sharing another's operator (vie_share_grid) computes the same
     products bitwise as one that assembled its own, keeps working after the

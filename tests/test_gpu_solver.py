@@ -139,7 +139,7 @@ def test_graph_replay_and_sync_interval_keep_bits(vie, torch, mode):
     for r in range(3):
         assert relerr(_host(x0, r), xrefs[r]) < (1e-8 if mode == 0 else 1e-7)
     ref = x0.cpu()
-    runs = [(1, 0), (1, 0), (1, 0), (1, 3), (1, 3), (1, 3), (0, 4), (0, 0), (1, 100)]
+    runs = [(1, 0), (1, 0), (1, 0), (1, 3), (1, 3), (1, 3), (0, 4), (0, 0), (-1, 0), (-1, 2), (1, 100)]
     for graph, sync in runs:
         x = torch.empty_like(etd)
         code, st = c.solve(etd, x, mode=mode, tol=tol, restart=6, graph=graph, sync_steps=sync)
