@@ -30,6 +30,9 @@ Fields in MRI", IEEE TAP 2020):
                   ``toeplitz`` (part 'K'), pinned by ``gaussian`` and
                   ``unreduced``
 * ``mie``       - Mie series absorbed power for a homogeneous sphere (Sec. V-A)
+* ``tucker``    - Tucker (low multilinear rank) compression of the
+                  Toeplitz-defining tensors (Sec. III-C, last paragraph):
+                  sequentially truncated HOSVD by SVD of the unfoldings
 * ``pwc``       - the piecewise-constant discretisation the paper compares
                   against (Sec. V: 3 unknowns per voxel, 6 unique tensors),
                   as the l = 1 restriction of the PWL system
