@@ -156,6 +156,47 @@ int vie_set_toeplitz(vie_ctx* ctx, const double* T_host);
  * host buffer of 60 * Nz * Ny * Nx complex128. */
 int vie_get_toeplitz(vie_ctx* ctx, double* T_host);
 
+/* -- Tucker compression of the operator (Sec. III-C, last paragraph) ------- */
+
+/* The Toeplitz-defining tensors of eq. 43 keep a low multilinear rank
+ * (Sec. III-C, last paragraph; Sec. V leaves their memory out of the
+ * footprint for that reason).  A compressed tensor is a core times one
+ * factor with orthonormal columns per axis: T_hat = core x_x U_x x_y U_y
+ * x_z U_z. */
+typedef struct {
+    int ranks[60][3];         /* (r_x, r_y, r_z) of each unique tensor          */
+    double rel_error[60];     /* ||T - T_hat||_F / ||T||_F per tensor            */
+    double max_rel_error;     /* the largest of them (<= tol)                    */
+    size_t bytes_dense;       /* the 60 tensors, complex128                      */
+    size_t bytes_compressed;  /* cores and factors, complex128                   */
+    double seconds;           /* wall time of the compression                    */
+} vie_tucker_info;
+
+/* Compress the context's 60 unique tensors (layout of vie_set_toeplitz) by
+ * sequentially truncated HOSVD in the axis order x, y, z: for each axis the
+ * eigenvectors of the FP64 Gram matrix of the unfolding of the tensor as
+ * compressed so far, keeping the fewest whose dropped eigenvalues sum to at
+ * most tol^2 ||T||_F^2 / 3, then the projection onto them.  Every tensor
+ * is then within tol of itself in the Frobenius norm (the dropped
+ * eigenvalues add up to the squared error exactly).  The compressed form
+ * (host memory, owned by the context, freed with the grid) replaces any
+ * earlier one; the operator is left as it was.  tol in [1e-7, 1):
+ * VIE_EINVAL otherwise; VIE_ESTATE before vie_set_grid.  info (host, may be
+ * NULL) receives ranks, errors and sizes. */
+int vie_tucker_compress(vie_ctx* ctx, double tol, vie_tucker_info* info);
+
+/* Write the reconstruction T_hat of the compressed form to out (device,
+ * 60 * Nz * Ny * Nx complex128, layout of vie_set_toeplitz; must not overlap
+ * the context's own blocks).  VIE_ESTATE without a compressed form. */
+int vie_tucker_reconstruct(vie_ctx* ctx, void* out);
+
+/* Replace the context's blocks by T_hat and rebuild the operator from them
+ * (circulant embedding, 3-D FFT, octant in complex128 and complex64, as
+ * vie_set_grid does), so later products and solves use the compressed
+ * operator.  VIE_ESTATE without a compressed form or when the operator is
+ * shared with another context (vie_share_grid). */
+int vie_tucker_expand(vie_ctx* ctx);
+
 /* Make dst use src's grid and operator (the same device buffers, read-only,
  * freed with the last context that uses them) instead of assembling its own;
  * dst's launch-shape choices are copied from src and its contrast cleared.

@@ -51,6 +51,16 @@ class SolveStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TuckerInfo(ctypes.Structure):
+    _fields_ = [("ranks", (_i * 3) * 60), ("rel_error", _d * 60), ("max_rel_error", _d),
+                ("bytes_dense", ctypes.c_size_t), ("bytes_compressed", ctypes.c_size_t), ("seconds", _d)]
+
+    def as_dict(self):
+        return {"ranks": np.array([[self.ranks[e][i] for i in range(3)] for e in range(60)]),
+                "rel_error": np.array(self.rel_error[:]), "max_rel_error": self.max_rel_error,
+                "bytes_dense": self.bytes_dense, "bytes_compressed": self.bytes_compressed, "seconds": self.seconds}
+
+
 class Request(ctypes.Structure):
     _fields_ = [("nx", _i), ("ny", _i), ("nz", _i), ("dx", _d), ("dy", _d), ("dz", _d), ("freq_hz", _d),
                 ("eps_re", _dp), ("sigma", _dp), ("nrhs", _i), ("pos", _dp), ("moment", _dp), ("mode", _i),
@@ -78,6 +88,9 @@ _sig = {
     "vie_set_grid": (_i, [_vp, _i, _i, _i, _d, _d, _d, _d, ctypes.POINTER(_i)]),
     "vie_set_toeplitz": (_i, [_vp, _dp]),
     "vie_get_toeplitz": (_i, [_vp, _dp]),
+    "vie_tucker_compress": (_i, [_vp, _d, ctypes.POINTER(TuckerInfo)]),
+    "vie_tucker_reconstruct": (_i, [_vp, _vp]),
+    "vie_tucker_expand": (_i, [_vp]),
     "vie_set_contrast": (_i, [_vp, _dp, _dp, _i]),
     "vie_incident_planewave": (_i, [_vp, _dp, _dp, _d, _vp]),
     "vie_incident_dipoles": (_i, [_vp, _i, _dp, _dp, _i, _vp]),
@@ -248,6 +261,23 @@ class Context:
         a = np.zeros((60, self.N[2], self.N[1], self.N[0]), dtype=np.complex128)
         _check(_lib.vie_get_toeplitz(self._h, a.view(np.float64).ctypes.data_as(_dp)))
         return a
+
+    def tucker_compress(self, tol):
+        """Tucker-compress the 60 unique tensors to relative tolerance tol;
+        returns ranks [60, 3] (x, y, z), per-tensor errors and sizes."""
+        info = TuckerInfo()
+        _check(_lib.vie_tucker_compress(self._h, float(tol), ctypes.byref(info)))
+        return info.as_dict()
+
+    def tucker_reconstruct(self, out):
+        """T_hat into out: complex128 GPU tensor [60, Nz, Ny, Nx]."""
+        import torch
+        _check(_lib.vie_tucker_reconstruct(self._h, _tensor_ptr(out, torch.complex128,
+                                                                  (60, self.N[2], self.N[1], self.N[0]))))
+
+    def tucker_expand(self):
+        """Rebuild the operator from the compressed form."""
+        _check(_lib.vie_tucker_expand(self._h))
 
     def set_contrast(self, eps_re, sigma):
         """eps', sigma as float64 arrays [Nz, Ny, Nx] (numpy on the host or

@@ -1,5 +1,7 @@
 // extern "C" entry points (include/vie.h).  Every call catches exceptions and
 // turns them into a status code plus a thread-local message.
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -28,6 +30,7 @@ Ctx::~Ctx() {
 
 void Ctx::free_grid() {
     graphs.clear();
+    tucker.clear();
     op.reset();   // frees the operator unless another context shares it
     for (auto& a : ax) a = FftAxis{};
     T = nullptr;
@@ -242,6 +245,66 @@ int vie_get_toeplitz(vie_ctx* ctx, double* T_host) {
         VIE_REQUIRE(c.has_grid, VIE_ESTATE, "no grid");
         VIE_REQUIRE(T_host != nullptr, VIE_EINVAL, "T_host is null");
         VIE_HIP(hipMemcpyAsync(T_host, c.T, 60 * c.V * sizeof(double2), hipMemcpyDeviceToHost, c.stream));
+        VIE_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+int vie_tucker_compress(vie_ctx* ctx, double tol, vie_tucker_info* info) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_grid, VIE_ESTATE, "vie_tucker_compress before vie_set_grid");
+        VIE_REQUIRE(tol >= 1e-7 && tol < 1.0, VIE_EINVAL, "tol must be in [1e-7, 1)");
+        const auto t0 = std::chrono::steady_clock::now();
+        tucker_compress(c, tol);
+        if (info) {
+            *info = vie_tucker_info{};
+            double worst = 0;
+            for (int e = 0; e < 60; ++e) {
+                const TuckerTensor& t = c.tucker.tensors[e];
+                for (int i = 0; i < 3; ++i) info->ranks[e][i] = t.r[i];
+                info->rel_error[e] = t.rel_error;
+                worst = std::max(worst, t.rel_error);
+            }
+            info->max_rel_error = worst;
+            info->bytes_dense = (size_t)60 * c.V * sizeof(double2);
+            info->bytes_compressed = c.tucker.values() * sizeof(double2);
+            info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+    });
+}
+
+int vie_tucker_reconstruct(vie_ctx* ctx, void* out) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_grid, VIE_ESTATE, "no grid");
+        VIE_REQUIRE(out != nullptr, VIE_EINVAL, "out is null");
+        VIE_REQUIRE(!overlaps(out, 60 * c.V * sizeof(double2), c.T, 60 * c.V * sizeof(double2)), VIE_EINVAL,
+                    "out overlaps the context's blocks");
+        tucker_reconstruct(c, static_cast<double2*>(out));
+        VIE_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+int vie_tucker_expand(vie_ctx* ctx) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_grid, VIE_ESTATE, "no grid");
+        VIE_REQUIRE(c.tucker.valid, VIE_ESTATE, "no Tucker form: call vie_tucker_compress first");
+        VIE_REQUIRE(c.op.use_count() == 1, VIE_ESTATE, "the operator is shared with another context");
+        // T <- T_hat, then the set-up's embedding, FFT and octant
+        tucker_reconstruct(c, c.T);
+        const long long Mt = (long long)c.M[0] * c.M[1] * c.M[2];
+        double2* circ = static_cast<double2*>(c.ws.get(Mt * sizeof(double2)));
+        const double2* tws[3] = {c.ax[0].tw128, c.ax[1].tw128, c.ax[2].tw128};
+        FftPlan plans[3] = {c.ax[0].plan, c.ax[1].plan, c.ax[2].plan};
+        embed_and_transform(c.U128, c.U64, c.T, circ, c.N[0], c.N[1], c.N[2], c.M[0], c.M[1], c.M[2], plans, tws,
+                            c.stream);
         VIE_HIP(hipStreamSynchronize(c.stream));
     });
 }

@@ -1,6 +1,7 @@
 // Library context: grid, resident operator, materials, workspaces.
 #pragma once
 
+#include <complex>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -182,6 +183,26 @@ struct GraphCache {
     }
 };
 
+// Tucker form of one Toeplitz-defining tensor (tucker.hip), complex128 on
+// the host: factors U_i (N_i x r_i, row-major) for x, y, z and the core
+// [r_z][r_y][r_x]
+struct TuckerTensor {
+    int r[3] = {0, 0, 0};
+    std::vector<std::vector<std::complex<double>>> U;
+    std::vector<std::complex<double>> core;
+    double norm = 0, rel_error = 0;   // ||T||_F and ||T - T_hat||_F / ||T||_F
+};
+struct TuckerForm {
+    bool valid = false;
+    double tol = 0;
+    std::vector<TuckerTensor> tensors;   // the 60 unique tensors
+    size_t values() const;               // complex values stored
+    void clear() {
+        valid = false;
+        tensors.clear();
+    }
+};
+
 // launch shapes of the operator product, chosen per (precision, nrhs) by
 // the autotuner; zeros mean the built-in defaults
 struct Tune {
@@ -226,6 +247,7 @@ struct Ctx {
     Profiler prof;
     std::map<std::pair<int, int>, Tune> tune;   // (precision, nrhs) -> shapes
     GraphCache graphs;
+    TuckerForm tucker;          // compressed copy of the grid's 60 tensors
 
     ~Ctx();
     void free_grid();
@@ -273,6 +295,11 @@ int guarded(F&& f) {
         return VIE_EDEVICE;
     }
 }
+
+// Tucker compression of the 60 Toeplitz-defining tensors at relative
+// tolerance tol (tucker.hip), and the reconstruction T_hat [60][V] into out
+void tucker_compress(Ctx& c, double tol);
+void tucker_reconstruct(Ctx& c, double2* out);
 
 // autotuner (tune.cpp): fastest launch shapes for (precision, nrhs)
 Tune autotune(Ctx& c, int precision, int nrhs, double* best_ms);

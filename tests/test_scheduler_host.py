@@ -46,7 +46,7 @@ def _c_layout(tmp_path, struct, fields):
 
 @pytest.mark.parametrize("name,cname", [("SolveOpts", "vie_solve_opts"), ("SolveStats", "vie_solve_stats"),
                                         ("Request", "vie_request"), ("RequestInfo", "vie_request_info"),
-                                        ("ServingStats", "vie_serving_stats")])
+                                        ("ServingStats", "vie_serving_stats"), ("TuckerInfo", "vie_tucker_info")])
 def test_ctypes_records_match_header(tmp_path, name, cname):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
