@@ -276,6 +276,9 @@ def main():
                     help="time one launch in this many of each kernel class by its own events inside the timed "
                          "solves (0: none there; the classes are then timed in one more solve after the timed "
                          "region); graph replay implies 0, since a replayed launch carries no events")
+    ap.add_argument("--tucker", type=float, default=0.0,
+                    help="Tucker-compress the operator tensors to this relative tolerance and solve on the "
+                         "operator rebuilt from the compressed form (0: off)")
     ap.add_argument("--products", type=int, default=0,
                     help="counter runs: after set-up and autotuning, time this many complex64 operator products "
                          "of one batch, run the 256 MiB calibration copy, print one JSON line and stop (no solves)")
@@ -307,6 +310,22 @@ def main():
         ctx.set_basis(nc)
     torch.cuda.synchronize()
     t_grid = time.perf_counter() - t0
+    tucker = None
+    if args.tucker > 0:
+        t0 = time.perf_counter()
+        info = ctx.tucker_compress(args.tucker)
+        t_c = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ctx.tucker_expand()
+        torch.cuda.synchronize()
+        t_e = time.perf_counter() - t0
+        tucker = {"tol": args.tucker, "max_rank": [int(v) for v in info["ranks"].max(axis=0)],
+                  "mean_rank": [round(float(v), 2) for v in info["ranks"].mean(axis=0)],
+                  "max_rel_error": info["max_rel_error"], "bytes_dense": info["bytes_dense"],
+                  "bytes_compressed": info["bytes_compressed"],
+                  "compressed_fraction": round(info["bytes_compressed"] / info["bytes_dense"], 5),
+                  "compress_s": round(t_c, 3), "expand_s": round(t_e, 3)}
+        log("tucker: %s" % tucker)
     t0 = time.perf_counter()
     tune64 = ctx.autotune(vie.C64, W.get("group", W.get("nrhs", 1)))
     tune128 = ctx.autotune(vie.C128, 1)
@@ -359,6 +378,7 @@ def main():
         dev_ms = sum(v[0] for v in mvprof.values()) / args.products
         by = sum(v[2] for v in mvprof.values()) / args.products
         print(json.dumps({"workload": args.workload, "products": args.products, "nrhs": group, "fft_size": ctx.fft_size,
+                          "tucker": tucker,
                           "autotune_c64": tune64, "product_ms": round(t_mv * 1e3, 4),
                           "product_device_ms": round(dev_ms, 4), "product_MB_algorithmic": round(by / 1e6, 1),
                           "product_GBps_algorithmic": round(by / (dev_ms * 1e-3) / 1e9, 1), "passes": passes,
@@ -552,6 +572,7 @@ def main():
         "setup_s": round(t_grid, 3),
         "autotune": {"c64": tune64[0], "c128": tune128[0], "seconds": round(t_tune, 2)},
         "solver": {"graph": args.graph, "sync_steps": args.sync_steps, "profile_every": every},
+        "tucker": tucker,
         "kernel_source_hash": kernel_source_hash(),
         "kernels": kernels,
         "roofline": roofline,
