@@ -29,7 +29,11 @@ Fields in MRI", IEEE TAP 2020):
                   energy and the errors of Sec. V-D; the K blocks come from
                   ``toeplitz`` (part 'K'), pinned by ``gaussian`` and
                   ``unreduced``
-* ``mie``       - Mie series absorbed power for a homogeneous sphere (Sec. V-A)
+* ``mie``       - Mie series absorbed power for a homogeneous sphere (Sec. V-A),
+                  also with a relative permeability (the J-M pin)
+* ``jm``        - the J-M formulation with magnetic contrast (Sec. II
+                  eq. 13-15): 24 unknowns per voxel, the N and K blocks
+                  combined, dense LU for tiny grids, fields and power
 * ``tucker``    - Tucker (low multilinear rank) compression of the
                   Toeplitz-defining tensors (Sec. III-C, last paragraph):
                   sequentially truncated HOSVD by SVD of the unfoldings

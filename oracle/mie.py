@@ -78,3 +78,41 @@ def absorbed_power(radius, eps_re, sigma, freq_hz, E0=1.0, method='logderiv'):
     """Absorbed power (W) for a plane wave of amplitude E0 (V/m)."""
     cext, csca = cross_sections(radius, eps_re, sigma, freq_hz, method)
     return (cext - csca) * E0 ** 2 / (2.0 * physics.ETA0)
+
+
+def coefficients_magnetic(x, m, mu_ratio):
+    """a_n, b_n of a sphere with relative permeability mu_ratio = mu1 / mu
+    (Bohren & Huffman eq. 4.53), direct spherical Bessel functions:
+      a_n = (m psi_n(mx) psi_n'(x) - mu_ratio psi_n(x) psi_n'(mx))
+            / (m psi_n(mx) xi_n'(x) - mu_ratio xi_n(x) psi_n'(mx))
+      b_n = (mu_ratio psi_n(mx) psi_n'(x) - m psi_n(x) psi_n'(mx))
+            / (mu_ratio psi_n(mx) xi_n'(x) - m xi_n(x) psi_n'(mx))
+    with m = sqrt(eps_r mu_r) the relative index; mu_ratio = 1 gives the
+    dielectric coefficients."""
+    nmax = _nmax(x, m)
+    n = np.arange(1, nmax + 1)
+    psi, dpsi, xi, dxi = _riccati_real(n, x)
+    mx = m * x
+    jm = sp.spherical_jn(n, mx)
+    jmd = sp.spherical_jn(n, mx, derivative=True)
+    psim = mx * jm
+    dpsim = jm + mx * jmd
+    a = (m * psim * dpsi - mu_ratio * psi * dpsim) / (m * psim * dxi - mu_ratio * xi * dpsim)
+    b = (mu_ratio * psim * dpsi - m * psi * dpsim) / (mu_ratio * psim * dxi - m * xi * dpsim)
+    return n, a, b
+
+
+def absorbed_power_magnetic(radius, eps_r, mu_r, freq_hz, E0=1.0):
+    """Absorbed power (W) of a plane wave of amplitude E0 on a sphere of
+    complex eps_r and mu_r given in the paper's convention (eq. 2, exp(+i w
+    t), negative imaginary parts for loss): mapped to exp(-i w t) by
+    conjugation, m = sqrt(eps mu) with a positive imaginary part."""
+    k = physics.k0(freq_hz)
+    e, mu = np.conj(eps_r), np.conj(mu_r)
+    m = np.sqrt(e * mu)
+    if m.imag < 0:
+        m = -m
+    n, a, b = coefficients_magnetic(k * radius, m, mu)
+    cext = 2 * np.pi / k ** 2 * np.sum((2 * n + 1) * np.real(a + b))
+    csca = 2 * np.pi / k ** 2 * np.sum((2 * n + 1) * (np.abs(a) ** 2 + np.abs(b) ** 2))
+    return (cext - csca) * E0 ** 2 / (2.0 * physics.ETA0)

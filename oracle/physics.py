@@ -1,8 +1,8 @@
 """Physical constants and material maps (TEST INFRASTRUCTURE, see package doc).
 
-Paper: Sec. II, eq. (1)-(2) (complex relative permittivity with time factor
-exp(+i w t)), eq. (6)-(7) (c_e = i w eps0, chi = eps_r - 1), Sec. IV-B
-(tau = chi / eps_r).
+Paper: Sec. II, eq. (1)-(2) (complex relative permittivity and permeability
+with time factor exp(+i w t)), eq. (6)-(7) (c_e = i w eps0, c_m = i w mu0,
+chi = eps_r - 1, chi_m = mu_r - 1), Sec. IV-B (tau = chi / eps_r).
 """
 import numpy as np
 
@@ -25,6 +25,16 @@ def k0(freq_hz):
 def c_e(freq_hz):
     """c_e = i w eps0 (eq. 6)."""
     return 1j * omega(freq_hz) * EPS0
+
+
+def c_m(freq_hz):
+    """c_m = i w mu0 (eq. 6)."""
+    return 1j * omega(freq_hz) * MU0
+
+
+def mu_r(mu_re, mu_im):
+    """mu_r = mu' - i mu'' (eq. 2, time factor exp(+i w t))."""
+    return np.asarray(mu_re, dtype=np.float64) - 1j * np.asarray(mu_im, dtype=np.float64)
 
 
 def eps_r(eps_re, sigma, freq_hz):
