@@ -142,7 +142,23 @@ int vie_set_grid(vie_ctx* ctx, int nx, int ny, int nz, double dx, double dy, dou
  * PWC product needs an fft length along x of 8, 16, 32, 64, 96, 128, 160,
  * 192, 256, 320, 384 or 512: a later vie_set_grid without fft_size picks the
  * smallest of them >= 2 Nx for a PWC context; products on other lengths
- * return VIE_EINVAL.  Returns VIE_EINVAL for ncomp other than 12 or 3. */
+ * return VIE_EINVAL.
+ *
+ * ncomp = 24 selects the J-M formulation on the PWL basis (Sec. II, eq.
+ * 13-15): objects with magnetic contrast carry polarisation and
+ * magnetisation currents j = c_e chi_e e and m = c_m chi_m h (eq. 6-7,
+ * c_m = i w mu0); a vector holds per right-hand side the 12 electric then
+ * the 12 magnetic coefficients ([nrhs][24][Nz][Ny][Nx]).  The operator is
+ *   (A x)_j = eps_r G x_j - chi_e (N x_j - c_e K x_m)
+ *   (A x)_m = mu_r G x_m - chi_m (N x_m + c_m K x_j)
+ * with K the curl operator (eq. 8b, 25b), preconditioned by
+ * P = diag(M_eps G, M_mu G); incident calls write [e_t; h_t], vie_rhs_prec
+ * and vie_solve take them, vie_fields returns [e; h], vie_absorbed_power
+ * adds the magnetic loss; vie_apply takes VIE_OP_PREC and VIE_OP_A.
+ * The magnetic contrast is mu_r = 1 until vie_set_magnetic_contrast.
+ * vie_total_field, vie_power_density, the magnetic-field calls and
+ * vie_apply_noalloc refuse a J-M context (VIE_EINVAL).  Returns VIE_EINVAL
+ * for ncomp other than 12, 3 or 24. */
 int vie_set_basis(vie_ctx* ctx, int ncomp);
 
 /* Debug / parity entry: replace the operator by caller-supplied unique block
@@ -214,6 +230,14 @@ int vie_fft_size(vie_ctx* ctx, int* m3);
  * chi = eps_r - 1 and tau = chi / eps_r on the device.  VIE_ENAN on
  * non-finite input, VIE_EINVAL on eps' <= 0 or sigma < 0. */
 int vie_set_contrast(vie_ctx* ctx, const double* eps_re, const double* sigma, int on_device);
+
+/* J-M formulation (vie_set_basis 24) only: per-voxel relative permeability
+ * mu_r = mu' - i mu'' (eq. 2), FP64 [Nz][Ny][Nx], host (on_device = 0) or
+ * device pointers; computes chi_m = mu_r - 1 and tau_m = chi_m / mu_r.
+ * VIE_ENAN on non-finite input, VIE_EINVAL on mu' <= 0, mu'' < 0 or a
+ * context that is not J-M.  Replaced by mu_r = 1 when the grid or the
+ * basis changes. */
+int vie_set_magnetic_contrast(vie_ctx* ctx, const double* mu_re, const double* mu_im, int on_device);
 
 /* Tested incident field of a plane wave E0 pol exp(-i k0 dir . r) (eq. 30,
  * plane wave of Sec. V-A for pol = x, dir = z), into e_t (device,

@@ -88,6 +88,7 @@ _sig = {
     "vie_set_grid": (_i, [_vp, _i, _i, _i, _d, _d, _d, _d, ctypes.POINTER(_i)]),
     "vie_set_toeplitz": (_i, [_vp, _dp]),
     "vie_get_toeplitz": (_i, [_vp, _dp]),
+    "vie_set_magnetic_contrast": (_i, [_vp, _dp, _dp, _i]),
     "vie_tucker_compress": (_i, [_vp, _d, ctypes.POINTER(TuckerInfo)]),
     "vie_tucker_reconstruct": (_i, [_vp, _vp]),
     "vie_tucker_expand": (_i, [_vp]),
@@ -228,7 +229,8 @@ class Context:
         self.N = (nx, ny, nz)
 
     def set_basis(self, ncomp):
-        """12: PWL basis (default); 3: PWC basis (pulse functions alone)."""
+        """12: PWL basis (default); 3: PWC basis (pulse functions alone); 24:
+        PWL basis, J-M formulation (electric then magnetic currents)."""
         _check(_lib.vie_set_basis(self._h, int(ncomp)))
         self.nc = int(ncomp)
 
@@ -261,6 +263,13 @@ class Context:
         a = np.zeros((60, self.N[2], self.N[1], self.N[0]), dtype=np.complex128)
         _check(_lib.vie_get_toeplitz(self._h, a.view(np.float64).ctypes.data_as(_dp)))
         return a
+
+    def set_magnetic_contrast(self, mu_re, mu_im):
+        """J-M contexts (set_basis(24)): mu', mu'' as float64 arrays [Nz, Ny, Nx]
+        on the host, mu_r = mu' - i mu''."""
+        a = np.ascontiguousarray(mu_re, dtype=np.float64)
+        b = np.ascontiguousarray(mu_im, dtype=np.float64)
+        _check(_lib.vie_set_magnetic_contrast(self._h, _dptr(a), _dptr(b), 0))
 
     def tucker_compress(self, tol):
         """Tucker-compress the 60 unique tensors to relative tolerance tol;

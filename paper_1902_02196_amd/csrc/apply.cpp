@@ -28,6 +28,9 @@ template <> const C<double>* twid<double>(const FftAxis& a) { return a.tw128; }
 template <typename R> static const C<R>* opspec(const Ctx& c);
 template <> const C<float>* opspec<float>(const Ctx& c) { return c.U64; }
 template <> const C<double>* opspec<double>(const Ctx& c) { return c.U128; }
+template <typename R> static const C<R>* curlspec(const Ctx& c);
+template <> const C<float>* curlspec<float>(const Ctx& c) { return c.op->UK64; }
+template <> const C<double>* curlspec<double>(const Ctx& c) { return c.op->UK128; }
 
 static int pick_tile(int n, size_t elem) { return strided_tile_for((int)elem, n, 16); }
 
@@ -47,11 +50,20 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs,
         if (it != c.tune.end()) tn = it->second;
     }
     VIE_REQUIRE(c.has_grid, VIE_ESTATE, "vie_apply before vie_set_grid");
-    if (op != OP_N && op != OP_CURL) VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "operator needs vie_set_contrast");
+    if (c.nc == 24) {   // J-M formulation: composed from N and K products
+        apply_jm<R>(c, op, nrhs, x, y, rhs, ws_ext, ws_cap);
+        return;
+    }
+    if (op != OP_N && op != OP_CURL && op != OP_K)
+        VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "operator needs vie_set_contrast");
     if (op == OP_CURL) {
         VIE_REQUIRE(sizeof(R) == 8 && c.nc == 12, VIE_EINVAL,
                     "the magnetic product is complex128 and PWL (12 unknowns per voxel) only");
         VIE_REQUIRE(c.op && c.op->UK128, VIE_ESTATE, "curl operator not built");
+    }
+    if (op == OP_K) {
+        VIE_REQUIRE(c.nc == 12, VIE_EINVAL, "the curl product is PWL (12 unknowns per voxel) only");
+        VIE_REQUIRE(c.op && curlspec<R>(c), VIE_ESTATE, "curl operator not built");
     }
     const int Nx = c.N[0], Ny = c.N[1], Nz = c.N[2];
     const int Mx = c.M[0], My = c.M[1], Mz = c.M[2];
@@ -142,22 +154,20 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs,
     p3.s_y = row;
     p3.u_e = c.O[0];
     p3.pitch = Mx;
-    if (op == OP_CURL) {
+    if (op == OP_CURL || op == OP_K) {
         // curl operator: staged x pass (any length up to 256) on its 30
         // unique tensors
-        if constexpr (sizeof(R) == 8) {
-            const int nt = p3_threads<R>();
-            const size_t ul = 30 * (size_t)c.O[0] * es;
-            int g = 4;
-            while (g > 1 && (ul + (size_t)lds_pad(g * 12 * Mx) * es > 80 * 1024 || !rows_fit(p3.plan, g * 12, nt) ||
-                             2 * g * Mx > nt))
-                --g;
-            p3.groups = g;
-            p3.variant = 0;
-            p3.sib_blocks = 1;
-            KernelTiming kt(c.prof, VIE_K_BLOCK, 2 * bA2 + 30.0 * c.Osz * es);
-            launch_p3_curl(A2, c.op->UK128, p3, twid<R>(c.ax[0]), s);
-        }
+        const int nt = p3_threads<R>();
+        const size_t ul = 30 * (size_t)c.O[0] * es;
+        int g = 4;
+        while (g > 1 && (ul + (size_t)lds_pad(g * 12 * Mx) * es > 80 * 1024 || !rows_fit(p3.plan, g * 12, nt) ||
+                         2 * g * Mx > nt))
+            --g;
+        p3.groups = g;
+        p3.variant = 0;
+        p3.sib_blocks = 1;
+        KernelTiming kt(c.prof, VIE_K_BLOCK, 2 * bA2 + 30.0 * c.Osz * es);
+        launch_p3_curl<R>(A2, curlspec<R>(c), p3, twid<R>(c.ax[0]), s);
     } else if (nc == 3) {
         // PWC: 6 of the operator's unique tensors per frequency
         VIE_REQUIRE(p3_ct_supported(Mx), VIE_EINVAL,
@@ -260,6 +270,7 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs,
                 ep.gb[l] = -scale;
                 break;
             case OP_N:
+            case OP_K:
                 ep.a_const = 0;
                 ep.ga[l] = 0;
                 ep.b_const = 1;

@@ -18,6 +18,7 @@ thread_local std::string g_err;
 Ctx::~Ctx() {
     free_grid();
     free_contrast();
+    jmbuf.release();
     ws.release();
     small.release();
     basis.release();
@@ -31,6 +32,7 @@ Ctx::~Ctx() {
 void Ctx::free_grid() {
     graphs.clear();
     tucker.clear();
+    free_mcontrast();
     op.reset();   // frees the operator unless another context shares it
     for (auto& a : ax) a = FftAxis{};
     T = nullptr;
@@ -47,6 +49,15 @@ void Ctx::free_contrast() {
     mat = Materials{};
     sigma = nullptr;
     has_contrast = false;
+}
+
+void Ctx::free_mcontrast() {
+    graphs.clear();
+    void* ps[] = {mmat.eps_r, mmat.chi, mmat.tau, mmat.tau64, mmat.epsr64, mmat.chi64};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    mmat = Materials{};
+    has_mcontrast = false;
 }
 
 }  // namespace vie
@@ -340,6 +351,43 @@ int vie_set_contrast(vie_ctx* ctx, const double* eps_re, const double* sigma, in
             throw Error(VIE_EINVAL, "permittivity must be > 0 and conductivity >= 0");
         }
         c.has_contrast = true;
+        if (c.nc == 24 && !c.has_mcontrast) jm_default_mcontrast(c);
+    });
+}
+
+int vie_set_magnetic_contrast(vie_ctx* ctx, const double* mu_re, const double* mu_im, int on_device) {
+    return guarded([&] {
+        check_ctx(ctx);
+        Ctx& c = ctx->c;
+        set_device(c);
+        VIE_REQUIRE(c.has_grid, VIE_ESTATE, "vie_set_magnetic_contrast before vie_set_grid");
+        VIE_REQUIRE(c.nc == 24, VIE_EINVAL, "a magnetic contrast needs the J-M formulation (vie_set_basis 24)");
+        VIE_REQUIRE(mu_re && mu_im, VIE_EINVAL, "null material array");
+        c.free_mcontrast();
+        const size_t V = (size_t)c.V;
+        Materials& m = c.mmat;
+        VIE_HIP(hipMalloc(&m.eps_r, V * sizeof(double2)));
+        VIE_HIP(hipMalloc(&m.chi, V * sizeof(double2)));
+        VIE_HIP(hipMalloc(&m.tau, V * sizeof(double2)));
+        VIE_HIP(hipMalloc(&m.tau64, V * sizeof(float2)));
+        VIE_HIP(hipMalloc(&m.epsr64, V * sizeof(float2)));
+        VIE_HIP(hipMalloc(&m.chi64, V * sizeof(float2)));
+        double* dev = static_cast<double*>(c.small.get(2 * V * sizeof(double)));
+        const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        VIE_HIP(hipMemcpyAsync(dev, mu_re, V * sizeof(double), k, c.stream));
+        VIE_HIP(hipMemcpyAsync(dev + V, mu_im, V * sizeof(double), k, c.stream));
+        VIE_HIP(hipMemsetAsync(c.flag, 0, sizeof(int), c.stream));
+        // mu_r = mu' - i mu'' (eq. 2): the permittivity kernel with sigma / (w eps0) -> mu''
+        launch_materials(dev, dev + V, 1.0, m, c.V, c.flag, c.stream);
+        int bad = 0;
+        VIE_HIP(hipMemcpyAsync(&bad, c.flag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        VIE_HIP(hipStreamSynchronize(c.stream));
+        if (bad) {
+            c.free_mcontrast();
+            if (bad & 1) throw Error(VIE_ENAN, "non-finite permeability");
+            throw Error(VIE_EINVAL, "mu' must be > 0 and mu'' >= 0");
+        }
+        c.has_mcontrast = true;
     });
 }
 
@@ -365,8 +413,10 @@ int vie_incident_planewave(vie_ctx* ctx, const double pol[3], const double dir[3
         const int pa = axis_of(pol), da = axis_of(dir);
         VIE_REQUIRE(pa >= 0 && da >= 0 && pa != da, VIE_EINVAL,
                     "pol and dir must be distinct unit vectors along coordinate axes");
-        launch_planewave(static_cast<double2*>(e_t), c.N[0], c.N[1], c.N[2], c.D, c.k0, pa, da, dir[da] > 0 ? 1.0 : -1.0,
-                         amp * sign_of(pol[pa]), c.nc, c.stream);
+        double2* et = static_cast<double2*>(e_t);
+        launch_planewave(et, c.N[0], c.N[1], c.N[2], c.D, c.k0, pa, da, dir[da] > 0 ? 1.0 : -1.0,
+                         amp * sign_of(pol[pa]), c.nc == 24 ? 12 : c.nc, c.stream);
+        if (c.nc == 24) planewave_h(c, pol, dir, amp, et + 12 * c.V);   // J-M: [e_t; h_t]
     });
 }
 
@@ -391,8 +441,20 @@ int vie_incident_dipoles(vie_ctx* ctx, int nrhs, const double* pos, const double
         }
         double* dev = static_cast<double*>(c.small.get(host.size() * sizeof(double)));
         VIE_HIP(hipMemcpyAsync(dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
-        launch_dipoles(static_cast<double2*>(e_t), nrhs, dev, dev + 3 * nrhs, nq, dev + 6 * nrhs, dev + 6 * nrhs + nq,
-                       c.mat.chi, c.N[0], c.N[1], c.N[2], c.D, c.k0, c.omega * kEps0, c.nc, c.stream);
+        if (c.nc == 24) {   // J-M: per right-hand side the tested e (on tissue) and h (everywhere)
+            for (int r = 0; r < nrhs; ++r) {
+                double2* et = static_cast<double2*>(e_t) + (long long)r * 24 * c.V;
+                launch_dipoles(et, 1, dev + 3 * r, dev + 3 * nrhs + 3 * r, nq, dev + 6 * nrhs, dev + 6 * nrhs + nq,
+                               c.mat.chi, c.N[0], c.N[1], c.N[2], c.D, c.k0, c.omega * kEps0, 12, c.stream);
+                launch_dipoles(et + 12 * c.V, 1, dev + 3 * r, dev + 3 * nrhs + 3 * r, nq, dev + 6 * nrhs,
+                               dev + 6 * nrhs + nq, nullptr, c.N[0], c.N[1], c.N[2], c.D, c.k0, c.omega * kEps0, 12,
+                               c.stream, 1);
+            }
+        } else {
+            launch_dipoles(static_cast<double2*>(e_t), nrhs, dev, dev + 3 * nrhs, nq, dev + 6 * nrhs,
+                           dev + 6 * nrhs + nq, c.mat.chi, c.N[0], c.N[1], c.N[2], c.D, c.k0, c.omega * kEps0, c.nc,
+                           c.stream);
+        }
         VIE_HIP(hipStreamSynchronize(c.stream));   // the host staging buffer is reused
     });
 }
@@ -404,6 +466,10 @@ int vie_rhs_prec(vie_ctx* ctx, int nrhs, const void* e_t, void* rhs) {
         set_device(c);
         VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "no contrast");
         VIE_REQUIRE(nrhs >= 1 && e_t && rhs, VIE_EINVAL, "bad arguments");
+        if (c.nc == 24) {
+            jm_rhs_prec(c, nrhs, static_cast<const double2*>(e_t), static_cast<double2*>(rhs));
+            return;
+        }
         const double dv = c.D[0] * c.D[1] * c.D[2];
         const double ginv[4] = {1 / dv, 12 / dv, 12 / dv, 12 / dv};
         launch_rhs_prec(static_cast<double2*>(rhs), static_cast<const double2*>(e_t), c.mat.tau, ginv,
@@ -477,6 +543,16 @@ int vie_fields(vie_ctx* ctx, int nrhs, const void* x, void* e) {
         set_device(c);
         VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "no contrast");
         VIE_REQUIRE(nrhs >= 1 && x && e, VIE_EINVAL, "bad arguments");
+        if (c.nc == 24) {   // J-M: e = x_j / (c_e chi_e), h = x_m / (c_m chi_m)
+            for (int r = 0; r < nrhs; ++r) {
+                const long long o = (long long)r * 24 * c.V, h = 12 * c.V;
+                launch_fields(static_cast<double2*>(e) + o, static_cast<const double2*>(x) + o, c.mat.chi,
+                              make_double2(0.0, c.omega * kEps0), c.V, 1, 12, c.stream);
+                launch_fields(static_cast<double2*>(e) + o + h, static_cast<const double2*>(x) + o + h, c.mmat.chi,
+                              make_double2(0.0, c.omega * kMu0), c.V, 1, 12, c.stream);
+            }
+            return;
+        }
         launch_fields(static_cast<double2*>(e), static_cast<const double2*>(x), c.mat.chi,
                       make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.nc, c.stream);
     });
@@ -488,6 +564,7 @@ int vie_total_field(vie_ctx* ctx, int nrhs, const void* e_t, const void* x, void
         Ctx& c = ctx->c;
         set_device(c);
         VIE_REQUIRE(c.has_grid, VIE_ESTATE, "no grid");
+        VIE_REQUIRE(c.nc != 24, VIE_EINVAL, "the total field is computed for the dielectric formulation");
         VIE_REQUIRE(nrhs >= 1 && e_t && x && e, VIE_EINVAL, "bad arguments");
         const size_t bytes = (size_t)nrhs * c.nc * c.V * sizeof(double2);
         VIE_REQUIRE(!overlaps(e, bytes, x, bytes) && !overlaps(e, bytes, e_t, bytes), VIE_EINVAL,
@@ -508,17 +585,27 @@ int vie_absorbed_power(vie_ctx* ctx, int nrhs, const void* x, double* p_abs_host
         VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "no contrast");
         VIE_REQUIRE(nrhs >= 1 && x && p_abs_host, VIE_EINVAL, "bad arguments");
         const int nb = 256;
-        double* part = static_cast<double*>(c.small.get((size_t)nb * nrhs * sizeof(double)));
+        const int halves = c.nc == 24 ? 2 : 1;
+        double* part = static_cast<double*>(c.small.get((size_t)nb * nrhs * halves * sizeof(double)));
         const double dv = c.D[0] * c.D[1] * c.D[2];
         const double gram[4] = {dv, dv / 12, dv / 12, dv / 12};
-        launch_power_partials(part, static_cast<const double2*>(x), c.mat.chi, gram,
-                              make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.nc, nb, c.stream);
-        std::vector<double> h((size_t)nb * nrhs);
+        if (c.nc == 24) {   // J-M: the electric and the magnetic loss, each half on its own
+            for (int r = 0; r < nrhs; ++r)
+                for (int hh = 0; hh < 2; ++hh)
+                    launch_power_partials(part + (size_t)(2 * r + hh) * nb,
+                                          static_cast<const double2*>(x) + ((long long)r * 24 + 12 * hh) * c.V,
+                                          hh ? c.mmat.chi : c.mat.chi, gram,
+                                          make_double2(0.0, c.omega * (hh ? kMu0 : kEps0)), c.V, 1, 12, nb, c.stream);
+        } else {
+            launch_power_partials(part, static_cast<const double2*>(x), c.mat.chi, gram,
+                                  make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.nc, nb, c.stream);
+        }
+        std::vector<double> h((size_t)nb * nrhs * halves);
         VIE_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
         VIE_HIP(hipStreamSynchronize(c.stream));
         for (int r = 0; r < nrhs; ++r) {
             double s = 0;
-            for (int b = 0; b < nb; ++b) s += h[(size_t)r * nb + b];
+            for (int b = 0; b < nb * halves; ++b) s += h[(size_t)r * nb * halves + b];
             p_abs_host[r] = s;
         }
     });
@@ -530,6 +617,7 @@ int vie_power_density(vie_ctx* ctx, int nrhs, const void* e, double* p_dev) {
         Ctx& c = ctx->c;
         set_device(c);
         VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "no contrast");
+        VIE_REQUIRE(c.nc != 24, VIE_EINVAL, "the power density is computed for the dielectric formulation");
         VIE_REQUIRE(nrhs >= 1 && e && p_dev, VIE_EINVAL, "bad arguments");
         launch_power_density(p_dev, static_cast<const double2*>(e), c.sigma, c.V, nrhs, c.nc, c.stream);
     });
@@ -553,7 +641,10 @@ int vie_autotune(vie_ctx* ctx, int precision, int nrhs, int* choice, double* bes
         VIE_REQUIRE(c.has_grid, VIE_ESTATE, "autotune needs a grid");
         VIE_REQUIRE(precision == VIE_C64 || precision == VIE_C128, VIE_EINVAL, "bad precision");
         VIE_REQUIRE(nrhs >= 1, VIE_EINVAL, "nrhs must be >= 1");
-        Tune t = autotune(c, precision, nrhs, best_ms);
+        // a J-M product runs its 2 nrhs halves as 12-component products
+        const int jm = c.nc == 24;
+        NcGuard g(c, jm ? 12 : c.nc);
+        Tune t = autotune(c, precision, jm ? 2 * nrhs : nrhs, best_ms);
         if (choice) {
             choice[0] = t.p3_variant;
             choice[1] = t.p3_sib_blocks;
@@ -566,11 +657,15 @@ int vie_autotune(vie_ctx* ctx, int precision, int nrhs, int* choice, double* bes
 int vie_set_basis(vie_ctx* ctx, int ncomp) {
     return guarded([&] {
         check_ctx(ctx);
-        VIE_REQUIRE(ncomp == 12 || ncomp == 3, VIE_EINVAL, "ncomp must be 12 (PWL) or 3 (PWC)");
+        VIE_REQUIRE(ncomp == 12 || ncomp == 3 || ncomp == 24, VIE_EINVAL,
+                    "ncomp must be 12 (PWL), 3 (PWC) or 24 (PWL, J-M formulation)");
         Ctx& c = ctx->c;
+        set_device(c);
         c.nc = ncomp;
         c.tune.clear();
         c.graphs.clear();
+        c.free_mcontrast();
+        if (ncomp == 24 && c.has_contrast) jm_default_mcontrast(c);
     });
 }
 
@@ -611,7 +706,7 @@ int vie_set_tuning(vie_ctx* ctx, int precision, int nrhs, const int* choice) {
         VIE_REQUIRE(strided_tile_ok(es, c.M[2], t.tile_z) && strided_tile_ok(es, c.M[1], t.tile_y), VIE_EINVAL,
                     "tile not available for this fft size (8 or 16, or 32 with a compiled length)");
         c.graphs.clear();
-        c.tune[{precision == VIE_C64 ? 0 : 1, nrhs}] = t;
+        c.tune[{precision == VIE_C64 ? 0 : 1, c.nc == 24 ? 2 * nrhs : nrhs}] = t;
     });
 }
 

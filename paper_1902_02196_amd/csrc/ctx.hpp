@@ -31,10 +31,11 @@ struct OperatorData {
     double2* U128 = nullptr;
     float2* U64 = nullptr;
     // curl operator K (eq. 8b, 25b), built on first use by a magnetic-field
-    // call: 30 unique tensors [30][V] and their octant [Oz][Oy][30][Ox],
-    // complex128
+    // call or a J-M product: 30 unique tensors [30][V] and their octant
+    // [Oz][Oy][30][Ox], complex128 and complex64
     double2* TK = nullptr;
     double2* UK128 = nullptr;
+    float2* UK64 = nullptr;
     std::mutex curl_m;
     size_t bytes = 0;
     ~OperatorData() {
@@ -47,6 +48,7 @@ struct OperatorData {
         if (U64) (void)hipFree(U64);
         if (TK) (void)hipFree(TK);
         if (UK128) (void)hipFree(UK128);
+        if (UK64) (void)hipFree(UK64);
     }
 };
 
@@ -234,6 +236,11 @@ struct Ctx {
     bool has_contrast = false;
     Materials mat{};
     double* sigma = nullptr;   // [V]
+    // magnetic contrast of the J-M formulation (nc = 24): mu_r, chi_m, tau_m
+    // in the slots of eps_r, chi, tau; unset means mu_r = 1 everywhere
+    bool has_mcontrast = false;
+    Materials mmat{};
+    Scratch jmbuf;             // N x and K x of the J-M product
 
     Scratch ws;                // FFT intermediates
     Scratch small;             // reductions
@@ -252,6 +259,7 @@ struct Ctx {
     ~Ctx();
     void free_grid();
     void free_contrast();
+    void free_mcontrast();
 };
 
 // plan / twiddles (plan.cpp)
@@ -261,7 +269,8 @@ void make_twiddles(int n, std::vector<double2>& tw);
 
 // operator products (apply.cpp); OP_CURL: h = G^-1 (h_t + K x) with the
 // curl operator, h_t passed as rhs (complex128, PWL basis)
-enum { OP_PREC = 0, OP_A = 1, OP_N = 2, OP_RESID = 3, OP_CURL = 4 };
+// OP_K: y = K x, the raw curl product (the J-M product's coupling blocks)
+enum { OP_PREC = 0, OP_A = 1, OP_N = 2, OP_RESID = 3, OP_CURL = 4, OP_K = 5 };
 // ws_ext: caller-owned workspace of ws_cap bytes for the FFT intermediates
 // (VIE_EINVAL when the product needs more); nullptr: the context's own,
 // grown on demand
@@ -270,9 +279,29 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs,
               size_t ws_cap = 0);
 size_t apply_workspace_bytes(const Ctx& c, int nrhs, size_t es);
 
+// J-M formulation (nc = 24, jm.hip): the product from one N and one K
+// product over the 2 nrhs 12-component halves; OP_PREC, OP_A, OP_RESID
+template <typename R>
+void apply_jm(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs, void* ws_ext, size_t ws_cap);
+// P^-1 b of the J-M system from [e_t; h_t] (complex128, [nrhs][24][V])
+void jm_rhs_prec(Ctx& c, int nrhs, const double2* eh_t, double2* rhs);
+// mu_r = 1 everywhere (the default magnetic contrast of a J-M context)
+void jm_default_mcontrast(Ctx& c);
+// the component count, set for the lifetime of the guard (the J-M product
+// runs its halves as 12-component products)
+struct NcGuard {
+    Ctx& c;
+    int saved;
+    NcGuard(Ctx& c_, int nc) : c(c_), saved(c_.nc) { c.nc = nc; }
+    ~NcGuard() { c.nc = saved; }
+};
+
 // build the curl operator of the context's grid if it is not there yet
 // (magnetic.cpp); shared operators build it once
 void ensure_curl(Ctx& c);
+// tested incident magnetic field of a plane wave (12 components, one
+// right-hand side) into h_t (magnetic.cpp)
+void planewave_h(Ctx& c, const double pol[3], const double dir[3], double amp, double2* h_t);
 
 // fixed per-device workspace of vie_apply_noalloc (noalloc.hip): looked up
 // once per device by vie_create with that device current

@@ -34,8 +34,9 @@ void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStr
 // x pass of the PWC basis (3 component rows per pencil, compiled lengths only)
 template <typename R>
 void launch_p3_pwc(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s);
-// x pass of the curl operator K (complex128; U the [Oz][Oy][30][Ox] octant)
-void launch_p3_curl(double2* A, const double2* U, const P3Params& p, const double2* tw, hipStream_t s);
+// x pass of the curl operator K (U the [Oz][Oy][30][Ox] octant)
+template <typename R>
+void launch_p3_curl(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s);
 bool p3_ct_supported(int n);
 int p3_ct_groups(int es, int n);
 bool p3_ct_fits(int es, int n);

@@ -24,37 +24,33 @@ void ensure_curl(Ctx& c) {
     const long long V = c.V, Mt = (long long)c.M[0] * c.M[1] * c.M[2];
     double2* TK = nullptr;
     double2* UK = nullptr;
+    float2* UK64 = nullptr;
     try {
         VIE_HIP(hipMalloc(&TK, 30 * V * sizeof(double2)));
         VIE_HIP(hipMalloc(&UK, 30 * c.Osz * sizeof(double2)));
+        VIE_HIP(hipMalloc(&UK64, 30 * c.Osz * sizeof(float2)));
         AssemblyTables tab = build_curl_tables(c.D, c.k0);
         assemble_blocks(TK, tab, c.N[0], c.N[1], c.N[2], c.stream);
         double2* circ = static_cast<double2*>(c.ws.get(Mt * sizeof(double2)));
         const double2* tws[3] = {c.ax[0].tw128, c.ax[1].tw128, c.ax[2].tw128};
         FftPlan plans[3] = {c.ax[0].plan, c.ax[1].plan, c.ax[2].plan};
-        embed_and_transform(UK, nullptr, TK, circ, c.N[0], c.N[1], c.N[2], c.M[0], c.M[1], c.M[2], plans, tws,
+        embed_and_transform(UK, UK64, TK, circ, c.N[0], c.N[1], c.N[2], c.M[0], c.M[1], c.M[2], plans, tws,
                             c.stream, true);
         VIE_HIP(hipStreamSynchronize(c.stream));
     } catch (...) {
         if (TK) (void)hipFree(TK);
         if (UK) (void)hipFree(UK);
+        if (UK64) (void)hipFree(UK64);
         throw;
     }
     op.TK = TK;
     op.UK128 = UK;
-    op.bytes += 30 * (V + c.Osz) * sizeof(double2);
+    op.UK64 = UK64;
+    op.bytes += 30 * (V + c.Osz) * sizeof(double2) + 30 * c.Osz * sizeof(float2);
 }
 
-}  // namespace vie
-
-using namespace vie;
-
-namespace {
-
-void check(vie_ctx* ctx) { VIE_REQUIRE(ctx != nullptr, VIE_EINVAL, "null context"); }
-
 // axis of a signed unit vector along a coordinate axis, -1 otherwise
-int unit_axis(const double v[3], double* sign) {
+static int unit_axis(const double v[3], double* sign) {
     int ax = -1, nz = 0;
     for (int i = 0; i < 3; ++i)
         if (v[i] != 0.0) {
@@ -65,6 +61,26 @@ int unit_axis(const double v[3], double* sign) {
     *sign = v[ax] > 0 ? 1.0 : -1.0;
     return ax;
 }
+
+void planewave_h(Ctx& c, const double pol[3], const double dir[3], double amp, double2* h_t) {
+    double sp = 1, sd = 1;
+    const int pa = unit_axis(pol, &sp), da = unit_axis(dir, &sd);
+    VIE_REQUIRE(pa >= 0 && da >= 0 && pa != da, VIE_EINVAL,
+                "pol and dir must be distinct unit vectors along coordinate axes");
+    // H = (1 / eta0) dir x E: polarisation dir x pol along the third axis
+    const int ha = 3 - pa - da;
+    const double eta0 = std::sqrt(kMu0 / kEps0);
+    const double sh = sp * sd * levi(da, pa, ha);
+    launch_planewave(h_t, c.N[0], c.N[1], c.N[2], c.D, c.k0, ha, da, sd, amp * sh / eta0, 12, c.stream);
+}
+
+}  // namespace vie
+
+using namespace vie;
+
+namespace {
+
+void check(vie_ctx* ctx) { VIE_REQUIRE(ctx != nullptr, VIE_EINVAL, "null context"); }
 
 bool overlap(const void* a, const void* b, size_t n) {
     const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
@@ -81,17 +97,11 @@ int vie_incident_planewave_h(vie_ctx* ctx, const double pol[3], const double dir
         Ctx& c = ctx->c;
         VIE_HIP(hipSetDevice(c.device));
         VIE_REQUIRE(c.has_grid, VIE_ESTATE, "no grid");
+        VIE_REQUIRE(c.nc == 12, VIE_EINVAL,
+                    "the incident magnetic field is tested on the PWL basis (a J-M context's incident calls "
+                    "write both halves)");
         VIE_REQUIRE(pol && dir && h_t, VIE_EINVAL, "null argument");
-        double sp = 1, sd = 1;
-        const int pa = unit_axis(pol, &sp), da = unit_axis(dir, &sd);
-        VIE_REQUIRE(pa >= 0 && da >= 0 && pa != da, VIE_EINVAL,
-                    "pol and dir must be distinct unit vectors along coordinate axes");
-        // H = (1 / eta0) dir x E: polarisation dir x pol along the third axis
-        const int ha = 3 - pa - da;
-        const double eta0 = std::sqrt(kMu0 / kEps0);
-        const double sh = sp * sd * levi(da, pa, ha);
-        launch_planewave(static_cast<double2*>(h_t), c.N[0], c.N[1], c.N[2], c.D, c.k0, ha, da, sd,
-                         amp * sh / eta0, c.nc, c.stream);
+        planewave_h(c, pol, dir, amp, static_cast<double2*>(h_t));
     });
 }
 
@@ -101,6 +111,9 @@ int vie_incident_dipoles_h(vie_ctx* ctx, int nrhs, const double* pos, const doub
         Ctx& c = ctx->c;
         VIE_HIP(hipSetDevice(c.device));
         VIE_REQUIRE(c.has_grid, VIE_ESTATE, "no grid");
+        VIE_REQUIRE(c.nc == 12, VIE_EINVAL,
+                    "the incident magnetic field is tested on the PWL basis (a J-M context's incident calls "
+                    "write both halves)");
         VIE_REQUIRE(nrhs >= 1 && pos && moment && h_t, VIE_EINVAL, "bad dipole arguments");
         VIE_REQUIRE(nq >= 1 && nq <= kMaxGauss, VIE_EINVAL, "nq must be in 1..16");
         AssemblyTables tab = build_assembly_tables(c.D, c.k0);   // holds the Gauss tables

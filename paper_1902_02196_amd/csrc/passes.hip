@@ -1047,10 +1047,11 @@ void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStr
     VIE_HIP(hipGetLastError());
 }
 
-// x pass of the curl operator (complex128, the staged kernel for any length
-// whose rows fit; a post-processing product, not on the solver's path)
-void launch_p3_curl(double2* A, const double2* U, const P3Params& p, const double2* tw, hipStream_t s) {
-    using R = double;
+// x pass of the curl operator (the staged kernel for any length whose rows
+// fit): the magnetic field's product, and the coupling blocks of the J-M
+// product in both precisions
+template <typename R>
+void launch_p3_curl(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
     const int nt = p3_threads<R>();
     VIE_REQUIRE(rows_fit(p.plan, p.groups * 12, nt) && 2 * p.groups * p.plan.n <= nt, -1,
                 "magnetic product: fft length along x above 256");
@@ -1069,6 +1070,8 @@ void launch_p3_curl(double2* A, const double2* U, const P3Params& p, const doubl
     else timed_launch(k_p3<R, 2, true>, dim3(p.Oy * p.Oz), dim3(nt), (unsigned)lds, s, A, U, p, tw);
     VIE_HIP(hipGetLastError());
 }
+template void launch_p3_curl<float>(C<float>*, const C<float>*, const P3Params&, const C<float>*, hipStream_t);
+template void launch_p3_curl<double>(C<double>*, const C<double>*, const P3Params&, const C<double>*, hipStream_t);
 
 template <typename R>
 void launch_p3_pwc(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {

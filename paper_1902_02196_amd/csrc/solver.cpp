@@ -186,7 +186,8 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
             const std::vector<long long> key{(long long)sizeof(R), na, m, o.reorth, j0, j1, n,
                                              (long long)reinterpret_cast<uintptr_t>(Vb), ldv,
                                              (long long)reinterpret_cast<uintptr_t>(L.rhs),
-                                             (long long)reinterpret_cast<uintptr_t>(c.ws.p)};
+                                             (long long)reinterpret_cast<uintptr_t>(c.ws.p),
+                                             (long long)reinterpret_cast<uintptr_t>(c.jmbuf.p), c.nc};
             auto it = c.graphs.execs.find(key);
             if (it == c.graphs.execs.end()) {
                 for (int j = j0; j < j1; ++j) step(j);
@@ -318,7 +319,15 @@ int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2*
 
     const double dv = c.D[0] * c.D[1] * c.D[2];
     const double ginv[4] = {1 / dv, 12 / dv, 12 / dv, 12 / dv};
-    launch_rhs_prec(L.rhs, et, c.mat.tau, ginv, make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.nc, c.stream);
+    if (c.nc == 24) {
+        // J-M: the curl operator and the product's buffers exist before any
+        // Arnoldi step (which may be captured)
+        ensure_curl(c);
+        c.jmbuf.get((size_t)2 * nrhs * 24 * c.V * sizeof(double2));
+        jm_rhs_prec(c, nrhs, et, L.rhs);
+    } else {
+        launch_rhs_prec(L.rhs, et, c.mat.tau, ginv, make_double2(0.0, c.omega * kEps0), c.V, nrhs, c.nc, c.stream);
+    }
     std::vector<double> bnorm;
     norms<double>(c, L.rhs, n, nrhs, L.npart, L.bn, bnorm);
     for (int r = 0; r < nrhs; ++r)

@@ -1,0 +1,239 @@
+"""The J-M formulation with magnetic contrast (Sec. II eq. 13-15) on the
+GPU against the oracle (``oracle/jm.py``), through the C ABI:
+
+* P^-1 A x and A x on ragged grids with random eps_r and mu_r, complex128
+  and complex64, against the oracle's direct sums of its N and K blocks;
+* the incident [e_t; h_t] of a plane wave and the right-hand side;
+* solves in both modes against the oracle's dense LU;
+* without a magnetic contrast the magnetic half stays zero and the
+  electric half is the dielectric solve;
+* a magneto-dielectric sphere: the device's solution and absorbed power
+  against the oracle's FFT-GMRES, and the power against the Mie series of
+  the permeable sphere;
+* refusals.
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import vie_inputs as vi
+from oracle import incident, jm, magnetic, matvec, mie, physics, toeplitz
+from tests.layout import relerr, vox_to_lib
+
+pytestmark = pytest.mark.gpu
+
+F = 298e6
+K = physics.k0(F)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def vie(torch):
+    import paper_1902_02196_amd as v
+    return v
+
+
+@functools.lru_cache(None)
+def _blocks(N, D, k0=K):
+    return toeplitz.toeplitz_full(N, D, k0), toeplitz.toeplitz_full(N, D, k0, part='K')
+
+
+def _to_lib(x):      # [R, 24, Nx, Ny, Nz] -> [R, 24, Nz, Ny, Nx]
+    return np.ascontiguousarray(np.asarray(x).transpose(0, 1, 4, 3, 2))
+
+
+def _from_lib(x):
+    return np.ascontiguousarray(np.asarray(x).transpose(0, 1, 4, 3, 2))
+
+
+def _random_materials(N, seed):
+    rng = np.random.default_rng(seed)
+    e = rng.uniform(2.0, 60.0, N)
+    s = rng.uniform(0.0, 1.5, N)
+    mre = rng.uniform(1.0, 4.0, N)
+    mim = rng.uniform(0.0, 1.0, N)
+    air = rng.uniform(0, 1, N) < 0.2
+    e[air], s[air], mre[air], mim[air] = 1.0, 0.0, 1.0, 0.0
+    return e, s, mre, mim
+
+
+def _jm_ctx(vie, N, D, e, s, mre=None, mim=None):
+    c = vie.Context(0)
+    c.set_basis(24)
+    c.set_grid(N, D, F)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    if mre is not None:
+        c.set_magnetic_contrast(vox_to_lib(mre), vox_to_lib(mim))
+    return c
+
+
+def _oracle_materials(e, s, mre, mim):
+    er = physics.eps_r(e, s, F)
+    mr = physics.mu_r(mre, mim)
+    return er, er - 1, mr, mr - 1, (er - 1) / er, (mr - 1) / mr
+
+
+@pytest.mark.parametrize("N,D", [((5, 4, 6), (0.005, 0.004, 0.006)), ((3, 5, 2), (0.004, 0.006, 0.005))])
+def test_jm_products_match_oracle(vie, torch, N, D):
+    _say("J-M products %s" % (N,))
+    TN, TK = _blocks(N, D)
+    e, s, mre, mim = _random_materials(N, 21)
+    er, chie, mr, chim, taue, taum = _oracle_materials(e, s, mre, mim)
+    c = _jm_ctx(vie, N, D, e, s, mre, mim)
+    xs = np.stack([vi.complex_normal(30 + r, (24,) + N) for r in range(2)])
+    ref = {vie.OP_PREC: [jm.apply_prec(TN, TK, x, taue, taum, D, F) for x in xs],
+           vie.OP_A: [jm.apply_A(TN, TK, x, er, chie, mr, chim, D, F) for x in xs]}
+    for dtype, tol in ((torch.complex128, 1e-9), (torch.complex64, 2e-5)):
+        xd = torch.from_numpy(_to_lib(xs)).to("cuda", dtype)
+        for op in (vie.OP_PREC, vie.OP_A):
+            y = torch.empty_like(xd)
+            c.apply(xd, y, op=op)
+            yh = _from_lib(y.cpu().numpy().astype(np.complex128))
+            for r in range(2):
+                err = relerr(yh[r], ref[op][r])
+                _say("  %s op %d rhs %d: %.2e" % (dtype, op, r, err))
+                assert err < tol
+
+
+def test_jm_incident_and_rhs(vie, torch):
+    N, D = (4, 3, 5), (0.005, 0.004, 0.006)
+    e, s, mre, mim = _random_materials(N, 22)
+    er, chie, mr, chim, taue, taum = _oracle_materials(e, s, mre, mim)
+    c = _jm_ctx(vie, N, D, e, s, mre, mim)
+    et = torch.empty(c.vec_shape(1), dtype=torch.complex128, device="cuda")
+    c.incident_planewave(et)
+    eh = np.concatenate([incident.planewave_tested(N, D, K), magnetic.planewave_h_tested(N, D, K)])
+    assert relerr(_from_lib(et.cpu().numpy())[0], eh) < 1e-12
+    b = torch.empty_like(et)
+    c.rhs_prec(et, b)
+    bref = jm.rhs_prec(eh[:12], eh[12:], taue, taum, D, F)
+    assert relerr(_from_lib(b.cpu().numpy())[0], bref) < 1e-12
+
+
+@pytest.mark.parametrize("mode,tol,bound", [(0, 1e-12, 1e-9), (1, 1e-10, 1e-7)])
+def test_jm_solve_matches_dense(vie, torch, mode, tol, bound):
+    N, D = (3, 3, 2), (0.005, 0.006, 0.004)
+    TN, TK = _blocks(N, D)
+    e, s, mre, mim = _random_materials(N, 23)
+    er, chie, mr, chim, taue, taum = _oracle_materials(e, s, mre, mim)
+    eh = np.concatenate([incident.planewave_tested(N, D, K), magnetic.planewave_h_tested(N, D, K)])
+    xref = jm.solve_dense(TN, TK, taue, taum, D, F, jm.rhs_prec(eh[:12], eh[12:], taue, taum, D, F))
+    c = _jm_ctx(vie, N, D, e, s, mre, mim)
+    et = torch.empty(c.vec_shape(1), dtype=torch.complex128, device="cuda")
+    c.incident_planewave(et)
+    x = torch.empty_like(et)
+    code, st = c.solve(et, x, mode=mode, tol=tol, restart=30)
+    _say("  J-M solve mode %d: %s" % (mode, st[0]))
+    assert code == vie.VIE_OK
+    err = relerr(_from_lib(x.cpu().numpy())[0], xref)
+    _say("  vs dense LU %.2e" % err)
+    assert err < bound
+    P = c.absorbed_power(x)[0]
+    Pref = jm.absorbed_power(xref, chie, chim, D, F)
+    assert abs(P - Pref) / abs(Pref) < 10 * bound
+
+
+def test_jm_without_magnetic_contrast_is_dielectric(vie, torch):
+    """A J-M context without vie_set_magnetic_contrast (mu_r = 1): the
+    magnetic half of the solution is exactly zero and the electric half is
+    the dielectric solve."""
+    N, D = (6, 5, 4), (0.005, 0.006, 0.005)
+    e, s = vi.ellipsoid_phantom(N, D, 71)
+    c = _jm_ctx(vie, N, D, e, s)
+    et = torch.empty(c.vec_shape(1), dtype=torch.complex128, device="cuda")
+    c.incident_planewave(et)
+    x = torch.empty_like(et)
+    code, st = c.solve(et, x, mode=0, tol=1e-11, restart=30)
+    assert code == vie.VIE_OK
+    d = vie.Context(0)
+    d.set_grid(N, D, F)
+    d.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    ed = torch.empty(d.vec_shape(1), dtype=torch.complex128, device="cuda")
+    d.incident_planewave(ed)
+    xd = torch.empty_like(ed)
+    code, _ = d.solve(ed, xd, mode=0, tol=1e-11, restart=30)
+    assert code == vie.VIE_OK
+    xh = x.cpu().numpy()[0]
+    assert not np.any(xh[12:])
+    assert relerr(xh[:12], xd.cpu().numpy()[0]) < 1e-8
+
+
+def test_jm_magnetodielectric_sphere(vie, torch):
+    """Sphere (r = 2.5 cm, eps' 50, sigma 0.7, mu_r 2 - 0.5 i) on 10^3 voxels
+    of 6 mm: the device solve (both modes) against the oracle's FFT-GMRES
+    element by element, and its absorbed power against the oracle's and the
+    Mie series of the volume-equivalent permeable sphere."""
+    N, h = (10, 10, 10), 0.006
+    D = (h,) * 3
+    TN, TK = _blocks(N, D)
+    M = tuple(2 * n for n in N)
+    CN, CK = matvec.circulant_spectrum(TN, M), matvec.circulant_spectrum(TK, M)
+    e, s = vi.sphere(N, D, 0.025, 50.0, 0.7)
+    inside = e != 1.0
+    mu_in = 2.0 - 0.5j
+    mre = np.where(inside, mu_in.real, 1.0)
+    mim = np.where(inside, -mu_in.imag, 0.0)
+    er, chie, mr, chim, taue, taum = _oracle_materials(e, s, mre, mim)
+    eh = np.concatenate([incident.planewave_tested(N, D, K), magnetic.planewave_h_tested(N, D, K)])
+    from oracle import solve
+    xref, info = solve.gmres(lambda v: jm.apply_prec(CN, CK, v, taue, taum, D, F, Nx_fn=matvec.fft_N,
+                                                     Kx_fn=matvec.fft_N),
+                             jm.rhs_prec(eh[:12], eh[12:], taue, taum, D, F), restart=50, tol=1e-11)
+    assert info["converged"]
+    Pref = jm.absorbed_power(xref, chie, chim, D, F)
+    req = (inside.sum() * h ** 3 * 3 / (4 * np.pi)) ** (1 / 3)
+    Pm = mie.absorbed_power_magnetic(req, er[inside][0], mu_in, F)
+    c = _jm_ctx(vie, N, D, e, s, mre, mim)
+    et = torch.empty(c.vec_shape(1), dtype=torch.complex128, device="cuda")
+    c.incident_planewave(et)
+    for mode in (0, 1):
+        x = torch.empty_like(et)
+        code, st = c.solve(et, x, mode=mode, tol=1e-10)
+        assert code == vie.VIE_OK
+        err = relerr(_from_lib(x.cpu().numpy())[0], xref)
+        P = c.absorbed_power(x)[0]
+        _say("  sphere mode %d: %d iterations, vs oracle %.2e, P %.4e (oracle %.4e, Mie %.4e: %.2f%%)" % (
+            mode, st[0]["iterations"], err, P, Pref, Pm, 100 * abs(P - Pm) / Pm))
+        assert err < 1e-8
+        assert abs(P - Pref) / Pref < 1e-8
+        assert abs(P - Pm) / Pm < 0.05
+    f = torch.empty_like(x)
+    c.fields(x, f)
+    fh = _from_lib(f.cpu().numpy())[0]
+    assert relerr(fh, jm.fields(_from_lib(x.cpu().numpy())[0], chie, chim, F)) < 1e-12
+
+
+def test_jm_refusals(vie, torch):
+    N, D = (4, 4, 4), (0.005,) * 3
+    e, s = vi.sphere(N, D, 0.008, 40.0, 0.5)
+    plain = vie.Context(0)
+    plain.set_grid(N, D, F)
+    with pytest.raises(vie.VieError):
+        plain.set_magnetic_contrast(vox_to_lib(np.ones(N)), vox_to_lib(np.zeros(N)))   # not J-M
+    c = _jm_ctx(vie, N, D, e, s)
+    with pytest.raises(vie.VieError):
+        c.set_magnetic_contrast(vox_to_lib(np.zeros(N)), vox_to_lib(np.zeros(N)))      # mu' <= 0
+    with pytest.raises(vie.VieError):
+        c.set_magnetic_contrast(vox_to_lib(np.ones(N)), vox_to_lib(-np.ones(N)))       # mu'' < 0
+    x = torch.zeros(c.vec_shape(1), dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    with pytest.raises(vie.VieError):
+        c.apply(x, y, op=vie.OP_N)
+    with pytest.raises(vie.VieError):
+        c.total_field(x, x.clone(), y)
+    with pytest.raises(vie.VieError):
+        c.incident_planewave_h(y)
