@@ -82,6 +82,9 @@ WORKLOADS = {
     # the same body with the PWC basis the paper compares against (3 unknowns
     # per voxel)
     "phantom64_pwc": dict(N=(64, 64, 64), h=0.003, f=298e6, seed=190202196 + 1, basis=3),
+    # the same body with a per-class permeability, J-M formulation (24
+    # unknowns per voxel)
+    "phantom64_jm": dict(N=(64, 64, 64), h=0.003, f=298e6, seed=190202196 + 1, basis=24),
     "sphere16": dict(N=(16, 16, 16), h=0.005, f=298e6, seed=None),
     # head-sized box, 16 Hertzian dipoles on a 15 cm cylinder, one batched solve
     "batched16": dict(N=(96, 128, 128), h=0.002, f=298e6, seed=190202196 + 3, nrhs=16, cyl=0.15,
@@ -120,20 +123,28 @@ def cpu_baseline(N, h, f, iters, restarts, seconds_budget=20.0, nc=12):
     the FP64 GPU solve's Arnoldi steps plus one residual product per restart
     cycle.  The oracle's block assembly is not included (random blocks and
     contrast of the right shapes: values do not change the time)."""
-    from oracle import matvec, pwc, solve
+    from oracle import jm, matvec, pwc, solve
     import vie_inputs as vi
     cores = min(CPU_SHARE, os.cpu_count() or 1)
     Nx, Ny, Nz = N
-    T = vi.complex_normal(5, (nc, nc, 2 * Nx - 1, 2 * Ny - 1, 2 * Nz - 1))
+    nb = 3 if nc == 3 else 12
     M = (2 * Nx, 2 * Ny, 2 * Nz)
     t0 = time.perf_counter()
-    Ch = matvec.circulant_spectrum(T, M, workers=cores) if nc == 12 else pwc.spectrum(T, M, workers=cores)
+    T = vi.complex_normal(5, (nb, nb, 2 * Nx - 1, 2 * Ny - 1, 2 * Nz - 1))
+    Ch = matvec.circulant_spectrum(T, M, workers=cores) if nb == 12 else pwc.spectrum(T, M, workers=cores)
     del T
+    if nc == 24:   # the J-M product also needs the curl operator's spectrum
+        T = vi.complex_normal(8, (12, 12, 2 * Nx - 1, 2 * Ny - 1, 2 * Nz - 1))
+        CK = matvec.circulant_spectrum(T, M, workers=cores)
+        del T
     t_setup = time.perf_counter() - t0
-    fft_N = matvec.fft_N if nc == 12 else pwc.fft_N
+    fft_N = matvec.fft_N if nb == 12 else pwc.fft_N
     tau = 0.1 * vi.complex_normal(7, tuple(N))
     D = (h, h, h)
-    if nc == 12:
+    if nc == 24:
+        fftw = lambda C_, u: matvec.fft_N(C_, u, workers=cores)
+        op = lambda v: jm.apply_prec(Ch, CK, v, tau, tau, D, f, Nx_fn=fftw, Kx_fn=fftw)
+    elif nc == 12:
         op = lambda v: matvec.apply_prec(None, v, tau, D, Nx_fn=lambda _t, u: fft_N(Ch, u, workers=cores))
     else:
         op = lambda v: pwc.apply_prec(None, v, tau, D, Nx_fn=lambda _t, u: fft_N(Ch, u, workers=cores))
@@ -331,13 +342,20 @@ def main():
     tune128 = ctx.autotune(vie.C128, 1)
     t_tune = time.perf_counter() - t0
     log("autotune %.2f s: c64 %s, c128 %s" % (t_tune, tune64, tune128))
+    mu = None
     if W["seed"] is None:
         e, s = vi.sphere(N, D, 0.03, 50.0, 0.7)
     elif W.get("layered"):
         e, s = vi.layered_phantom(N, D, W["seed"])
+    elif nc == 24:
+        e, s, mre, mim = vi.magnetic_phantom(N, D, W["seed"])
+        mu = (mre, mim)
     else:
         e, s = vi.ellipsoid_phantom(N, D, W["seed"])
     ctx.set_contrast(np.ascontiguousarray(e.transpose(2, 1, 0)), np.ascontiguousarray(s.transpose(2, 1, 0)))
+    if mu is not None:
+        ctx.set_magnetic_contrast(np.ascontiguousarray(mu[0].transpose(2, 1, 0)),
+                                  np.ascontiguousarray(mu[1].transpose(2, 1, 0)))
     nrhs = W.get("nrhs", 1)
     et = torch.empty(ctx.vec_shape(nrhs), dtype=torch.complex128, device=dev)
     if nrhs == 1:
@@ -469,7 +487,7 @@ def main():
     P_64 = ctx.absorbed_power(x64)
     # field difference in the Gram-weighted norm (the L2 norm of the field
     # over the body: weight 1 for the pulse coefficients, 1/12 for the linear)
-    gw = torch.tensor([1.0, 1 / 12, 1 / 12, 1 / 12] * (nc // 4) if nc == 12 else [1.0] * nc,
+    gw = torch.tensor([1.0, 1 / 12, 1 / 12, 1 / 12] * (nc // 4) if nc in (12, 24) else [1.0] * nc,
                       dtype=torch.float64, device=dev).view(nc, 1, 1, 1)
     field_err = max(float(torch.sqrt((gw * (e_ir[r] - e_64[r]).abs() ** 2).sum() / (gw * e_64[r].abs() ** 2).sum()))
                     for r in range(n64))
@@ -520,7 +538,9 @@ def main():
                 "launches_timed": nl, "avg_launch_us": round(avg_s * 1e6, 2), "bytes_per_launch": by / nl,
                 "timed_in": "the timed solves" if every else "one more solve after the timed region"}
     if dom == "block":
-        fl = block_flops(ctx.fft_size, group, nc)
+        # a J-M x-pass launch is an N or a K pass over the 2 nrhs
+        # 12-component halves
+        fl = block_flops(ctx.fft_size, 2 * group, 12) if nc == 24 else block_flops(ctx.fft_size, group, nc)
         achieved = fl / avg_s / 1e12
         t_hbm, t_alu = (by / nl) / (HBM_PEAK_GBS * 1e9), fl / (FP32_VECTOR_PEAK_TFLOPS * 1e12)
         if t_alu > t_hbm:   # flops bind at the published peaks
@@ -556,7 +576,9 @@ def main():
                                   ("10-class layered phantom" if W.get("layered") else "6-class ellipsoid phantom")
                                   if W["seed"] else "eps 50 sigma 0.7 sphere r=3 cm",
                                   excitation, args.restart,
-                                  "PWL (12 unknowns per voxel)" if nc == 12 else "PWC (3 unknowns per voxel)"),
+                                  {12: "PWL (12 unknowns per voxel)", 3: "PWC (3 unknowns per voxel)",
+                                   24: "PWL J-M formulation with a per-class permeability (24 unknowns per "
+                                       "voxel)"}[nc]),
                    "nrhs": nrhs},
         "fp64_solves_per_s": round(n64 / t_64, 4),
         "fp64_rhs": n64,

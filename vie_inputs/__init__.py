@@ -20,6 +20,9 @@ which are not available):
 * ``layered_phantom``: body ellipsoid with semi-axes (0.40, 0.40, 0.45) L and
   n equal-thickness ellipsoidal shells as classes; eps' ~ U[5, 80],
   sigma ~ U[0.02, 2] S/m.
+* ``magnetic_phantom``: the ellipsoid phantom with a per-class permeability
+  mu' ~ U[1, 3], mu'' ~ U[0, 0.5] (the J-M formulation's workload; tissue
+  is non-magnetic, so this stands in for magnetically loaded materials).
 * ``dipoles_on_cylinder``: z-directed unit dipoles (1 A m) at angle U[0, 2 pi)
   and height U[-0.4, 0.4] L_z on a cylinder about the z axis.
 """
@@ -72,6 +75,37 @@ def ellipsoid_phantom(N, Delta, seed, n_classes=6, n_blobs=16,
     e = np.where(cls >= 0, eps_c[np.maximum(cls, 0)], 1.0)
     s = np.where(cls >= 0, sig_c[np.maximum(cls, 0)], 0.0)
     return e, s
+
+
+def magnetic_phantom(N, Delta, seed, mu_range=(1.0, 3.0), mu_loss_range=(0.0, 0.5), **kw):
+    """The ellipsoid phantom of the same seed (identical eps', sigma) with a
+    permeability per class drawn after it: mu' ~ U[1, 3], mu'' ~ U[0, 0.5]
+    in the body, (1, 0) in air.  Returns (eps', sigma, mu', mu'')."""
+    n_classes = kw.get("n_classes", 6)
+    e, s = ellipsoid_phantom(N, Delta, seed, **kw)
+    # replay the class map: the same draws in the same order
+    g = rng(seed)
+    g.uniform(0, 1, size=n_classes)
+    g.uniform(0, 1, size=n_classes)
+    L = np.array([N[i] * Delta[i] for i in range(3)])
+    X, Y, Z = _grid(N, Delta)
+    ax = 0.45 * L
+    body = (X / ax[0]) ** 2 + (Y / ax[1]) ** 2 + (Z / ax[2]) ** 2 <= 1.0
+    cls = np.where(body, 0, -1)
+    for _ in range(kw.get("n_blobs", 16)):
+        while True:
+            c = g.uniform(-ax, ax)
+            if np.sum((c / ax) ** 2) <= 1.0:
+                break
+        semi = g.uniform(0.08, 0.30, size=3) * L.min()
+        k = int(g.integers(1, n_classes))
+        blob = ((X - c[0]) / semi[0]) ** 2 + ((Y - c[1]) / semi[1]) ** 2 + ((Z - c[2]) / semi[2]) ** 2 <= 1.0
+        cls = np.where(blob & body, k, cls)
+    mu_c = g.uniform(*mu_range, size=n_classes)
+    mul_c = g.uniform(*mu_loss_range, size=n_classes)
+    mre = np.where(cls >= 0, mu_c[np.maximum(cls, 0)], 1.0)
+    mim = np.where(cls >= 0, mul_c[np.maximum(cls, 0)], 0.0)
+    return e, s, mre, mim
 
 
 def layered_phantom(N, Delta, seed, n_classes=10, eps_range=(5.0, 80.0), sigma_range=(0.02, 2.0)):
