@@ -690,52 +690,64 @@ __global__ void __launch_bounds__(kP3QuadThreads) k_p3_quad(C<R>* __restrict__ A
     ct_passes<R, true, N, 0, 1, NT, 48, true>(buf, twl, nrows, N, tid);   // Nx <= N / 2
     {
         const C<R>* Ur = U + (long long)row * 60 * OX;
+        // Fold signs: sibling (sy, sz) and the upper half of the x range
+        // (fx) read the octant value of the mirrored frequency, D T D with
+        // D = diag(+-1), applied to x and y as a flip of the sign bit.  When
+        // N is a multiple of 128 a wave's 64 frequencies lie in one half of
+        // the x range (with the Nyquist column counted in the upper half,
+        // where the block is invariant under the x fold) and in one z
+        // sibling, so the masks are wave-uniform scalars and each flip is a
+        // single XOR with a scalar operand.
+        constexpr bool UNIFORM = N % 128 == 0 && NT % 64 == 0;
+        constexpr unsigned MX = fold_mask(1, 0, 0), MY = fold_mask(0, 1, 0), MZ = fold_mask(0, 0, 1);
         for (int w = tid; w < nz_sib * N; w += NT) {
-            const int sz = w >= N, xi = w - sz * N;
-            const int fx = 2 * xi > N;
+            int sz = w >= N;
+            const int xi = w - sz * N;
+            int fx = UNIFORM ? (2 * xi >= N) : (2 * xi > N);
+            if constexpr (UNIFORM) {
+                sz = __builtin_amdgcn_readfirstlane(sz);
+                fx = __builtin_amdgcn_readfirstlane(fx);
+            }
             const int ox = fx ? N - xi : xi;
             const int s0 = sz * ny_sib;
+            const unsigned m0 = (fx ? MX : 0u) ^ (sz ? MZ : 0u);
+            auto flip = [](C<R> v, unsigned m, int a) {
+                if constexpr (sizeof(R) == 4) {
+                    const unsigned f = ((m >> a) & 1u) << 31;
+                    v.x = __uint_as_float(__float_as_uint(v.x) ^ f);
+                    v.y = __uint_as_float(__float_as_uint(v.y) ^ f);
+                } else if ((m >> a) & 1u) {
+                    v.x = -v.x;
+                    v.y = -v.y;
+                }
+                return v;
+            };
             if (ny_sib == 2) {
-                const unsigned m0 = fold_mask(fx, 0, sz), m1 = fold_mask(fx, 1, sz);
+                const unsigned m1 = m0 ^ MY;
                 C<R> x0[12], x1[12], y0[12], y1[12];
 #pragma unroll
                 for (int a = 0; a < 12; ++a) {
-                    C<R> v = buf[lds_pad((s0 * 12 + a) * N + xi)];
-                    if (m0 & (1u << a)) { v.x = -v.x; v.y = -v.y; }
-                    x0[a] = v;
-                    v = buf[lds_pad(((s0 + 1) * 12 + a) * N + xi)];
-                    if (m1 & (1u << a)) { v.x = -v.x; v.y = -v.y; }
-                    x1[a] = v;
+                    x0[a] = flip(buf[lds_pad((s0 * 12 + a) * N + xi)], m0, a);
+                    x1[a] = flip(buf[lds_pad(((s0 + 1) * 12 + a) * N + xi)], m1, a);
                     y0[a] = mk<R>(0, 0);
                     y1[a] = mk<R>(0, 0);
                 }
                 orbit_product2<R, 0>(y0, y1, x0, x1, Ur, ox, OX);
 #pragma unroll
                 for (int a = 0; a < 12; ++a) {
-                    C<R> v = y0[a];
-                    if (m0 & (1u << a)) { v.x = -v.x; v.y = -v.y; }
-                    buf[lds_pad((s0 * 12 + a) * N + xi)] = v;
-                    v = y1[a];
-                    if (m1 & (1u << a)) { v.x = -v.x; v.y = -v.y; }
-                    buf[lds_pad(((s0 + 1) * 12 + a) * N + xi)] = v;
+                    buf[lds_pad((s0 * 12 + a) * N + xi)] = flip(y0[a], m0, a);
+                    buf[lds_pad(((s0 + 1) * 12 + a) * N + xi)] = flip(y1[a], m1, a);
                 }
             } else {
-                const unsigned m0 = fold_mask(fx, 0, sz);
                 C<R> x0[12], y0[12];
 #pragma unroll
                 for (int a = 0; a < 12; ++a) {
-                    C<R> v = buf[lds_pad((s0 * 12 + a) * N + xi)];
-                    if (m0 & (1u << a)) { v.x = -v.x; v.y = -v.y; }
-                    x0[a] = v;
+                    x0[a] = flip(buf[lds_pad((s0 * 12 + a) * N + xi)], m0, a);
                     y0[a] = mk<R>(0, 0);
                 }
                 orbit_product<R, 0>(y0, x0, Ur, ox, OX);
 #pragma unroll
-                for (int a = 0; a < 12; ++a) {
-                    C<R> v = y0[a];
-                    if (m0 & (1u << a)) { v.x = -v.x; v.y = -v.y; }
-                    buf[lds_pad((s0 * 12 + a) * N + xi)] = v;
-                }
+                for (int a = 0; a < 12; ++a) buf[lds_pad((s0 * 12 + a) * N + xi)] = flip(y0[a], m0, a);
             }
         }
     }
