@@ -278,6 +278,8 @@ def main():
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0, help="serving: admission budget")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--reorth", type=int, default=0, help="second Gram-Schmidt pass (1) or not (0)")
+    ap.add_argument("--s-step", type=int, default=0,
+                    help="Arnoldi steps per pass over the basis: 1 or 2 (0: the library's choice)")
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--graph", type=int, default=-1,
                     help="replay the Arnoldi steps from HIP graphs (1), not (0), or when the vectors are small (-1)")
@@ -423,9 +425,10 @@ def main():
     log("setup: grid+operator %.2f s" % t_grid)
 
     opts_ir = vie.default_opts(mode=vie.SOLVE_FP32_IR, tol=1e-6, restart=args.restart, inner_tol=1e-5,
-                               reorth=args.reorth, graph=args.graph, sync_steps=args.sync_steps)
+                               reorth=args.reorth, graph=args.graph, sync_steps=args.sync_steps,
+                               s_step=args.s_step)
     opts_64 = vie.default_opts(mode=vie.SOLVE_FP64, tol=1e-6, restart=args.restart, reorth=args.reorth,
-                               graph=args.graph, sync_steps=args.sync_steps)
+                               graph=args.graph, sync_steps=args.sync_steps, s_step=args.s_step)
     for i in range(args.warmup):
         code, st = solve_all(opts_ir)
         log("warmup %d: %s" % (i, st[0]))
@@ -451,7 +454,8 @@ def main():
         # the kernel classes timed in one more solve, launched one by one
         ctx.profile(True, every=PROFILE_EVERY)
         solve_all(vie.default_opts(mode=vie.SOLVE_FP32_IR, tol=1e-6, restart=args.restart, inner_tol=1e-5,
-                                   reorth=args.reorth, graph=0, sync_steps=args.sync_steps))
+                                   reorth=args.reorth, graph=0, sync_steps=args.sync_steps,
+                                   s_step=args.s_step))
         torch.cuda.synchronize()
         prof = ctx.profile_read()
         ctx.profile(False)
@@ -593,7 +597,8 @@ def main():
         "matvec_c64_GBps_algorithmic": round(mv_bytes / (mv_dev_ms * 1e-3) / 1e9, 1),
         "setup_s": round(t_grid, 3),
         "autotune": {"c64": tune64[0], "c128": tune128[0], "seconds": round(t_tune, 2)},
-        "solver": {"graph": args.graph, "sync_steps": args.sync_steps, "profile_every": every},
+        "solver": {"graph": args.graph, "sync_steps": args.sync_steps, "s_step": args.s_step,
+                   "profile_every": every},
         "tucker": tucker,
         "kernel_source_hash": kernel_source_hash(),
         "kernels": kernels,

@@ -93,6 +93,18 @@ typedef struct {
                             from the vector size.  Larger values cost fewer
                             host round trips and up to 2 sync_steps - 1
                             steps computed past convergence                   */
+    int s_step;          /* Arnoldi steps per pass over the basis: 1, the
+                            classical step (one product, then Gram-Schmidt
+                            against the basis); 2, two products, then one
+                            dot and one update pass over the basis for both
+                            (s-step Arnoldi with s = 2, the second vector
+                            shifted by the Rayleigh quotient h_jj), which
+                            halves the basis reads per step; 0 (default): 2
+                            when a batch of vectors exceeds 2 MB (below, the
+                            pair's extra small kernels cost more than the
+                            halved reads), else 1.  reorth = 1 always runs
+                            single steps.  The iterates of 1 and 2 agree to
+                            rounding, not bitwise                             */
 } vie_solve_opts;
 
 typedef struct {

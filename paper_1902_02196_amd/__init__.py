@@ -40,7 +40,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 class SolveOpts(ctypes.Structure):
     _fields_ = [("mode", _i), ("restart", _i), ("max_outer", _i), ("tol", _d), ("inner_tol", _d),
                 ("max_refine", _i), ("reorth", _i), ("use_x0", _i),
-                ("graph", _i), ("sync_steps", _i)]
+                ("graph", _i), ("sync_steps", _i), ("s_step", _i)]
 
 
 class SolveStats(ctypes.Structure):

@@ -135,6 +135,7 @@ struct ArnoldiState {
     int* status;           // [0] columns folded in, [1] every slot has met its
                            // target, [2] a non-finite estimate was seen
     int m;
+    double2* Hr;           // [na][m][m + 1]: the unrotated columns (or nullptr)
 };
 // zero the status, g_0 = ||r||, ivn of the first basis vector = 1
 void launch_arnoldi_init(ArnoldiState st, double* ivn, long long ivn_ld, int na, hipStream_t s);
@@ -145,6 +146,33 @@ void launch_arnoldi_init(ArnoldiState st, double* ivn, long long ivn_ld, int na,
 // are left alone once status[1] or status[2] is set
 void launch_givens(ArnoldiState st, const double2* h1, const double2* h2, const double* npart, int nblocks,
                    double* nrm, double* ivn_next, long long ivn_ld, int j, int na, hipStream_t s);
+// Two Arnoldi steps per pass over the basis (s-step Arnoldi with s = 2, the
+// second vector shifted by the Rayleigh quotient h_jj; krylov.hip states the
+// algebra).  Dot partials of V against w and w + ldw: 2 planes of
+// [nrhs][nvec][nblocks].
+template <typename R>
+void launch_multidot2(double2* partial, const C<R>* Vb, long long ldv, int nvec, const C<R>* w, long long ldw,
+                      long long n, long long rstride_v, long long rstride_w, int nrhs, int nblocks, hipStream_t s);
+// h (column j above the diagonal), g (= V^H (A - h_jj) w1) and the update
+// coefficients of both from the 2 planes (w1 = A u_jw)
+void launch_reduce_pair(double2* h, double2* coef, double2* gcol, double2* coef2, const double2* partial, int nvec,
+                        int nblocks, int nrhs, const double* ivn, long long ivn_ld, int jw, hipStream_t s);
+// both updates in one pass over the basis (w2 = w + ldv), with the partial
+// sums of ||w1||^2 and conj(w1) w2
+template <typename R>
+void launch_update_pair(C<R>* w, const C<R>* Vb, long long ldv, int nvec, const double2* coef, const double2* coef2,
+                        const double2* h, long long n, long long rstride_v, long long rstride_w, double* norm_partial,
+                        double2* dot_partial, const double* ivn, long long ivn_ld, int jw, int nrhs, int nblocks,
+                        hipStream_t s);
+// pc[2 s] = conj(w1) w2 / ||w1||^2, pc[2 s + 1] = (1 / ||w1||, ||w1||)
+void launch_pair_coef(double2* pc, const double2* dpart, int nblocks, const double* nrm, int nrhs, hipStream_t s);
+// u_{j+2} = (w2 - pc0 u_{j+1}) pc1 in place, with its norm partials
+template <typename R>
+void launch_axpy_pair(C<R>* u1, long long ldv, long long n, long long rstride, const double2* pc,
+                      double* norm_partial, int nrhs, int nblocks, hipStream_t s);
+// Hessenberg column j + 1 of the pair, entries 0..j + 1, into col [na][j + 2]
+void launch_pair_column(ArnoldiState st, const double2* h, const double2* gcol, const double2* pc, double2* col,
+                        int j, int na, hipStream_t s);
 // y = R^-1 g over the first nvec columns, scaled by the basis vectors'
 // reciprocal norms (the coefficients of the stored vectors), y [na][nvec]
 void launch_backsolve(ArnoldiState st, const double* ivn, long long ivn_ld, double2* y, int nvec, int na,

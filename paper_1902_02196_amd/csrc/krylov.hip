@@ -55,24 +55,29 @@ static bool pair_units(const void* a, const void* b, long long n, long long s1, 
     return ((n | s1 | s2 | s3) & 1) == 0 && ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0;
 }
 
-// One group of G basis vectors (G compile-time, so that the G + 1 loads of an
-// element are issued together with no guard between them): FP64 sums of
-// conj(V_i) w over this thread's elements, reduced over the workgroup and
-// written to partial[(r * nvec + i) * nblocks + block].
-template <typename R, bool PAIR, int G>
+// One group of G basis vectors (G compile-time, so that the G + NW loads of an
+// element are issued together) against NW vectors w_q = wr + q ldwu: partial
+// sums of conj(V_i) w_q over this thread's elements, reduced over the
+// workgroup and written to partial[((q nrhs + r) nvec + i) nblocks + block].
+template <typename R, bool PAIR, int G, int NW>
 __device__ __forceinline__ void dot_group(double2* __restrict__ partial,
                                           const typename Unit<R, PAIR>::T* __restrict__ V,
-                                          const typename Unit<R, PAIR>::T* __restrict__ wr, long long ldu,
-                                          long long nu, int i0, int nvec, int r, double (*red)[2 * kGroup]) {
+                                          const typename Unit<R, PAIR>::T* __restrict__ wr, long long ldwu,
+                                          long long ldu, long long nu, int i0, int nvec, int r,
+                                          double (*red)[2 * 2 * kGroup]) {
     using U = Unit<R, PAIR>;
     using T = typename U::T;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long stride = (long long)gridDim.x * kTpb;
-    double ar[G], ai[G];
+    double ar[NW][G], ai[NW][G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) ar[g] = ai[g] = 0.0;
+    for (int q = 0; q < NW; ++q)
+#pragma unroll
+        for (int g = 0; g < G; ++g) ar[q][g] = ai[q][g] = 0.0;
     for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < nu; k += stride) {
-        const T wu = wr[k];
+        T wu[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) wu[q] = wr[q * ldwu + k];
         T vu[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) vu[g] = stream_load(&V[(i0 + g) * ldu + k]);
@@ -80,64 +85,83 @@ __device__ __forceinline__ void dot_group(double2* __restrict__ partial,
         for (int g = 0; g < G; ++g) {
 #pragma unroll
             for (int h = 0; h < U::per; ++h) {
-                const double2 v = U::get(vu[g], h), wv = U::get(wu, h);
-                ar[g] += v.x * wv.x + v.y * wv.y;
-                ai[g] += v.x * wv.y - v.y * wv.x;
+                const double2 v = U::get(vu[g], h);
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    const double2 wv = U::get(wu[q], h);
+                    ar[q][g] += v.x * wv.x + v.y * wv.y;
+                    ai[q][g] += v.x * wv.y - v.y * wv.x;
+                }
             }
         }
     }
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const double sr = wave_sum(ar[g]), si = wave_sum(ai[g]);
-        if (lane == 0) { red[wave][2 * g] = sr; red[wave][2 * g + 1] = si; }
-    }
+    for (int q = 0; q < NW; ++q)
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const double sr = wave_sum(ar[q][g]), si = wave_sum(ai[q][g]);
+            if (lane == 0) { red[wave][2 * (q * G + g)] = sr; red[wave][2 * (q * G + g) + 1] = si; }
+        }
     __syncthreads();
-    if (threadIdx.x < G) {
-        const int g = threadIdx.x;
+    if (threadIdx.x < NW * G) {
+        const int q = threadIdx.x / G, g = threadIdx.x - q * G;
         double sr = 0, si = 0;
-        for (int wv = 0; wv < kTpb / 64; ++wv) { sr += red[wv][2 * g]; si += red[wv][2 * g + 1]; }
-        partial[((long long)r * nvec + i0 + g) * gridDim.x + blockIdx.x] = make_double2(sr, si);
+        for (int wv = 0; wv < kTpb / 64; ++wv) { sr += red[wv][2 * threadIdx.x]; si += red[wv][2 * threadIdx.x + 1]; }
+        partial[(((long long)q * gridDim.y + r) * nvec + i0 + g) * gridDim.x + blockIdx.x] = make_double2(sr, si);
     }
     __syncthreads();
 }
 
-// partial sums of conj(V_i) w for i < nvec: workgroup (b, r, g) takes group g
-// of kGroup basis vectors (the last group may hold fewer) over its share of
-// the elements, so the groups stream side by side (vectors read in units of
-// Unit<R, PAIR>; n and the strides multiples of the unit)
-template <typename R, bool PAIR>
+// partial sums of conj(V_i) w_q for i < nvec and the NW vectors w_q = w + q
+// ldw: workgroup (b, r, g) takes group g of kGroup basis vectors (the last
+// group may hold fewer) over its share of the elements, so the groups stream
+// side by side (vectors read in units of Unit<R, PAIR>; n and the strides
+// multiples of the unit)
+template <typename R, bool PAIR, int NW>
 __global__ void __launch_bounds__(kTpb) k_multidot(double2* __restrict__ partial, const C<R>* __restrict__ Vb,
-                                                   long long ldv, int nvec, const C<R>* __restrict__ w, long long n,
-                                                   long long rsv, long long rsw) {
+                                                   long long ldv, int nvec, const C<R>* __restrict__ w,
+                                                   long long ldw, long long n, long long rsv, long long rsw) {
     using U = Unit<R, PAIR>;
     using T = typename U::T;
-    __shared__ double red[kTpb / 64][2 * kGroup];
+    __shared__ double red[kTpb / 64][2 * 2 * kGroup];
     const int r = blockIdx.y;
     const T* V = reinterpret_cast<const T*>(Vb + r * rsv);
     const T* wr = reinterpret_cast<const T*>(w + r * rsw);
-    const long long nu = n / U::per, ldu = ldv / U::per;
+    const long long nu = n / U::per, ldu = ldv / U::per, ldwu = ldw / U::per;
     static_assert(kGroup == 8, "the group sizes below cover 1 to 8");
     const int i0 = blockIdx.z * kGroup;
     switch (min(kGroup, nvec - i0)) {   // uniform over the workgroup
 #define VIE_DOT_G(g_) \
-    case g_: dot_group<R, PAIR, g_>(partial, V, wr, ldu, nu, i0, nvec, r, red); break;
+    case g_: dot_group<R, PAIR, g_, NW>(partial, V, wr, ldwu, ldu, nu, i0, nvec, r, red); break;
         VIE_DOT_G(1) VIE_DOT_G(2) VIE_DOT_G(3) VIE_DOT_G(4) VIE_DOT_G(5) VIE_DOT_G(6) VIE_DOT_G(7) VIE_DOT_G(8)
 #undef VIE_DOT_G
         default: break;
     }
 }
 
+template <typename R, int NW>
+static void multidot_nw(double2* partial, const C<R>* Vb, long long ldv, int nvec, const C<R>* w, long long ldw,
+                        long long n, long long rsv, long long rsw, int nrhs, int nblocks, hipStream_t s) {
+    const unsigned ngroups = (unsigned)((nvec + kGroup - 1) / kGroup);
+    if (pair_units<R>(Vb, w, n, ldv, rsv, rsw) && (ldw & 1) == 0)
+        hipLaunchKernelGGL((k_multidot<R, true, NW>), dim3(nblocks, nrhs, ngroups), dim3(kTpb), 0, s, partial, Vb,
+                           ldv, nvec, w, ldw, n, rsv, rsw);
+    else
+        hipLaunchKernelGGL((k_multidot<R, false, NW>), dim3(nblocks, nrhs, ngroups), dim3(kTpb), 0, s, partial, Vb,
+                           ldv, nvec, w, ldw, n, rsv, rsw);
+    VIE_HIP(hipGetLastError());
+}
+
 template <typename R>
 void launch_multidot(double2* partial, const C<R>* Vb, long long ldv, int nvec, const C<R>* w, long long n,
                      long long rsv, long long rsw, int nrhs, int nblocks, hipStream_t s) {
-    const unsigned ngroups = (unsigned)((nvec + kGroup - 1) / kGroup);
-    if (pair_units<R>(Vb, w, n, ldv, rsv, rsw))
-        hipLaunchKernelGGL((k_multidot<R, true>), dim3(nblocks, nrhs, ngroups), dim3(kTpb), 0, s, partial, Vb, ldv,
-                           nvec, w, n, rsv, rsw);
-    else
-        hipLaunchKernelGGL((k_multidot<R, false>), dim3(nblocks, nrhs, ngroups), dim3(kTpb), 0, s, partial, Vb, ldv,
-                           nvec, w, n, rsv, rsw);
-    VIE_HIP(hipGetLastError());
+    multidot_nw<R, 1>(partial, Vb, ldv, nvec, w, 0, n, rsv, rsw, nrhs, nblocks, s);
+}
+
+template <typename R>
+void launch_multidot2(double2* partial, const C<R>* Vb, long long ldv, int nvec, const C<R>* w, long long ldw,
+                      long long n, long long rsv, long long rsw, int nrhs, int nblocks, hipStream_t s) {
+    multidot_nw<R, 2>(partial, Vb, ldv, nvec, w, ldw, n, rsv, rsw, nrhs, nblocks, s);
 }
 
 // The basis is stored unnormalised: slot i holds u_i with v_i = u_i * ivn[i]
@@ -255,6 +279,306 @@ void launch_update(C<R>* w, const C<R>* Vb, long long ldv, int nvec, const doubl
     else
         hipLaunchKernelGGL((k_update<R, false>), dim3(nblocks, nrhs), dim3(kTpb), 0, s, w, Vb, ldv, nvec, h, n, rsv,
                            rsw, norm_partial, ivn, ivn_ld, jw);
+    VIE_HIP(hipGetLastError());
+}
+
+// ---- two Arnoldi steps per pass over the basis (s-step Arnoldi, s = 2) ----
+//
+// For the pair of steps (j, j + 1): w1 = A v_j and w2 = (A - sigma) w1 with
+// sigma = h_jj = v_j^H A v_j, the Rayleigh quotient of v_j, which keeps w2
+// from leaning on w1.  One dot pass gives h = V^H w1 and g = V^H w2, one
+// update pass w1 - V h and w2 - V g (V = v_0..v_j).  With beta1 = ||w1 -
+// V h|| the next basis vector is v_{j+1} = (w1 - V h) / beta1, and w2 is
+// then orthogonalised against it alone: with d = (w1 - V h)^H (w2 - V g),
+// u_{j+2} = (w2 - V g - d / beta1^2 (w1 - V h)) / beta1, whose norm is the
+// subdiagonal entry h_{j+2, j+1}.  Column j + 1 of the Hessenberg matrix
+// follows from A v_{j+1} = (A w1 - A V h) / beta1 = (w2 + sigma w1 - V_{j+2}
+// H h) / beta1 (the Arnoldi relation for A V h; H the unrotated columns 0..j):
+//   h_{i, j+1} = (g_i + sigma h_i - (H h)_i) / beta1   (i <= j)
+//   h_{j+1, j+1} = d / beta1^2                          (as sigma = h_j).
+// Both products are applied to stored vectors as they are (w1 to the raw
+// output of the first): the stored scale of u_j, sw = ivn[j], multiplies
+// both, as in the one-step update.
+
+// one wave per (row i, slot r): h_i = conj(v_i) (sw w1) from plane 0 of the
+// dot partials, g_i = conj(v_i) (sw w2_raw) - sigma h_i from plane 1, with
+// sigma = h_j summed again by every wave (the same order, so the same bits),
+// and the update coefficients h_i ivn[i], g_i ivn[i]
+__global__ void __launch_bounds__(64) k_reduce_pair(double2* __restrict__ h, double2* __restrict__ coef,
+                                                    double2* __restrict__ gcol, double2* __restrict__ coef2,
+                                                    const double2* __restrict__ partial, int nblocks, int nvec,
+                                                    int na, const double* __restrict__ ivn, long long ivn_ld, int jw) {
+    const int i = blockIdx.x, r = blockIdx.y, lane = threadIdx.x, j = nvec - 1;
+    const double2* p1 = partial + ((long long)r * nvec + i) * nblocks;
+    const double2* p2 = partial + (((long long)na + r) * nvec + i) * nblocks;
+    const double2* pj = partial + ((long long)r * nvec + j) * nblocks;
+    double a = 0, b = 0, c = 0, d = 0, e = 0, f = 0;
+    for (int k = lane; k < nblocks; k += 64) {
+        a += p1[k].x;
+        b += p1[k].y;
+        c += p2[k].x;
+        d += p2[k].y;
+        e += pj[k].x;
+        f += pj[k].y;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    d = wave_sum(d);
+    e = wave_sum(e);
+    f = wave_sum(f);
+    if (lane == 0) {
+        const double sw = ivn[r * ivn_ld + jw], iv = ivn[r * ivn_ld + i], ivj = ivn[r * ivn_ld + j];
+        const double2 sigma = make_double2(e * sw * ivj, f * sw * ivj);
+        const double2 hv = make_double2(a * sw * iv, b * sw * iv);
+        const double2 gv = csub(make_double2(c * sw * iv, d * sw * iv), cmul(sigma, hv));
+        h[(long long)r * nvec + i] = hv;
+        coef[(long long)r * nvec + i] = make_double2(hv.x * iv, hv.y * iv);
+        gcol[(long long)r * nvec + i] = gv;
+        coef2[(long long)r * nvec + i] = make_double2(gv.x * iv, gv.y * iv);
+    }
+}
+
+void launch_reduce_pair(double2* h, double2* coef, double2* gcol, double2* coef2, const double2* partial, int nvec,
+                        int nblocks, int nrhs, const double* ivn, long long ivn_ld, int jw, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_pair, dim3(nvec, nrhs), dim3(64), 0, s, h, coef, gcol, coef2, partial, nblocks, nvec,
+                       nrhs, ivn, ivn_ld, jw);
+    VIE_HIP(hipGetLastError());
+}
+
+// w1 <- sw w1 - sum_i c_i u_i and w2 <- sw (w2 - sigma w1) - sum_i c2_i u_i
+// (w2 = w1 + ldv, w1 the value before its update; sigma = h[r nvec + nvec -
+// 1]), with partial sums of |w1|^2 and of conj(w1) w2 over the stored values
+template <typename R, bool PAIR>
+__global__ void __launch_bounds__(kTpb) k_update_pair(C<R>* __restrict__ w, const C<R>* __restrict__ Vb,
+                                                      long long ldv, int nvec, const double2* __restrict__ coef,
+                                                      const double2* __restrict__ coef2,
+                                                      const double2* __restrict__ hcol, long long n, long long rsv,
+                                                      long long rsw, double* __restrict__ norm_partial,
+                                                      double2* __restrict__ dot_partial,
+                                                      const double* __restrict__ ivn, long long ivn_ld, int jw) {
+    using U = Unit<R, PAIR>;
+    using T = typename U::T;
+    __shared__ double red[kTpb / 64][3];
+    const int r = blockIdx.y;
+    const T* V = reinterpret_cast<const T*>(Vb + r * rsv);
+    T* w1p = reinterpret_cast<T*>(w + r * rsw);
+    T* w2p = reinterpret_cast<T*>(w + r * rsw + ldv);
+    const long long nu = n / U::per, ldu = ldv / U::per;
+    const double2* c1 = coef + (long long)r * nvec;
+    const double2* c2 = coef2 + (long long)r * nvec;
+    const double2 sigma = hcol[(long long)r * nvec + nvec - 1];
+    const double sw = ivn[r * ivn_ld + jw];
+    double nacc = 0.0, dre = 0.0, dim_ = 0.0;
+    for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < nu; k += (long long)gridDim.x * kTpb) {
+        T a1 = w1p[k], a2 = w2p[k];
+        double2 x1[U::per], x2[U::per];
+#pragma unroll
+        for (int q = 0; q < U::per; ++q) {
+            const double2 o1 = U::get(a1, q), o2 = U::get(a2, q);
+            const double2 t = csub(o2, cmul(sigma, o1));
+            x1[q] = make_double2(sw * o1.x, sw * o1.y);
+            x2[q] = make_double2(sw * t.x, sw * t.y);
+        }
+        int i = 0;
+        for (; i + 8 <= nvec; i += 8) {
+            T vu[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) vu[u] = stream_load(&V[(i + u) * ldu + k]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double2 p = c1[i + u], q2 = c2[i + u];
+#pragma unroll
+                for (int q = 0; q < U::per; ++q) {
+                    const double2 v = U::get(vu[u], q);
+                    x1[q].x -= p.x * v.x - p.y * v.y;
+                    x1[q].y -= p.x * v.y + p.y * v.x;
+                    x2[q].x -= q2.x * v.x - q2.y * v.y;
+                    x2[q].y -= q2.x * v.y + q2.y * v.x;
+                }
+            }
+        }
+        for (; i < nvec; ++i) {
+            const T vu = stream_load(&V[i * ldu + k]);
+            const double2 p = c1[i], q2 = c2[i];
+#pragma unroll
+            for (int q = 0; q < U::per; ++q) {
+                const double2 v = U::get(vu, q);
+                x1[q].x -= p.x * v.x - p.y * v.y;
+                x1[q].y -= p.x * v.y + p.y * v.x;
+                x2[q].x -= q2.x * v.x - q2.y * v.y;
+                x2[q].y -= q2.x * v.y + q2.y * v.x;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < U::per; ++q) {
+            U::set(a1, q, x1[q]);
+            U::set(a2, q, x2[q]);
+        }
+        w1p[k] = a1;
+        w2p[k] = a2;
+#pragma unroll
+        for (int q = 0; q < U::per; ++q) {   // the stored (rounded) values
+            const double2 o1 = U::get(a1, q), o2 = U::get(a2, q);
+            nacc += o1.x * o1.x + o1.y * o1.y;
+            dre += o1.x * o2.x + o1.y * o2.y;
+            dim_ += o1.x * o2.y - o1.y * o2.x;
+        }
+    }
+    nacc = wave_sum(nacc);
+    dre = wave_sum(dre);
+    dim_ = wave_sum(dim_);
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6][0] = nacc;
+        red[threadIdx.x >> 6][1] = dre;
+        red[threadIdx.x >> 6][2] = dim_;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0, c = 0;
+        for (int i = 0; i < kTpb / 64; ++i) { a += red[i][0]; b += red[i][1]; c += red[i][2]; }
+        norm_partial[(long long)r * gridDim.x + blockIdx.x] = a;
+        dot_partial[(long long)r * gridDim.x + blockIdx.x] = make_double2(b, c);
+    }
+}
+
+template <typename R>
+void launch_update_pair(C<R>* w, const C<R>* Vb, long long ldv, int nvec, const double2* coef, const double2* coef2,
+                        const double2* h, long long n, long long rsv, long long rsw, double* norm_partial,
+                        double2* dot_partial, const double* ivn, long long ivn_ld, int jw, int nrhs, int nblocks,
+                        hipStream_t s) {
+    if (pair_units<R>(Vb, w, n, ldv, rsv, rsw))
+        hipLaunchKernelGGL((k_update_pair<R, true>), dim3(nblocks, nrhs), dim3(kTpb), 0, s, w, Vb, ldv, nvec, coef,
+                           coef2, h, n, rsv, rsw, norm_partial, dot_partial, ivn, ivn_ld, jw);
+    else
+        hipLaunchKernelGGL((k_update_pair<R, false>), dim3(nblocks, nrhs), dim3(kTpb), 0, s, w, Vb, ldv, nvec, coef,
+                           coef2, h, n, rsv, rsw, norm_partial, dot_partial, ivn, ivn_ld, jw);
+    VIE_HIP(hipGetLastError());
+}
+
+// per slot: d = sum of the conj(w1) w2 partials (lane-strided, the order of
+// the norm sums), beta1 = nrm[s] (from the Givens step of column j), and
+// pc[s] = (d / beta1^2, 1 / beta1), both 0 for beta1 = 0
+__global__ void __launch_bounds__(64) k_pair_coef(double2* __restrict__ pc, const double2* __restrict__ dpart,
+                                                  int nblocks, const double* __restrict__ nrm) {
+    const int r = blockIdx.x, lane = threadIdx.x;
+    double sr = 0, si = 0;
+    for (int b = lane; b < nblocks; b += 64) {
+        sr += dpart[(long long)r * nblocks + b].x;
+        si += dpart[(long long)r * nblocks + b].y;
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) {
+        const double b1 = nrm[r];
+        const double ib = b1 > 0 ? 1.0 / b1 : 0.0;
+        pc[2 * r] = make_double2(sr * ib * ib, si * ib * ib);
+        pc[2 * r + 1] = make_double2(ib, b1);
+    }
+}
+
+void launch_pair_coef(double2* pc, const double2* dpart, int nblocks, const double* nrm, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_pair_coef, dim3(nrhs), dim3(64), 0, s, pc, dpart, nblocks, nrm);
+    VIE_HIP(hipGetLastError());
+}
+
+// u2 <- (u2 - gamma u1) / beta1 in place (u2 = u1 + ldv; gamma, 1 / beta1
+// from pc), with partial sums of |u2|^2 over the stored values
+template <typename R, bool PAIR>
+__global__ void __launch_bounds__(kTpb) k_axpy_pair(C<R>* __restrict__ u1, long long ldv, long long n,
+                                                    long long rs, const double2* __restrict__ pc,
+                                                    double* __restrict__ norm_partial) {
+    using U = Unit<R, PAIR>;
+    using T = typename U::T;
+    __shared__ double red[kTpb / 64];
+    const int r = blockIdx.y;
+    const T* a = reinterpret_cast<const T*>(u1 + r * rs);
+    T* b = reinterpret_cast<T*>(u1 + r * rs + ldv);
+    const long long nu = n / U::per;
+    const double2 gm = pc[2 * r];
+    const double ib = pc[2 * r + 1].x;
+    double acc = 0.0;
+    for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < nu; k += (long long)gridDim.x * kTpb) {
+        const T au = a[k];
+        T bu = b[k];
+#pragma unroll
+        for (int q = 0; q < U::per; ++q) {
+            const double2 t = csub(U::get(bu, q), cmul(gm, U::get(au, q)));
+            U::set(bu, q, make_double2(t.x * ib, t.y * ib));
+        }
+        b[k] = bu;
+#pragma unroll
+        for (int q = 0; q < U::per; ++q) {
+            const double2 o = U::get(bu, q);
+            acc += o.x * o.x + o.y * o.y;
+        }
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int i = 0; i < kTpb / 64; ++i) t += red[i];
+        norm_partial[(long long)r * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+template <typename R>
+void launch_axpy_pair(C<R>* u1, long long ldv, long long n, long long rs, const double2* pc, double* norm_partial,
+                      int nrhs, int nblocks, hipStream_t s) {
+    if (pair_units<R>(u1, u1, n, ldv, rs, rs))
+        hipLaunchKernelGGL((k_axpy_pair<R, true>), dim3(nblocks, nrhs), dim3(kTpb), 0, s, u1, ldv, n, rs, pc,
+                           norm_partial);
+    else
+        hipLaunchKernelGGL((k_axpy_pair<R, false>), dim3(nblocks, nrhs), dim3(kTpb), 0, s, u1, ldv, n, rs, pc,
+                           norm_partial);
+    VIE_HIP(hipGetLastError());
+}
+
+// Hessenberg column j + 1 of a pair (entries 0..j + 1, the subdiagonal comes
+// from the norm of u_{j+2}) from h (column j above the diagonal), g, sigma =
+// h_j, pc and the unrotated columns 0..j (st.Hr).  One workgroup of 4 waves
+// per slot: lane l takes rows l, l + 64, ..., wave w the columns k = w, w +
+// 4, ... of (H h)_i = sum_k H[i, k] h_k (H[i, k] = 0 for k < i - 1), summed
+// over the waves in LDS in a fixed order.
+constexpr int kColWaves = 4;
+constexpr int kColRows = 201;   // restart <= 200
+
+__global__ void __launch_bounds__(64 * kColWaves) k_pair_column(ArnoldiState st, const double2* __restrict__ h,
+                                                                const double2* __restrict__ gcol,
+                                                                const double2* __restrict__ pc,
+                                                                double2* __restrict__ col, int j) {
+    __shared__ double2 part[kColWaves][kColRows];
+    const int r = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6, m = st.m, nvec = j + 1;
+    const double2* hr = h + (long long)r * nvec;
+    const double2* Hr = st.Hr + (long long)r * m * (m + 1);
+    for (int i = lane; i <= j; i += 64) {
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+        for (int k = wv; k <= j; k += kColWaves)
+            if (k >= i - 1) acc = cadd(acc, cmul(Hr[(long long)k * (m + 1) + i], hr[k]));
+        part[wv][i] = acc;
+    }
+    __syncthreads();
+    if (wv == 0) {
+        const double2 sigma = hr[j];
+        const double ib = pc[2 * r + 1].x;
+        double2* out = col + (long long)r * (nvec + 1);
+        for (int i = lane; i <= j; i += 64) {
+            double2 hh = part[0][i];
+            for (int w = 1; w < kColWaves; ++w) hh = cadd(hh, part[w][i]);
+            const double2 t = csub(cadd(gcol[(long long)r * nvec + i], cmul(sigma, hr[i])), hh);
+            out[i] = make_double2(t.x * ib, t.y * ib);
+        }
+        if (lane == 0) out[j + 1] = pc[2 * r];
+    }
+}
+
+void launch_pair_column(ArnoldiState st, const double2* h, const double2* gcol, const double2* pc, double2* col,
+                        int j, int na, hipStream_t s) {
+    VIE_REQUIRE(st.Hr != nullptr && j + 1 < st.m && j + 1 < kColRows, VIE_EINVAL,
+                "pair column without the unrotated Hessenberg matrix");
+    hipLaunchKernelGGL(k_pair_column, dim3(na), dim3(64 * kColWaves), 0, s, st, h, gcol, pc, col, j);
     VIE_HIP(hipGetLastError());
 }
 
@@ -447,6 +771,11 @@ __global__ void __launch_bounds__(64 * kGivWaves) k_givens(ArnoldiState st, cons
                 c = make_double2(a.x / den, -a.y / den);   // conj(a) / den
                 z = make_double2(hn / den, 0.0);
             }
+            if (st.Hr) {   // the unrotated column, for the two-step Arnoldi
+                double2* Hu = st.Hr + ((long long)s * m + j) * (m + 1);
+                for (int i = 0; i <= j; ++i) Hu[i] = lh[wv][i];
+                Hu[j + 1] = make_double2(hn, 0.0);
+            }
             st.cs[(long long)s * m + j] = c;
             st.sn[(long long)s * m + j] = z;
             Hc[j] = make_double2(den, 0.0);
@@ -581,6 +910,13 @@ void launch_nonfinite(int* flag, const double2* v, long long n, hipStream_t s) {
                                      long long, int, int, hipStream_t);                                          \
     template void launch_update<R>(C<R>*, const C<R>*, long long, int, const double2*, long long, long long,   \
                                    long long, double*, const double*, long long, int, int, int, hipStream_t);    \
+    template void launch_multidot2<R>(double2*, const C<R>*, long long, int, const C<R>*, long long, long long,  \
+                                      long long, long long, int, int, hipStream_t);                               \
+    template void launch_update_pair<R>(C<R>*, const C<R>*, long long, int, const double2*, const double2*,      \
+                                        const double2*, long long, long long, long long, double*, double2*,      \
+                                        const double*, long long, int, int, int, hipStream_t);                   \
+    template void launch_axpy_pair<R>(C<R>*, long long, long long, long long, const double2*, double*, int, int, \
+                                      hipStream_t);                                                               \
     template void launch_scale_into<R>(C<R>*, const C<R>*, const double*, long long, long long, long long, int, \
                                        hipStream_t);                                                             \
     template void launch_combine<R>(double2*, const C<R>*, long long, int, const double2*, long long, long long, \

@@ -57,6 +57,11 @@ struct Layout {
     double *nrm, *npart, *inv, *bn, *rn, *ivn;
     double2 *H, *cs, *sn, *g, *slot;   // least-squares state (ArnoldiState)
     int* stat;
+    // two-step Arnoldi: unrotated Hessenberg columns, second coefficients,
+    // conj(w1) w2 partials, norm partials of u_{j+2}, pair coefficients and
+    // the assembled column j + 1
+    double2 *Hr, *coef2, *dpart, *pc, *col;
+    double* npart2;
 };
 
 // Arnoldi steps between host checks of the convergence flag: several while
@@ -136,7 +141,7 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
             slot[s] = make_double2(rnorm[active[s]], ir ? std::max(o.inner_tol, need) : need);
         }
         VIE_HIP(hipMemcpyAsync(L.slot, slot.data(), na * sizeof(double2), hipMemcpyHostToDevice, c.stream));
-        const ArnoldiState as{L.H, L.cs, L.sn, L.g, L.slot, L.stat, m};
+        const ArnoldiState as{L.H, L.cs, L.sn, L.g, L.slot, L.stat, m, L.Hr};
         const long long ivld = m + 1;
         launch_arnoldi_init(as, L.ivn, ivld, na, c.stream);
 
@@ -172,25 +177,74 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
                           c.stream);
         };
 
+        // Arnoldi steps j and j + 1 with one pass over the basis (s-step
+        // Arnoldi, s = 2; the algebra is stated with the kernels):
+        // w1 = P^-1 A u_j into slot j + 1, w2 = P^-1 A w1 into slot j + 2,
+        // both orthogonalised against u_0..u_j by one dot and one update
+        // pass, then u_{j+2} against u_{j+1} alone
+        auto pair = [&](int j) {
+            C<R>* vj = Vb + (long long)j * ldv;
+            C<R>* w1 = Vb + (long long)(j + 1) * ldv;
+            C<R>* w2 = Vb + (long long)(j + 2) * ldv;
+            apply_op<R>(c, OP_PREC, na, vj, w1, nullptr);
+            apply_op<R>(c, OP_PREC, na, w1, w2, nullptr);
+            const int nvec = j + 1;
+            const double vb = (double)na * n * sizeof(C<R>);
+            {
+                ProfScope ps(c.prof, c.stream, VIE_K_GS_DOT, vb * (nvec + 2.0 * ((nvec + 7) / 8)));
+                launch_multidot2<R>(L.partial, Vb, ldv, nvec, w1, ldv, n, n, n, na, nbd, c.stream);
+                launch_reduce_pair(L.h1, L.coef, L.h2, L.coef2, L.partial, nvec, nbd, na, L.ivn, ivld, j, c.stream);
+            }
+            {   // reads the basis, reads and writes w1 and w2
+                ProfScope ps(c.prof, c.stream, VIE_K_GS_UPDATE, vb * (nvec + 4));
+                launch_update_pair<R>(w1, Vb, ldv, nvec, L.coef, L.coef2, L.h1, n, n, n, L.npart, L.dpart, L.ivn,
+                                      ivld, j, na, nb, c.stream);
+            }
+            launch_givens(as, L.h1, nullptr, L.npart, nb, L.nrm, L.ivn + (j + 1), ivld, j, na, c.stream);
+            launch_pair_coef(L.pc, L.dpart, nb, L.nrm, na, c.stream);
+            {   // reads u_{j+1}, reads and writes u_{j+2}
+                ProfScope ps(c.prof, c.stream, VIE_K_GS_UPDATE, vb * 3);
+                launch_axpy_pair<R>(w1, ldv, n, n, L.pc, L.npart2, na, nb, c.stream);
+            }
+            launch_pair_column(as, L.h1, L.h2, L.pc, L.col, j, na, c.stream);
+            launch_givens(as, L.col, nullptr, L.npart2, nb, L.nrm, L.ivn + (j + 2), ivld, j + 1, na, c.stream);
+        };
+        // s = 2 by default once a batch of vectors is large enough for the
+        // passes over the basis to stream it (below, the pair's extra small
+        // kernels cost more than the halved reads); the second Gram-Schmidt
+        // pass runs with single steps
+        const long long vec_bytes = na * n * (long long)sizeof(C<R>);
+        const bool two = (o.s_step == 2 || (o.s_step == 0 && vec_bytes > kGraphAutoBytes)) && !o.reorth && m >= 2;
+
         // steps [j0, j1): launched one by one, or replayed from a graph
         // (the product's workspace is grown first, so that no step
         // reallocates it under a capture)
-        const long long vec_bytes = na * n * (long long)sizeof(C<R>);
         const bool use_graph = (o.graph > 0 || (o.graph < 0 && vec_bytes <= kGraphAutoBytes)) && !c.prof.on;
         if (use_graph) c.ws.get(apply_workspace_bytes(c, na, sizeof(C<R>)));
         auto enqueue = [&](int j0, int j1) {
+            auto run_steps = [&] {
+                for (int j = j0; j < j1;) {
+                    if (two && j + 1 < j1) {
+                        pair(j);
+                        j += 2;
+                    } else {
+                        step(j);
+                        j += 1;
+                    }
+                }
+            };
             if (!use_graph) {
-                for (int j = j0; j < j1; ++j) step(j);
+                run_steps();
                 return;
             }
-            const std::vector<long long> key{(long long)sizeof(R), na, m, o.reorth, j0, j1, n,
+            const std::vector<long long> key{(long long)sizeof(R), na, m, o.reorth, two, j0, j1, n,
                                              (long long)reinterpret_cast<uintptr_t>(Vb), ldv,
                                              (long long)reinterpret_cast<uintptr_t>(L.rhs),
                                              (long long)reinterpret_cast<uintptr_t>(c.ws.p),
                                              (long long)reinterpret_cast<uintptr_t>(c.jmbuf.p), c.nc};
             auto it = c.graphs.execs.find(key);
             if (it == c.graphs.execs.end()) {
-                for (int j = j0; j < j1; ++j) step(j);
+                run_steps();
                 if (c.graphs.execs.size() >= GraphCache::kMax) c.graphs.clear();
                 c.graphs.execs.emplace(key, nullptr);
                 return;
@@ -202,7 +256,7 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
                 c.stream = c.graphs.cap;
                 VIE_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
                 try {
-                    for (int j = j0; j < j1; ++j) step(j);
+                    run_steps();
                 } catch (...) {
                     (void)hipStreamEndCapture(c.stream, &gr);
                     if (gr) (void)hipGraphDestroy(gr);
@@ -225,7 +279,8 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
         // steps and keeps one chunk queued ahead of the one it waits for, so
         // the device does not idle on the round trip; a chunk queued behind
         // the converged one runs with its Givens updates turned off.
-        const int S = o.sync_steps > 0 ? o.sync_steps : auto_sync_steps(vec_bytes);
+        int S = o.sync_steps > 0 ? o.sync_steps : auto_sync_steps(vec_bytes);
+        if (two) S += S & 1;   // chunks of whole pairs
         const int nch = (m + S - 1) / S;
         int* pin = static_cast<int*>(c.hpin.get(2 * 4 * sizeof(int)));
         for (auto& e : c.col_ev)
@@ -284,7 +339,7 @@ int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2*
         return o_;
     };
     const size_t o_rhs = take((size_t)nrhs * n * 16), o_r = take((size_t)nrhs * n * 16);
-    const size_t o_part = take((size_t)nrhs * (m + 1) * std::max(nb, dot_blocks_for(n)) * 16);
+    const size_t o_part = take((size_t)2 * nrhs * (m + 1) * std::max(nb, dot_blocks_for(n)) * 16);
     const size_t o_h1 = take((size_t)nrhs * (m + 1) * 16), o_h2 = take((size_t)nrhs * (m + 1) * 16);
     const size_t o_coef = take((size_t)nrhs * (m + 1) * 16), o_ivn = take((size_t)nrhs * (m + 1) * 8);
     const size_t o_y = take((size_t)nrhs * m * 16);
@@ -293,6 +348,9 @@ int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2*
     const size_t o_H = take((size_t)nrhs * m * (m + 1) * 16), o_cs = take((size_t)nrhs * m * 16);
     const size_t o_sn = take((size_t)nrhs * m * 16), o_g = take((size_t)nrhs * (m + 1) * 16);
     const size_t o_slot = take((size_t)nrhs * 16), o_stat = take(4 * sizeof(int));
+    const size_t o_Hr = take((size_t)nrhs * m * (m + 1) * 16), o_coef2 = take((size_t)nrhs * (m + 1) * 16);
+    const size_t o_dp = take((size_t)nrhs * nb * 16), o_pc = take((size_t)nrhs * 2 * 16);
+    const size_t o_col = take((size_t)nrhs * (m + 1) * 16), o_np2 = take((size_t)nrhs * nb * 8);
     char* base = static_cast<char*>(c.vecs.get(off));
     Layout L{};
     L.rhs = reinterpret_cast<double2*>(base + o_rhs);
@@ -314,6 +372,12 @@ int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2*
     L.g = reinterpret_cast<double2*>(base + o_g);
     L.slot = reinterpret_cast<double2*>(base + o_slot);
     L.stat = reinterpret_cast<int*>(base + o_stat);
+    L.Hr = reinterpret_cast<double2*>(base + o_Hr);
+    L.coef2 = reinterpret_cast<double2*>(base + o_coef2);
+    L.dpart = reinterpret_cast<double2*>(base + o_dp);
+    L.pc = reinterpret_cast<double2*>(base + o_pc);
+    L.col = reinterpret_cast<double2*>(base + o_col);
+    L.npart2 = reinterpret_cast<double*>(base + o_np2);
     if (st)
         for (int r = 0; r < nrhs; ++r) st[r] = vie_solve_stats{};
 

@@ -13,7 +13,9 @@
   unknowns per vector (3 V, V odd);
 * the Arnoldi steps replayed from HIP graphs, and other intervals between
   host checks of the device-side convergence flag, give the same bits as
-  launching every kernel and checking after every step.
+  launching every kernel and checking after every step;
+* two Arnoldi steps per pass over the basis (s-step Arnoldi, s = 2) against
+  the classical step and dense LU.
 """
 import functools
 import sys
@@ -108,8 +110,9 @@ def test_batched_pwl_solve_with_compaction(vie, torch, mode, tol, bound):
         assert abs(P[r] - pr) / abs(pr) < 10 * bound
 
 
+@pytest.mark.parametrize("s_step", [1, 2])
 @pytest.mark.parametrize("mode", [0, 1])
-def test_graph_replay_and_sync_interval_keep_bits(vie, torch, mode):
+def test_graph_replay_and_sync_interval_keep_bits(vie, torch, mode, s_step):
     """The batched solve of the compaction test with every kernel launched
     one by one and the host checking convergence after every step, against
     graph replay (a run of steps is captured the second time the solver
@@ -117,9 +120,10 @@ def test_graph_replay_and_sync_interval_keep_bits(vie, torch, mode):
     device does the same arithmetic, so solutions and statistics are the
     same bits, and every one matches dense LU.  The solves run back to back
     with host copies and synchronisations in between, so each replay is
-    checked after the solver's own uncaptured work."""
+    checked after the solver's own uncaptured work.  Both Arnoldi forms
+    (one step per pass over the basis, and two)."""
     N, D = (6, 5, 4), (0.005, 0.006, 0.005)
-    _say("graph replay mode %d" % mode)
+    _say("graph replay mode %d s_step %d" % (mode, s_step))
     T = _blocks(N, D)
     e, s = vi.ellipsoid_phantom(N, D, 71)
     tau, chi = physics.tau(e, s, F), physics.chi(e, s, F)
@@ -134,7 +138,7 @@ def test_graph_replay_and_sync_interval_keep_bits(vie, torch, mode):
     etd = _dev_batch(torch, ets)
     tol = 1e-11 if mode == 0 else 1e-10
     x0 = torch.empty_like(etd)
-    code, st0 = c.solve(etd, x0, mode=mode, tol=tol, restart=6, graph=0, sync_steps=1)
+    code, st0 = c.solve(etd, x0, mode=mode, tol=tol, restart=6, graph=0, sync_steps=1, s_step=s_step)
     assert code == vie.VIE_OK
     for r in range(3):
         assert relerr(_host(x0, r), xrefs[r]) < (1e-8 if mode == 0 else 1e-7)
@@ -142,13 +146,50 @@ def test_graph_replay_and_sync_interval_keep_bits(vie, torch, mode):
     runs = [(1, 0), (1, 0), (1, 0), (1, 3), (1, 3), (1, 3), (0, 4), (0, 0), (-1, 0), (-1, 2), (1, 100)]
     for graph, sync in runs:
         x = torch.empty_like(etd)
-        code, st = c.solve(etd, x, mode=mode, tol=tol, restart=6, graph=graph, sync_steps=sync)
+        code, st = c.solve(etd, x, mode=mode, tol=tol, restart=6, graph=graph, sync_steps=sync, s_step=s_step)
         torch.cuda.synchronize()
         same = torch.equal(x.cpu(), ref)
         _say("  graph %d sync %d: same bits %s, %s" % (graph, sync, same, [s_["iterations"] for s_ in st]))
         assert code == vie.VIE_OK and same
         for a, b in zip(st, st0):
             assert {k: v for k, v in a.items() if k != "seconds"} == {k: v for k, v in b.items() if k != "seconds"}
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("restart", [6, 7])
+def test_two_step_arnoldi_matches_one_step(vie, torch, mode, restart):
+    """Two Arnoldi steps per pass over the basis (s_step = 2, the default)
+    against the classical step (s_step = 1): both reach dense LU's solution
+    for a batch of three dipoles whose active set shrinks between cycles,
+    with an even and an odd restart length (the odd one ends each cycle
+    with a single step), and take about as many steps."""
+    N, D = (6, 5, 4), (0.005, 0.006, 0.005)
+    _say("two-step Arnoldi mode %d restart %d" % (mode, restart))
+    T = _blocks(N, D)
+    e, s = vi.ellipsoid_phantom(N, D, 72)
+    tau, chi = physics.tau(e, s, F), physics.chi(e, s, F)
+    pos = np.array([[0.0, 0.0, 0.012], [0.02, 0.0, -0.004], [0.0, 0.06, 0.0]])
+    mom = np.array([[0.0, 0.0, 1.0], [0.0, 1.0, 0.0], [1.0, 0.0, 0.0]])
+    ets = list(incident.dipoles_tested(N, D, F, pos, mom, chi != 0, nq=6))
+    A = solve.dense_prec_matrix(T, tau, D)
+    xrefs = [np.linalg.solve(A, matvec.rhs_prec(et, tau, D, F).reshape(-1)).reshape(et.shape) for et in ets]
+    c = vie.Context(0)
+    c.set_grid(N, D, F)
+    c.set_contrast(vox_to_lib(e), vox_to_lib(s))
+    etd = _dev_batch(torch, ets)
+    tol = 1e-11 if mode == 0 else 1e-10
+    its = {}
+    for s_step in (1, 2, 0):
+        x = torch.empty_like(etd)
+        code, st = c.solve(etd, x, mode=mode, tol=tol, restart=restart, s_step=s_step)
+        assert code == vie.VIE_OK
+        its[s_step] = [s_["iterations"] for s_ in st]
+        errs = [relerr(_host(x, r), xrefs[r]) for r in range(3)]
+        _say("  s_step %d: iterations %s, vs dense LU %s" % (s_step, its[s_step], ["%.1e" % v for v in errs]))
+        assert max(errs) < (1e-8 if mode == 0 else 1e-7)
+    assert its[0] in (its[1], its[2])   # the default picks one of the two forms
+    for a, b in zip(its[1], its[2]):
+        assert abs(a - b) <= max(4, 0.15 * a)
 
 
 @functools.lru_cache(None)
