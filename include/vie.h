@@ -424,7 +424,9 @@ enum {
     VIE_K_FFT_Z_INV = 4,  /* inverse FFT along z, crop, contrast epilogue     */
     VIE_K_GS_DOT = 5,     /* Gram-Schmidt inner products (and their reduction) */
     VIE_K_GS_UPDATE = 6,  /* Gram-Schmidt update, norm and normalisation      */
-    VIE_K_COUNT = 7
+    VIE_K_GS_PAIR = 7,    /* two-step Arnoldi: the second new vector against
+                             the first (u_{j+2} = (w2 - gamma u_{j+1}) / beta) */
+    VIE_K_COUNT = 8
 };
 
 /* enable = k > 0 clears the records and starts timing launches of the

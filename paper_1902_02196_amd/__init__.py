@@ -25,7 +25,7 @@ VIE_OK, VIE_EINVAL, VIE_ENOMEM, VIE_EDEVICE, VIE_ENOCONV, VIE_ENAN, VIE_ESTATE =
 C64, C128 = 0, 1
 OP_PREC, OP_A, OP_N = 0, 1, 2
 SOLVE_FP64, SOLVE_FP32_IR = 0, 1
-KERNELS = ("fft_z_fwd", "fft_y_fwd", "block", "fft_y_inv", "fft_z_inv", "gs_dot", "gs_update")
+KERNELS = ("fft_z_fwd", "fft_y_fwd", "block", "fft_y_inv", "fft_z_inv", "gs_dot", "gs_update", "gs_pair")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libvie.so is not built; run `python paper_1902_02196_amd/build.py` (needs hipcc)")

@@ -203,7 +203,7 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
             launch_givens(as, L.h1, nullptr, L.npart, nb, L.nrm, L.ivn + (j + 1), ivld, j, na, c.stream);
             launch_pair_coef(L.pc, L.dpart, nb, L.nrm, na, c.stream);
             {   // reads u_{j+1}, reads and writes u_{j+2}
-                ProfScope ps(c.prof, c.stream, VIE_K_GS_UPDATE, vb * 3);
+                ProfScope ps(c.prof, c.stream, VIE_K_GS_PAIR, vb * 3);
                 launch_axpy_pair<R>(w1, ldv, n, n, L.pc, L.npart2, na, nb, c.stream);
             }
             launch_pair_column(as, L.h1, L.h2, L.pc, L.col, j, na, c.stream);
