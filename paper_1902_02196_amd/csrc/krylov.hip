@@ -11,6 +11,9 @@ constexpr int kTpb = 256;
 
 // Basis vectors are streamed once per Gram-Schmidt pass and a whole basis is
 // larger than the caches, so their loads are non-temporal (stream_load).
+// The small kernels that sum per-workgroup partials walk them lane-strided
+// with the loop unrolled, so that a lane's loads are in flight together (the
+// additions keep their order, so the sums keep their bits).
 constexpr int kGroup = 8;   // basis vectors per workgroup of the dot kernel
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -177,6 +180,7 @@ __global__ void k_reduce_partials(double2* __restrict__ h, double2* __restrict__
     const int r = (int)(row / nvec), i = (int)(row % nvec);
     const double2* p = partial + row * nblocks;
     double sr = 0, si = 0;
+#pragma unroll 8
     for (int b = threadIdx.x; b < nblocks; b += 64) { sr += p[b].x; si += p[b].y; }
     sr = wave_sum(sr);
     si = wave_sum(si);
@@ -313,6 +317,7 @@ __global__ void __launch_bounds__(64) k_reduce_pair(double2* __restrict__ h, dou
     const double2* p2 = partial + (((long long)na + r) * nvec + i) * nblocks;
     const double2* pj = partial + ((long long)r * nvec + j) * nblocks;
     double a = 0, b = 0, c = 0, d = 0, e = 0, f = 0;
+#pragma unroll 8
     for (int k = lane; k < nblocks; k += 64) {
         a += p1[k].x;
         b += p1[k].y;
@@ -463,6 +468,7 @@ __global__ void __launch_bounds__(64) k_pair_coef(double2* __restrict__ pc, cons
                                                   int nblocks, const double* __restrict__ nrm) {
     const int r = blockIdx.x, lane = threadIdx.x;
     double sr = 0, si = 0;
+#pragma unroll 8
     for (int b = lane; b < nblocks; b += 64) {
         sr += dpart[(long long)r * nblocks + b].x;
         si += dpart[(long long)r * nblocks + b].y;
@@ -588,6 +594,7 @@ __global__ void k_reduce_norm(double* __restrict__ out, const double* __restrict
                               double* __restrict__ inv, long long inv_ld) {
     const int r = blockIdx.x;
     double s = 0;
+#pragma unroll 8
     for (int b = threadIdx.x; b < nblocks; b += 64) s += partial[(long long)r * nblocks + b];
     s = wave_sum(s);
     if (threadIdx.x == 0) {
@@ -731,6 +738,7 @@ __global__ void __launch_bounds__(64 * kGivWaves) k_givens(ArnoldiState st, cons
         const int s = base + wv;
         if (s < na) {
             double q = 0;
+#pragma unroll 8
             for (int b = lane; b < nblocks; b += 64) q += npart[(long long)s * nblocks + b];
             q = wave_sum(q);
             if (lane == 0) {
