@@ -224,6 +224,17 @@ def serving_main(args):
             time.sleep(delay)
         ids.append(submit(i))
         log("submitted %d at %.3f s" % (i, time.perf_counter() - t0))
+    # progress while the queue drains (a long stream otherwise prints
+    # nothing until the end)
+    reported = 0
+    while True:
+        done = sum(1 for i in ids if srv.poll(i)["done"])
+        if done == len(ids):
+            break
+        if done != reported:
+            log("completed %d of %d at %.1f s" % (done, len(ids), time.perf_counter() - t0))
+            reported = done
+        time.sleep(0.25)
     srv.wait()
     wall = time.perf_counter() - t0
     st = srv.stats(first_id=wid + 1)
