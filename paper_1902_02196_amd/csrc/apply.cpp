@@ -54,8 +54,12 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs,
         apply_jm<R>(c, op, nrhs, x, y, rhs, ws_ext, ws_cap);
         return;
     }
-    if (op != OP_N && op != OP_CURL && op != OP_K)
+    if (op != OP_N && op != OP_CURL && op != OP_K && op != OP_JMS)
         VIE_REQUIRE(c.has_contrast, VIE_ESTATE, "operator needs vie_set_contrast");
+    if (op == OP_JMS) {
+        VIE_REQUIRE(c.nc == 12 && nrhs % 2 == 0 && c.op && curlspec<R>(c) && jm_fused_supported(c, sizeof(C<R>)),
+                    VIE_EINVAL, "the fused J-M sums need vector pairs on a compiled x length");
+    }
     if (op == OP_CURL) {
         VIE_REQUIRE(sizeof(R) == 8 && c.nc == 12, VIE_EINVAL,
                     "the magnetic product is complex128 and PWL (12 unknowns per voxel) only");
@@ -154,7 +158,15 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs,
     p3.s_y = row;
     p3.u_e = c.O[0];
     p3.pitch = Mx;
-    if (op == OP_CURL || op == OP_K) {
+    if (op == OP_JMS) {
+        // both halves of each pair in one workgroup: the 30 curl and the 60
+        // N tensors per frequency
+        p3.nrhs = nrhs / 2;
+        KernelTiming kt(c.prof, VIE_K_BLOCK, 2 * bA2 + 90.0 * c.Osz * es);
+        const bool ok = launch_p3_jm<R>(A2, opspec<R>(c), curlspec<R>(c), p3, twid<R>(c.ax[0]),
+                                        mk<R>(0, R(-c.omega * kEps0)), mk<R>(0, R(c.omega * kMu0)), s);
+        VIE_REQUIRE(ok, VIE_EINVAL, "J-M x pass: no compiled kernel for this length");
+    } else if (op == OP_CURL || op == OP_K) {
         // curl operator: staged x pass (any length up to 256) on its 30
         // unique tensors
         const int nt = p3_threads<R>();
@@ -271,6 +283,7 @@ void apply_op(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs,
                 break;
             case OP_N:
             case OP_K:
+            case OP_JMS:
                 ep.a_const = 0;
                 ep.ga[l] = 0;
                 ep.b_const = 1;

@@ -270,7 +270,11 @@ void make_twiddles(int n, std::vector<double2>& tw);
 // operator products (apply.cpp); OP_CURL: h = G^-1 (h_t + K x) with the
 // curl operator, h_t passed as rhs (complex128, PWL basis)
 // OP_K: y = K x, the raw curl product (the J-M product's coupling blocks)
-enum { OP_PREC = 0, OP_A = 1, OP_N = 2, OP_RESID = 3, OP_CURL = 4, OP_K = 5 };
+// OP_JMS: the J-M coupled sums over nrhs / 2 vector pairs (x_j, x_m) =
+// vectors (2 r, 2 r + 1): y_j = N x_j - c_e K x_m, y_m = N x_m + c_m K x_j,
+// in one pass of the FFTs (only where jm_fused_supported)
+enum { OP_PREC = 0, OP_A = 1, OP_N = 2, OP_RESID = 3, OP_CURL = 4, OP_K = 5, OP_JMS = 6 };
+bool jm_fused_supported(const Ctx& c, size_t es);
 // ws_ext: caller-owned workspace of ws_cap bytes for the FFT intermediates
 // (VIE_EINVAL when the product needs more); nullptr: the context's own,
 // grown on demand

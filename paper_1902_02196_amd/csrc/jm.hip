@@ -13,9 +13,12 @@
 //
 //   P^-1 A x = [x_j - tau_e G^-1 (N x_j - c_e K x_m); x_m - tau_m G^-1 (N x_m + c_m K x_j)].
 //
-// A vector [nrhs][24][V] is read as 2 nrhs vectors of 12 components, so the
-// product is one N product and one K product over them (the five-pass
-// pipeline with N's and K's x passes), then one elementwise pass.
+// A vector [nrhs][24][V] is read as 2 nrhs vectors of 12 components.  Where
+// the x length has a compiled J-M x pass, the FFT passes run once over them
+// and the x pass forms both coupled sums, N x_j - c_e K x_m and N x_m + c_m
+// K x_j, from the two halves of a pencil together; elsewhere the product is
+// one N product and one K product over the 2 nrhs vectors.  Then one
+// elementwise pass applies the materials.
 #include <algorithm>
 #include <vector>
 
@@ -49,10 +52,14 @@ __global__ void __launch_bounds__(256) k_jm_combine(int op, const C<R>* __restri
         const R G = (a & 3) ? g1 : g0;
         const long long ij = r * 2 * V12 + rem, im = ij + V12;
         const C<R> xj = x[ij], xm = x[im];
-        // N x_j - c_e K x_m and N x_m + c_m K x_j, c = i w (eps0 | mu0)
-        const C<R> Nj = wN[ij], Nm = wN[im], Kj = wK[ij], Km = wK[im];
-        const C<R> sj = mk<R>(Nj.x + wce * Km.y, Nj.y - wce * Km.x);
-        const C<R> sm = mk<R>(Nm.x - wcm * Kj.y, Nm.y + wcm * Kj.x);
+        // N x_j - c_e K x_m and N x_m + c_m K x_j, c = i w (eps0 | mu0):
+        // from the separate products, or formed by the fused x pass (wK null)
+        C<R> sj = wN[ij], sm = wN[im];
+        if (wK) {
+            const C<R> Kj = wK[ij], Km = wK[im];
+            sj = mk<R>(sj.x + wce * Km.y, sj.y - wce * Km.x);
+            sm = mk<R>(sm.x - wcm * Kj.y, sm.y + wcm * Kj.x);
+        }
         C<R> yj, ym;
         if (op == OP_A) {
             yj = csub(cscale(cmul(m.epsr[v], xj), G), cmul(m.chie[v], sj));
@@ -104,11 +111,16 @@ void apply_jm(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs,
     const long long V = c.V;
     const size_t half = (size_t)nrhs * 24 * V;   // elements of one product over the 2 nrhs halves
     C<R>* wN = static_cast<C<R>*>(c.jmbuf.get(2 * half * sizeof(C<R>)));
-    C<R>* wK = wN + half;
+    C<R>* wK = nullptr;
     {
         NcGuard g(c, 12);
-        apply_op<R>(c, OP_N, 2 * nrhs, x, wN, nullptr);
-        apply_op<R>(c, OP_K, 2 * nrhs, x, wK, nullptr);
+        if (jm_fused_supported(c, sizeof(C<R>))) {
+            apply_op<R>(c, OP_JMS, 2 * nrhs, x, wN, nullptr);
+        } else {
+            wK = wN + half;
+            apply_op<R>(c, OP_N, 2 * nrhs, x, wN, nullptr);
+            apply_op<R>(c, OP_K, 2 * nrhs, x, wK, nullptr);
+        }
     }
     JmMat<R> m;
     if constexpr (sizeof(R) == 4) {
@@ -121,6 +133,13 @@ void apply_jm(Ctx& c, int op, int nrhs, const C<R>* x, C<R>* y, const C<R>* rhs,
     hipLaunchKernelGGL((k_jm_combine<R>), dim3(grid_for(n)), dim3(256), 0, c.stream, op, x, wN, wK, rhs, y, m,
                        R(dv), R(dv / 12), R(c.omega * kEps0), R(c.omega * kMu0), V, n);
     VIE_HIP(hipGetLastError());
+}
+
+bool jm_fused_supported(const Ctx& c, size_t es) {
+    const int Mx = c.M[0];
+    if (!p3_ct_supported(Mx) || 2 * c.N[0] > Mx) return false;
+    if (es == sizeof(C<double>) && Mx > 128) return false;
+    return ((size_t)Mx + (size_t)lds_pad(24 * Mx) + 2) * es <= 160 * 1024;
 }
 
 template void apply_jm<float>(Ctx&, int, int, const C<float>*, C<float>*, const C<float>*, void*, size_t);

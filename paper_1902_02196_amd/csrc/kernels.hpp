@@ -37,6 +37,13 @@ void launch_p3_pwc(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hi
 // x pass of the curl operator K (U the [Oz][Oy][30][Ox] octant)
 template <typename R>
 void launch_p3_curl(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s);
+// x pass of the J-M product: the coupled sums s_j = N x_j + kj K x_m and
+// s_m = N x_m + km K x_j of the vector pairs (2 r, 2 r + 1), p.nrhs pairs (UN
+// the 60-tensor octant, UK the 30-tensor curl octant); false when the length
+// along x has no compiled kernel (the caller then composes the two products)
+template <typename R>
+bool launch_p3_jm(C<R>* A, const C<R>* UN, const C<R>* UK, const P3Params& p, const C<R>* tw, C<R> kj, C<R> km,
+                  hipStream_t s);
 bool p3_ct_supported(int n);
 int p3_ct_groups(int es, int n);
 bool p3_ct_fits(int es, int n);

@@ -644,12 +644,12 @@ __device__ __forceinline__ void orbit_apply2(C<R>* y0, C<R>* y1, const C<R>* x0,
     }
 }
 
-template <typename R, int E>
+template <typename R, int E, int EEND = 60>
 __device__ __forceinline__ void orbit_product2(C<R>* y0, C<R>* y1, const C<R>* x0, const C<R>* x1,
                                                const C<R>* __restrict__ Ur, int ox, int OXs) {
-    if constexpr (E < 60) {
+    if constexpr (E < EEND) {
         orbit_apply2<R, E, 0>(y0, y1, x0, x1, Ur[E * OXs + ox]);
-        orbit_product2<R, E + 1>(y0, y1, x0, x1, Ur, ox, OXs);
+        orbit_product2<R, E + 1, EEND>(y0, y1, x0, x1, Ur, ox, OXs);
     }
 }
 
@@ -754,6 +754,179 @@ __global__ void __launch_bounds__(kP3QuadThreads) k_p3_quad(C<R>* __restrict__ A
     __syncthreads();
     ct_passes<R, false, N, 0, 1, NT, 48, false, true>(buf, twl, nrows, N, tid);   // crop to Nx
     lds_to_rows<R, N, NT>(buf, nrows, p.Nx, rowp);
+}
+
+// x pass of the J-M product (24 unknowns per voxel, Sec. II eq. 15): one
+// workgroup per (octant row, right-hand side, sibling) holds the 12 rows of
+// the electric half x_j and the 12 of the magnetic half x_m of its pencil
+// (24 rows in LDS), and per frequency forms both coupled sums
+//
+//   s_j = N x_j + kj K x_m,   kj = -c_e = -i w eps0
+//   s_m = N x_m + km K x_j,   km = +c_m = +i w mu0
+//
+// one work item per frequency: the 30 curl tensors first, each applied to
+// both halves (K x_m into s_j, K x_j into s_m), the factors kj and km, then
+// the 60 N tensors, each applied to both halves.  Fold signs as in the other
+// x passes: D on the inputs and outputs of both blocks, and the curl's extra
+// sign (-1)^(fx + fy + fz) (odd under reflection) goes into the factors.
+// The two halves of right-hand side r are the vectors 2 r and 2 r + 1 of the
+// buffer (stride s_r).
+struct CurlOrbits {
+    OrbitMember m[30][4];
+    int cnt[30];
+};
+constexpr CurlOrbits make_curl_orbits() {
+    CurlOrbits o{};
+    for (int e = 0; e < 30; ++e) o.cnt[e] = 0;
+    for (int a = 0; a < 12; ++a)
+        for (int b = 0; b < 12; ++b) {
+            const int sg = curl_unique_sign(a, b);
+            if (sg == 0) continue;
+            const int e = curl_unique_index(a, b);
+            o.m[e][o.cnt[e]] = OrbitMember{a, b, sg};
+            o.cnt[e]++;
+        }
+    return o;
+}
+
+template <typename R, int E, int K>
+__device__ __forceinline__ void curl_orbit_apply2(C<R>* y0, C<R>* y1, const C<R>* x0, const C<R>* x1, C<R> u) {
+    constexpr CurlOrbits o = make_curl_orbits();
+    if constexpr (K < o.cnt[E]) {
+        constexpr int a = o.m[E][K].a, b = o.m[E][K].b, sg = o.m[E][K].s;
+        const C<R> us = sg > 0 ? u : mk<R>(-u.x, -u.y);
+        cfma(y0[a], us, x0[b]);
+        cfma(y1[a], us, x1[b]);
+        curl_orbit_apply2<R, E, K + 1>(y0, y1, x0, x1, u);
+    }
+}
+
+template <typename R, int E>
+__device__ __forceinline__ void curl_orbit_product2(C<R>* y0, C<R>* y1, const C<R>* x0, const C<R>* x1,
+                                                    const C<R>* __restrict__ Ur, int ox, int OXs) {
+    if constexpr (E < 30) {
+        curl_orbit_apply2<R, E, 0>(y0, y1, x0, x1, Ur[E * OXs + ox]);
+        curl_orbit_product2<R, E + 1>(y0, y1, x0, x1, Ur, ox, OXs);
+    }
+}
+
+constexpr int kP3JmThreads = 256;
+
+template <typename R, int N>
+__global__ void __launch_bounds__(kP3JmThreads) k_p3_jm(C<R>* __restrict__ A, const C<R>* __restrict__ UN,
+                                                        const C<R>* __restrict__ UK, P3Params p,
+                                                        const C<R>* __restrict__ tw, C<R> kj, C<R> km) {
+    constexpr int NT = kP3JmThreads;
+    constexpr int OX = N / 2 + 1;
+    extern __shared__ unsigned char smem_raw[];
+    C<R>* twl = reinterpret_cast<C<R>*>(smem_raw);
+    C<R>* buf = twl + N;
+    const int tid = threadIdx.x;
+    // block -> (octant row, right-hand side, sibling); the 4 nrhs workgroups
+    // of one operator row get indices congruent modulo 8 (one XCD, one L2)
+    const int K = 4 * p.nrhs;
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+    const int row = (q / K) * 8 + xcd;
+    if (row >= p.Oy * p.Oz) return;       // padding rows, uniform over the workgroup
+    const int kk = q - (q / K) * K;
+    const int r = kk >> 2, sib = kk & 3;
+    const int oz = row / p.Oy, oy = row - oz * p.Oy;
+    const int ny_sib = (oy == 0 || 2 * oy == p.My) ? 1 : 2;
+    const int nz_sib = (oz == 0 || 2 * oz == p.Mz) ? 1 : 2;
+    if (sib >= ny_sib * nz_sib) return;   // uniform over the workgroup
+    const int sz = sib / ny_sib, sy = sib - sz * ny_sib;
+    const int z = sz ? p.Mz - oz : oz;
+    const int y = sy ? p.My - oy : oy;
+    // LDS row h * 12 + c: half h (0 electric, 1 magnetic), component c
+    C<R>* base = A + (long long)(2 * r) * p.s_r + (long long)z * p.s_z + (long long)y * p.s_y;
+    const long long s_c = p.s_c, s_r = p.s_r;
+    auto rowp = [=](int rr) {
+        const int h = rr >= 12, c = rr - 12 * h;
+        return base + h * s_r + c * s_c;
+    };
+    for (int m = tid; m < N; m += NT) twl[m] = tw[m];
+    rows_to_lds<R, N, NT>(buf, 24, p.Nx, rowp);
+    __syncthreads();
+    ct_passes<R, true, N, 0, 1, NT, 24, true>(buf, twl, 24, N, tid);   // Nx <= N / 2
+    {
+        const C<R>* Un = UN + (long long)row * 60 * OX;
+        const C<R>* Uk = UK + (long long)row * 30 * OX;
+        // LDS address of (row, column xi): one column base plus a constant
+        // per row when rows are whole 16-element blocks (no per-row index
+        // arithmetic, no per-row address registers)
+        auto at = [&](int rr, int xi) -> C<R>& {
+            if constexpr (N % 16 == 0) return buf[rr * (N + N / 16) + xi + (xi >> 4)];
+            else return buf[lds_pad(rr * N + xi)];
+        };
+        // sign flip of both parts where bit a of m is set (no branches)
+        auto flip = [](C<R> v, unsigned m, int a) {
+            if constexpr (sizeof(R) == 4) {
+                const unsigned f = ((m >> a) & 1u) << 31;
+                v.x = __uint_as_float(__float_as_uint(v.x) ^ f);
+                v.y = __uint_as_float(__float_as_uint(v.y) ^ f);
+            } else {
+                const unsigned long long f = (unsigned long long)((m >> a) & 1u) << 63;
+                v.x = __longlong_as_double(__double_as_longlong(v.x) ^ f);
+                v.y = __longlong_as_double(__double_as_longlong(v.y) ^ f);
+            }
+            return v;
+        };
+        for (int xi = tid; xi < N; xi += NT) {
+            const int fx = 2 * xi > N;
+            const int ox = fx ? N - xi : xi;
+            const unsigned mask = fold_mask(fx, sy, sz);
+            const bool odd = (fx + sy + sz) & 1;
+            C<R> xj[12], xm[12], yj[12], ym[12];
+#pragma unroll
+            for (int a = 0; a < 12; ++a) {
+                xj[a] = flip(at(a, xi), mask, a);
+                xm[a] = flip(at(12 + a, xi), mask, a);
+                yj[a] = mk<R>(0, 0);
+                ym[a] = mk<R>(0, 0);
+            }
+            curl_orbit_product2<R, 0>(yj, ym, xm, xj, Uk, ox, OX);   // K x_m -> s_j, K x_j -> s_m
+            const C<R> fj = odd ? mk<R>(-kj.x, -kj.y) : kj, fm = odd ? mk<R>(-km.x, -km.y) : km;
+#pragma unroll
+            for (int a = 0; a < 12; ++a) {
+                yj[a] = cmul(fj, yj[a]);
+                ym[a] = cmul(fm, ym[a]);
+            }
+            orbit_product2<R, 0>(yj, ym, xj, xm, Un, ox, OX);
+#pragma unroll
+            for (int a = 0; a < 12; ++a) {   // own column: in place
+                at(a, xi) = flip(yj[a], mask, a);
+                at(12 + a, xi) = flip(ym[a], mask, a);
+            }
+        }
+    }
+    __syncthreads();
+    ct_passes<R, false, N, 0, 1, NT, 24, false, true>(buf, twl, 24, N, tid);   // crop to Nx
+    lds_to_rows<R, N, NT>(buf, 24, p.Nx, rowp);
+}
+
+// compiled for complex64 at every length of the list, for complex128 up to
+// 128 (beyond, its 24 rows of butterflies would not stay in registers)
+template <typename R, int N>
+static bool launch_p3_jm_n(C<R>* A, const C<R>* UN, const C<R>* UK, const P3Params& p, const C<R>* tw, C<R> kj,
+                           C<R> km, hipStream_t s) {
+    if constexpr (sizeof(R) == 8 && N > 128) {
+        return false;
+    } else {
+    const size_t lds = ((size_t)N + lds_pad(24 * N) + 2) * sizeof(C<R>);
+    if (lds > 160 * 1024) return false;
+    const long long rows8 = ((long long)p.Oy * p.Oz + 7) / 8 * 8;
+    const long long nblk = rows8 * 4LL * p.nrhs;
+    VIE_REQUIRE(nblk < (1LL << 31), -1, "J-M x pass: too many workgroups");
+    static std::once_flag once;
+    std::call_once(once, [&] {
+        (void)hipFuncSetAttribute((const void*)k_p3_jm<R, N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    });
+    timed_launch(k_p3_jm<R, N>, dim3((unsigned)nblk), dim3(kP3JmThreads), (unsigned)lds, s, A, UN, UK, p, tw, kj,
+                 km);
+    VIE_HIP(hipGetLastError());
+    return true;
+    }
 }
 
 // x pass of the PWC basis (3 unknowns per voxel, the pulse functions): one
@@ -1084,6 +1257,25 @@ void launch_p3_curl(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, h
 }
 template void launch_p3_curl<float>(C<float>*, const C<float>*, const P3Params&, const C<float>*, hipStream_t);
 template void launch_p3_curl<double>(C<double>*, const C<double>*, const P3Params&, const C<double>*, hipStream_t);
+
+template <typename R>
+bool launch_p3_jm(C<R>* A, const C<R>* UN, const C<R>* UK, const P3Params& p, const C<R>* tw, C<R> kj, C<R> km,
+                  hipStream_t s) {
+    if (2 * p.Nx > p.plan.n) return false;
+    switch (p.plan.n) {
+#define CASE(n_)                                                       \
+    case n_:                                                          \
+        return launch_p3_jm_n<R, n_>(A, UN, UK, p, tw, kj, km, s);
+        VIE_P3_LENGTHS(CASE)
+#undef CASE
+        default: break;
+    }
+    return false;
+}
+template bool launch_p3_jm<float>(C<float>*, const C<float>*, const C<float>*, const P3Params&, const C<float>*,
+                                  C<float>, C<float>, hipStream_t);
+template bool launch_p3_jm<double>(C<double>*, const C<double>*, const C<double>*, const P3Params&,
+                                   const C<double>*, C<double>, C<double>, hipStream_t);
 
 template <typename R>
 void launch_p3_pwc(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {

@@ -10,6 +10,11 @@ GPU against the oracle (``oracle/jm.py``), through the C ABI:
 * a magneto-dielectric sphere: the device's solution and absorbed power
   against the oracle's FFT-GMRES, and the power against the Mie series of
   the permeable sphere;
+* the x pass that forms both coupled sums together (x lengths with a
+  compiled kernel: 8, 16, ..., here 8, 16 and 128) against the oracle on
+  small grids, in solves against dense LU, and at 64^3 (the benchmark's
+  grid) by unit currents: output voxel m of A e_(n0, a) is column a of the
+  oracle's N and K blocks at m - n0 times the materials at m (eq. 15);
 * refusals.
 """
 import functools
@@ -87,7 +92,8 @@ def _oracle_materials(e, s, mre, mim):
     return er, er - 1, mr, mr - 1, (er - 1) / er, (mr - 1) / mr
 
 
-@pytest.mark.parametrize("N,D", [((5, 4, 6), (0.005, 0.004, 0.006)), ((3, 5, 2), (0.004, 0.006, 0.005))])
+@pytest.mark.parametrize("N,D", [((5, 4, 6), (0.005, 0.004, 0.006)), ((3, 5, 2), (0.004, 0.006, 0.005)),
+                                 ((4, 5, 3), (0.005, 0.004, 0.006)), ((8, 3, 5), (0.004, 0.006, 0.005))])
 def test_jm_products_match_oracle(vie, torch, N, D):
     _say("J-M products %s" % (N,))
     TN, TK = _blocks(N, D)
@@ -124,9 +130,10 @@ def test_jm_incident_and_rhs(vie, torch):
     assert relerr(_from_lib(b.cpu().numpy())[0], bref) < 1e-12
 
 
+@pytest.mark.parametrize("N", [(3, 3, 2), (4, 3, 2)])
 @pytest.mark.parametrize("mode,tol,bound", [(0, 1e-12, 1e-9), (1, 1e-10, 1e-7)])
-def test_jm_solve_matches_dense(vie, torch, mode, tol, bound):
-    N, D = (3, 3, 2), (0.005, 0.006, 0.004)
+def test_jm_solve_matches_dense(vie, torch, mode, tol, bound, N):
+    D = (0.005, 0.006, 0.004)
     TN, TK = _blocks(N, D)
     e, s, mre, mim = _random_materials(N, 23)
     er, chie, mr, chim, taue, taum = _oracle_materials(e, s, mre, mim)
@@ -215,6 +222,53 @@ def test_jm_magnetodielectric_sphere(vie, torch):
     c.fields(x, f)
     fh = _from_lib(f.cpu().numpy())[0]
     assert relerr(fh, jm.fields(_from_lib(x.cpu().numpy())[0], chie, chim, F)) < 1e-12
+
+
+def test_jm_delta_columns_full_size(vie, torch):
+    """64^3 at 3 mm (the benchmark's grid, the fused x pass at length 128),
+    magneto-dielectric phantom: unit currents in both halves, A applied in
+    both precisions, sampled outputs against the oracle's blocks."""
+    N, D = (64, 64, 64), (0.003,) * 3
+    e, s, mre, mim = vi.magnetic_phantom(N, D, vi.BASE_SEED + 1)
+    er, mr = physics.eps_r(e, s, F), physics.mu_r(mre, mim)
+    chie, chim = er - 1, mr - 1
+    c = _jm_ctx(vie, N, D, e, s, mre, mim)
+    G = physics.gram_vector(*D)
+    ce, cm = physics.c_e(F), physics.c_m(F)
+    # (n0 (ix, iy, iz), component a, half h)
+    sources = [((31, 32, 30), 5, 0), ((0, 63, 17), 0, 1), ((63, 10, 40), 11, 0), ((20, 45, 2), 7, 1)]
+    g = vi.rng(7101)
+    for dtype, tol in ((torch.complex128, 1e-10), (torch.complex64, 2e-5)):
+        x = torch.zeros((len(sources), 24, N[2], N[1], N[0]), dtype=dtype, device="cuda")
+        for r, (n0, a, h) in enumerate(sources):
+            x[r, 12 * h + a, n0[2], n0[1], n0[0]] = 1.0
+        y = torch.empty_like(x)
+        c.apply(x, y, op=vie.OP_A)
+        worst = 0.0
+        for r, (n0, a, h) in enumerate(sources):
+            ms = {tuple(n0), tuple(int(np.clip(n0[i] + 1, 0, N[i] - 1)) for i in range(3))}
+            while len(ms) < 10:
+                ms.add(tuple(int(g.integers(0, N[i])) for i in range(3)))
+            ms = sorted(ms)
+            offs = np.array([[m[i] - n0[i] for i in range(3)] for m in ms])
+            NB = toeplitz.galerkin_blocks(offs, D, K)[:, :, a]
+            KB = toeplitz.galerkin_blocks(offs, D, K, part='K')[:, :, a]
+            ref = np.zeros((len(ms), 24), dtype=np.complex128)
+            for k, m in enumerate(ms):
+                self_ = np.zeros(12, dtype=np.complex128)
+                if tuple(m) == tuple(n0):
+                    self_[a] = G[a]
+                if h == 0:
+                    ref[k, :12] = er[m] * self_ - chie[m] * NB[k]
+                    ref[k, 12:] = -chim[m] * cm * KB[k]
+                else:
+                    ref[k, :12] = chie[m] * ce * KB[k]
+                    ref[k, 12:] = mr[m] * self_ - chim[m] * NB[k]
+            got = np.stack([y[r, :, m[2], m[1], m[0]].cpu().numpy().astype(np.complex128) for m in ms])
+            err = float(np.abs(got - ref).max() / np.abs(ref).max())
+            worst = max(worst, err)
+            assert err < tol, (dtype, r, err)
+        _say("  64^3 J-M %s: worst sampled error %.3e" % (dtype, worst))
 
 
 def test_jm_refusals(vie, torch):
