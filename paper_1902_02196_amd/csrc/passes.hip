@@ -764,9 +764,9 @@ __global__ void __launch_bounds__(kP3QuadThreads) k_p3_quad(C<R>* __restrict__ A
 //   s_j = N x_j + kj K x_m,   kj = -c_e = -i w eps0
 //   s_m = N x_m + km K x_j,   km = +c_m = +i w mu0
 //
-// one work item per frequency: the 30 curl tensors first, each applied to
-// both halves (K x_m into s_j, K x_j into s_m), the factors kj and km, then
-// the 60 N tensors, each applied to both halves.  Fold signs as in the other
+// two work items per frequency, one per half: the 30 curl tensors applied
+// to the other half, the factor (kj or km), then the 60 N tensors applied
+// to its own half.  Fold signs as in the other
 // x passes: D on the inputs and outputs of both blocks, and the curl's extra
 // sign (-1)^(fx + fy + fz) (odd under reflection) goes into the factors.
 // The two halves of right-hand side r are the vectors 2 r and 2 r + 1 of the
@@ -790,23 +790,22 @@ constexpr CurlOrbits make_curl_orbits() {
 }
 
 template <typename R, int E, int K>
-__device__ __forceinline__ void curl_orbit_apply2(C<R>* y0, C<R>* y1, const C<R>* x0, const C<R>* x1, C<R> u) {
+__device__ __forceinline__ void curl_orbit_apply(C<R>* yv, const C<R>* xv, C<R> u) {
     constexpr CurlOrbits o = make_curl_orbits();
     if constexpr (K < o.cnt[E]) {
         constexpr int a = o.m[E][K].a, b = o.m[E][K].b, sg = o.m[E][K].s;
-        const C<R> us = sg > 0 ? u : mk<R>(-u.x, -u.y);
-        cfma(y0[a], us, x0[b]);
-        cfma(y1[a], us, x1[b]);
-        curl_orbit_apply2<R, E, K + 1>(y0, y1, x0, x1, u);
+        if constexpr (sg > 0) cfma(yv[a], u, xv[b]);
+        else cfma(yv[a], mk<R>(-u.x, -u.y), xv[b]);
+        curl_orbit_apply<R, E, K + 1>(yv, xv, u);
     }
 }
 
 template <typename R, int E>
-__device__ __forceinline__ void curl_orbit_product2(C<R>* y0, C<R>* y1, const C<R>* x0, const C<R>* x1,
-                                                    const C<R>* __restrict__ Ur, int ox, int OXs) {
+__device__ __forceinline__ void curl_orbit_product(C<R>* yv, const C<R>* xv, const C<R>* __restrict__ Ur, int ox,
+                                                   int OXs) {
     if constexpr (E < 30) {
-        curl_orbit_apply2<R, E, 0>(y0, y1, x0, x1, Ur[E * OXs + ox]);
-        curl_orbit_product2<R, E + 1>(y0, y1, x0, x1, Ur, ox, OXs);
+        curl_orbit_apply<R, E, 0>(yv, xv, Ur[E * OXs + ox]);
+        curl_orbit_product<R, E + 1>(yv, xv, Ur, ox, OXs);
     }
 }
 
@@ -871,31 +870,36 @@ __global__ void __launch_bounds__(kP3JmThreads) k_p3_jm(C<R>* __restrict__ A, co
             }
             return v;
         };
-        for (int xi = tid; xi < N; xi += NT) {
+        // two work items per frequency, item h forming the sum of half h
+        // from both halves' inputs; each round reads its columns, waits,
+        // then writes them (the rounds' columns are disjoint)
+        for (int w0 = 0; w0 < 2 * N; w0 += NT) {
+            const int w = w0 + tid;
+            const bool act = w < 2 * N;
+            const int xi = w >> 1, h = w & 1;
             const int fx = 2 * xi > N;
             const int ox = fx ? N - xi : xi;
             const unsigned mask = fold_mask(fx, sy, sz);
             const bool odd = (fx + sy + sz) & 1;
-            C<R> xj[12], xm[12], yj[12], ym[12];
+            C<R> xo[12], xt[12], yv[12];
+            if (act) {
 #pragma unroll
-            for (int a = 0; a < 12; ++a) {
-                xj[a] = flip(at(a, xi), mask, a);
-                xm[a] = flip(at(12 + a, xi), mask, a);
-                yj[a] = mk<R>(0, 0);
-                ym[a] = mk<R>(0, 0);
+                for (int a = 0; a < 12; ++a) {
+                    xo[a] = flip(at(12 * h + a, xi), mask, a);
+                    xt[a] = flip(at(12 - 12 * h + a, xi), mask, a);
+                    yv[a] = mk<R>(0, 0);
+                }
+                curl_orbit_product<R, 0>(yv, xt, Uk, ox, OX);   // K x_other
+                C<R> f = h ? km : kj;
+                if (odd) f = mk<R>(-f.x, -f.y);
+#pragma unroll
+                for (int a = 0; a < 12; ++a) yv[a] = cmul(f, yv[a]);
+                orbit_product<R, 0>(yv, xo, Un, ox, OX);        // + N x_own
             }
-            curl_orbit_product2<R, 0>(yj, ym, xm, xj, Uk, ox, OX);   // K x_m -> s_j, K x_j -> s_m
-            const C<R> fj = odd ? mk<R>(-kj.x, -kj.y) : kj, fm = odd ? mk<R>(-km.x, -km.y) : km;
+            __syncthreads();
+            if (act) {
 #pragma unroll
-            for (int a = 0; a < 12; ++a) {
-                yj[a] = cmul(fj, yj[a]);
-                ym[a] = cmul(fm, ym[a]);
-            }
-            orbit_product2<R, 0>(yj, ym, xj, xm, Un, ox, OX);
-#pragma unroll
-            for (int a = 0; a < 12; ++a) {   // own column: in place
-                at(a, xi) = flip(yj[a], mask, a);
-                at(12 + a, xi) = flip(ym[a], mask, a);
+                for (int a = 0; a < 12; ++a) at(12 * h + a, xi) = flip(yv[a], mask, a);
             }
         }
     }
