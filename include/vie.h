@@ -406,7 +406,8 @@ int vie_autotune(vie_ctx* ctx, int precision, int nrhs, int* choice, double* bes
  * earlier vie_autotune returned: choice = {variant (0 staged operator row,
  * 1 one pencil group per workgroup, 2 the sibling pencil groups of a row per
  * workgroup, complex64 only, 3 as 1 with the operator row prefetched into
- * LDS, fft length <= 128 along x, 4 as 1 with two threads per frequency),
+ * LDS, fft length <= 128 along x, 4 as 1 with two threads per frequency,
+ * 5 the pencils of two right-hand sides per workgroup),
  * workgroups per row (1, 2, 4; variant 0),
  * z tile, y tile (pencils per workgroup of the strided passes: 8 or 16, or
  * 32 where the fft length has a compiled kernel)}.  VIE_EINVAL for shapes

@@ -694,7 +694,9 @@ int vie_set_tuning(vie_ctx* ctx, int precision, int nrhs, const int* choice) {
         t.p3_sib_blocks = choice[1];
         t.tile_z = choice[2];
         t.tile_y = choice[3];
-        VIE_REQUIRE(t.p3_variant >= 0 && t.p3_variant <= 4, VIE_EINVAL, "unknown x-pass variant");
+        VIE_REQUIRE(t.p3_variant >= 0 && t.p3_variant <= 5, VIE_EINVAL, "unknown x-pass variant");
+        VIE_REQUIRE(t.p3_variant != 5 || p3_pair_fits(es, c.M[0]), VIE_EINVAL,
+                    "the right-hand-side pair variant needs a compiled x length whose 24 rows fit LDS");
         VIE_REQUIRE(t.p3_variant != 0 || !p3_ct_supported(c.M[0]) || p3_ct_fits(es, c.M[0]), VIE_EINVAL,
                     "x-pass variant 0 does not fit LDS for this fft length and precision");
         VIE_REQUIRE(t.p3_variant != 3 || p3_pref_fits(c.M[0]), VIE_EINVAL,

@@ -48,6 +48,7 @@ bool p3_ct_supported(int n);
 int p3_ct_groups(int es, int n);
 bool p3_ct_fits(int es, int n);
 bool p3_quad_fits(int es, int n);
+bool p3_pair_fits(int es, int n);
 bool p3_pref_fits(int n);
 // strided.hip: compiled-length strided passes; false when (length, tile)
 // has no compiled kernel

@@ -542,6 +542,80 @@ __global__ void __launch_bounds__(kP3SmallThreads) k_p3_small(C<R>* __restrict__
     lds_to_rows<R, N, NT>(buf, 12, p.Nx, rowp);
 }
 
+// Right-hand-side pairs (variant 5, for batches): as the light variant, but
+// a workgroup holds the pencils of two right-hand sides (the same sibling of
+// the same octant row, 24 rows in LDS; the last of an odd batch holds one)
+// and runs two work items per frequency, one per right-hand side.  The two
+// items of a frequency sit in neighbouring lanes and read the same operator
+// values in one load instruction, so the operator is read from L2 half as
+// often as by the light variant, and every thread works in the product.
+template <typename R, int N>
+__global__ void __launch_bounds__(kP3SmallThreads) k_p3_pair(C<R>* __restrict__ A, const C<R>* __restrict__ U,
+                                                             P3Params p, const C<R>* __restrict__ tw) {
+    constexpr int NT = kP3SmallThreads;
+    constexpr int OX = N / 2 + 1;
+    extern __shared__ unsigned char smem_raw[];
+    C<R>* twl = reinterpret_cast<C<R>*>(smem_raw);
+    C<R>* buf = twl + N;
+    const int tid = threadIdx.x;
+    // block -> (octant row, right-hand-side pair, sibling); the 4 npairs
+    // workgroups of one operator row get indices congruent modulo 8
+    const int npairs = (p.nrhs + 1) >> 1;
+    const int K = 4 * npairs;
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+    const int row = (q / K) * 8 + xcd;
+    if (row >= p.Oy * p.Oz) return;       // padding rows, uniform over the workgroup
+    const int kk = q - (q / K) * K;
+    const int pr = kk >> 2, sib = kk & 3;
+    const int oz = row / p.Oy, oy = row - oz * p.Oy;
+    const int ny_sib = (oy == 0 || 2 * oy == p.My) ? 1 : 2;
+    const int nz_sib = (oz == 0 || 2 * oz == p.Mz) ? 1 : 2;
+    if (sib >= ny_sib * nz_sib) return;   // uniform over the workgroup
+    const int sz = sib / ny_sib, sy = sib - sz * ny_sib;
+    const int z = sz ? p.Mz - oz : oz;
+    const int y = sy ? p.My - oy : oy;
+    const int nr = min(2, p.nrhs - 2 * pr);   // right-hand sides held (1 or 2)
+    C<R>* base = A + (long long)(2 * pr) * p.s_r + (long long)z * p.s_z + (long long)y * p.s_y;
+    const long long s_c = p.s_c, s_r = p.s_r;
+    auto rowp = [=](int rr) {   // LDS row h * 12 + c: right-hand side 2 pr + h, component c
+        const int h = rr >= 12, c = rr - 12 * h;
+        return base + h * s_r + c * s_c;
+    };
+    for (int m = tid; m < N; m += NT) twl[m] = tw[m];
+    rows_to_lds<R, N, NT>(buf, 12 * nr, p.Nx, rowp);
+    __syncthreads();
+    ct_passes<R, true, N, 0, 1, NT, 24, true>(buf, twl, 12 * nr, N, tid);   // Nx <= N / 2
+    {
+        const C<R>* Ur = U + (long long)row * 60 * OX;
+        // each item reads and writes only its own rows of its own column
+        for (int w = tid; w < 2 * N; w += NT) {
+            const int xi = w >> 1, h = w & 1;
+            if (h >= nr) continue;
+            const int fx = 2 * xi > N;
+            const int ox = fx ? N - xi : xi;
+            const unsigned mask = fold_mask(fx, sy, sz);
+            C<R> xv[12], yv[12];
+#pragma unroll
+            for (int a = 0; a < 12; ++a) {
+                C<R> v = buf[lds_pad((12 * h + a) * N + xi)];
+                if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                xv[a] = v;
+                yv[a] = mk<R>(0, 0);
+            }
+            orbit_product<R, 0>(yv, xv, Ur, ox, OX);
+#pragma unroll
+            for (int a = 0; a < 12; ++a) {
+                C<R> v = yv[a];
+                if (mask & (1u << a)) { v.x = -v.x; v.y = -v.y; }
+                buf[lds_pad((12 * h + a) * N + xi)] = v;
+            }
+        }
+    }
+    __syncthreads();
+    ct_passes<R, false, N, 0, 1, NT, 24, false, true>(buf, twl, 12 * nr, N, tid);   // crop to Nx
+    lds_to_rows<R, N, NT>(buf, 12 * nr, p.Nx, rowp);
+}
+
 // Prefetching variant of the light x pass (fft lengths up to 128): as the
 // light variant, but the workgroup first issues the loads of its operator row
 // (60 Ox values, contiguous) into registers, so that they are in flight
@@ -1054,6 +1128,22 @@ static void launch_p3_small_n(C<R>* A, const C<R>* U, const P3Params& p, const C
 }
 
 template <typename R, int N>
+static void launch_p3_pair_n(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
+    const size_t lds = ((size_t)N + lds_pad(24 * N) + 2) * sizeof(C<R>);
+    const long long rows8 = ((long long)p.Oy * p.Oz + 7) / 8 * 8;
+    const long long nblk = rows8 * 4LL * ((p.nrhs + 1) / 2);
+    VIE_REQUIRE(nblk < (1LL << 31), -1, "x pass: too many workgroups");
+    VIE_REQUIRE(lds <= 160 * 1024, -1, "x pass: pair variant does not fit LDS");
+    static std::once_flag once;
+    std::call_once(once, [&] {
+        (void)hipFuncSetAttribute((const void*)k_p3_pair<R, N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    });
+    timed_launch(k_p3_pair<R, N>, dim3((unsigned)nblk), dim3(kP3SmallThreads), (unsigned)lds, s, A, U, p, tw);
+    VIE_HIP(hipGetLastError());
+}
+
+template <typename R, int N>
 static void launch_p3_quad_n(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
     const size_t lds = ((size_t)N + lds_pad(48 * N) + 2) * sizeof(C<R>);
     const long long rows8 = ((long long)p.Oy * p.Oz + 7) / 8 * 8;
@@ -1113,6 +1203,10 @@ template <typename R, int N>
 static void launch_p3_quad(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStream_t s) {
     if constexpr (sizeof(R) == 4) launch_p3_quad_n<R, N>(A, U, p, tw, s);
     else throw Error(-1, "x pass: sibling variant is complex64 only");
+}
+
+bool p3_pair_fits(int es, int n) {
+    return p3_ct_supported(n) && ((size_t)n + (size_t)lds_pad(24 * n) + 2) * (size_t)es <= 160 * 1024;
 }
 
 bool p3_quad_fits(int es, int n) {
@@ -1214,6 +1308,7 @@ void launch_p3(C<R>* A, const C<R>* U, const P3Params& p, const C<R>* tw, hipStr
         else if (p.variant == 4) launch_p3_small_n<R, n_, 2>(A, U, p, tw, s);            \
         else if (p.variant == 2) launch_p3_quad<R, n_>(A, U, p, tw, s);                  \
         else if (p.variant == 3) launch_p3_pref<R, n_>(A, U, p, tw, s);                  \
+        else if (p.variant == 5) launch_p3_pair_n<R, n_>(A, U, p, tw, s);                \
         else launch_p3_ct_n<R, n_>(A, U, p, tw, s);                                      \
         return;
         VIE_P3_LENGTHS(CASE)

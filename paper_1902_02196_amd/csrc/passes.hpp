@@ -55,7 +55,10 @@ struct P3Params {
     unsigned magic_ox;         // fast division by Ox
     int sib_blocks;            // workgroups sharing one octant row (1, 2, 4)
     int variant;               // 0: staged operator row, 1: one pencil group per workgroup,
-                               // 2: the sibling pencil groups of a row per workgroup (complex64)
+                               // 2: the sibling pencil groups of a row per workgroup (complex64),
+                               // 3: as 1 with the operator row prefetched, 4: as 1 with two
+                               // threads per frequency, 5: the pencils of two right-hand sides
+                               // per workgroup
 };
 
 // workgroup size of the x pass: complex64 1024 threads (128 VGPRs each),

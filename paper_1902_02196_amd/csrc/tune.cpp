@@ -58,13 +58,14 @@ static Tune tune_t(Ctx& c, int nrhs, double* best_ms) {
     VIE_HIP(hipMemsetAsync(x, 0, n * sizeof(C<R>), c.stream));
     const int key0 = sizeof(R) == 4 ? 0 : 1;
     std::vector<Tune> cands;
-    for (int var = 0; var <= 4; ++var)
+    for (int var = 0; var <= 5; ++var)
         for (int sb : {1, 2, 4}) {
             if (var >= 1 && sb != 1) continue;
             if (c.nc == 3 && var != 1) continue;   // one x-pass kernel for the PWC basis: tiles only
             if (var == 0 && p3_ct_supported(c.M[0]) && !p3_ct_fits((int)sizeof(C<R>), c.M[0])) continue;
             if (var == 2 && !p3_quad_fits((int)sizeof(C<R>), c.M[0])) continue;
             if (var == 3 && !p3_pref_fits(c.M[0])) continue;
+            if (var == 5 && (nrhs < 2 || !p3_pair_fits((int)sizeof(C<R>), c.M[0]))) continue;
             for (int tz : {4, 8, 16, 32})
                 for (int ty : {4, 8, 16, 32}) {
                     Tune t;

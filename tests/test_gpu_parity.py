@@ -312,7 +312,8 @@ def test_every_launch_shape_matches_oracle(vie, torch, N):
     Ch = matvec.circulant_spectrum(T, tuple(2 * n for n in N))
     ref = [matvec.fft_N(Ch, x) for x in xs]
     x = torch.from_numpy(np.stack([vec_to_lib(v) for v in xs]))
-    shapes = [dict(variant=v, sib_blocks=sb, tile_z=tz, tile_y=ty) for v, sb in ((0, 1), (0, 2), (0, 4), (1, 1), (2, 1), (3, 1), (4, 1))
+    shapes = [dict(variant=v, sib_blocks=sb, tile_z=tz, tile_y=ty)
+              for v, sb in ((0, 1), (0, 2), (0, 4), (1, 1), (2, 1), (3, 1), (4, 1), (5, 1))
               for tz in (8, 16, 32) for ty in (8, 16, 32)]
     ran = 0
     for dtype, prec, tol in ((torch.complex64, vie.C64, 1e-5), (torch.complex128, vie.C128, 1e-11)):
