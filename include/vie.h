@@ -99,12 +99,10 @@ typedef struct {
                             dot and one update pass over the basis for both
                             (s-step Arnoldi with s = 2, the second vector
                             shifted by the Rayleigh quotient h_jj), which
-                            halves the basis reads per step; 0 (default): 2
-                            when a batch of vectors exceeds 2 MB (below, the
-                            pair's extra small kernels cost more than the
-                            halved reads), else 1.  reorth = 1 always runs
-                            single steps.  The iterates of 1 and 2 agree to
-                            rounding, not bitwise                             */
+                            halves the basis reads per step; 0 (default):
+                            2.  reorth = 1 always runs single steps.  The
+                            iterates of 1 and 2 agree to rounding, not
+                            bitwise                                           */
 } vie_solve_opts;
 
 typedef struct {

@@ -209,12 +209,10 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
             launch_pair_column(as, L.h1, L.h2, L.pc, L.col, j, na, c.stream);
             launch_givens(as, L.col, nullptr, L.npart2, nb, L.nrm, L.ivn + (j + 2), ivld, j + 1, na, c.stream);
         };
-        // s = 2 by default once a batch of vectors is large enough for the
-        // passes over the basis to stream it (below, the pair's extra small
-        // kernels cost more than the halved reads); the second Gram-Schmidt
-        // pass runs with single steps
+        // s = 2 unless asked otherwise; the second Gram-Schmidt pass runs
+        // with single steps
         const long long vec_bytes = na * n * (long long)sizeof(C<R>);
-        const bool two = (o.s_step == 2 || (o.s_step == 0 && vec_bytes > kGraphAutoBytes)) && !o.reorth && m >= 2;
+        const bool two = o.s_step != 1 && !o.reorth && m >= 2;
 
         // steps [j0, j1): launched one by one, or replayed from a graph
         // (the product's workspace is grown first, so that no step
