@@ -292,6 +292,8 @@ def main():
     ap.add_argument("--s-step", type=int, default=0,
                     help="Arnoldi steps per pass over the basis: 1 or 2 (0: the library's choice)")
     ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--tuning", default="",
+                    help="complex64 x-pass variant,sib_blocks,tile_z,tile_y installed instead of autotuning")
     ap.add_argument("--graph", type=int, default=-1,
                     help="replay the Arnoldi steps from HIP graphs (1), not (0), or when the vectors are small (-1)")
     ap.add_argument("--sync-steps", type=int, default=0,
@@ -351,7 +353,15 @@ def main():
                   "compress_s": round(t_c, 3), "expand_s": round(t_e, 3)}
         log("tucker: %s" % tucker)
     t0 = time.perf_counter()
-    tune64 = ctx.autotune(vie.C64, W.get("group", W.get("nrhs", 1)))
+    if args.tuning:
+        # a fixed complex64 launch shape instead of the timed search (runs
+        # whose counters are compared need the same kernels)
+        v = [int(t) for t in args.tuning.split(",")]
+        choice = dict(variant=v[0], sib_blocks=v[1], tile_z=v[2], tile_y=v[3])
+        ctx.set_tuning(choice, vie.C64, W.get("group", W.get("nrhs", 1)))
+        tune64 = (choice, None)
+    else:
+        tune64 = ctx.autotune(vie.C64, W.get("group", W.get("nrhs", 1)))
     tune128 = ctx.autotune(vie.C128, 1)
     t_tune = time.perf_counter() - t0
     log("autotune %.2f s: c64 %s, c128 %s" % (t_tune, tune64, tune128))
