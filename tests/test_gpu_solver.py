@@ -188,6 +188,8 @@ def test_two_step_arnoldi_matches_one_step(vie, torch, mode, restart):
         _say("  s_step %d: iterations %s, vs dense LU %s" % (s_step, its[s_step], ["%.1e" % v for v in errs]))
         assert max(errs) < (1e-8 if mode == 0 else 1e-7)
     assert its[0] in (its[1], its[2])   # the default picks one of the two forms
+    with pytest.raises(vie.VieError):
+        c.solve(etd, torch.empty_like(etd), mode=mode, tol=tol, restart=restart, s_step=3)
     for a, b in zip(its[1], its[2]):
         assert abs(a - b) <= max(4, 0.15 * a)
 
