@@ -446,10 +446,12 @@ typedef struct vie_server vie_server;
 
 /* One solve request: its own grid, tissue map (host [Nz][Ny][Nx], eps' and
  * sigma), nrhs Hertzian-dipole excitations (host [nrhs][3] positions in m and
- * current moments in A m) and solver options (mode VIE_SOLVE_*, tol <= 0 for
- * 1e-6, restart <= 0 for 50).  Inputs are copied at submission.  x_out (host
- * [nrhs][12][Nz][Ny][Nx] complex128) and p_abs_out (host [nrhs]) are optional
- * and must stay valid until the request is done. */
+ * current moments in A m), solver options (mode VIE_SOLVE_*, tol <= 0 for
+ * 1e-6, restart <= 0 for 50) and the basis (12 PWL, 3 PWC; 0 means 12).
+ * Inputs are copied at submission.  x_out (host [nrhs][basis][Nz][Ny][Nx]
+ * complex128) and p_abs_out (host [nrhs]) are optional and must stay valid
+ * until the request is done.  Admission counts the PWL footprint for either
+ * basis (an upper bound for PWC). */
 typedef struct {
     int nx, ny, nz;
     double dx, dy, dz, freq_hz;
@@ -463,6 +465,7 @@ typedef struct {
     int restart;
     double* x_out;
     double* p_abs_out;
+    int basis;
 } vie_request;
 
 typedef struct {

@@ -64,7 +64,7 @@ class TuckerInfo(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("nx", _i), ("ny", _i), ("nz", _i), ("dx", _d), ("dy", _d), ("dz", _d), ("freq_hz", _d),
                 ("eps_re", _dp), ("sigma", _dp), ("nrhs", _i), ("pos", _dp), ("moment", _dp), ("mode", _i),
-                ("tol", _d), ("restart", _i), ("x_out", _dp), ("p_abs_out", _dp)]
+                ("tol", _d), ("restart", _i), ("x_out", _dp), ("p_abs_out", _dp), ("basis", _i)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -482,8 +482,8 @@ class Server:
             pass
 
     def submit(self, N, Delta, freq_hz, eps_re, sigma, positions, moments, mode=SOLVE_FP32_IR, tol=1e-6,
-               restart=50, want_x=False):
-        """Queue one request (nrhs = number of dipoles); returns its id."""
+               restart=50, want_x=False, basis=12):
+        """Queue one request (nrhs = number of dipoles; basis 12 PWL or 3 PWC); returns its id."""
         nx, ny, nz = (int(v) for v in N)
         e = np.ascontiguousarray(eps_re, dtype=np.float64)
         sg = np.ascontiguousarray(sigma, dtype=np.float64)
@@ -495,10 +495,10 @@ class Server:
             raise ValueError("positions and moments differ in length")
         n = pos.shape[0]
         p_abs = np.zeros(n)
-        x = np.zeros((n, 12, nz, ny, nx), dtype=np.complex128) if want_x else None
+        x = np.zeros((n, int(basis), nz, ny, nx), dtype=np.complex128) if want_x else None
         r = Request(nx, ny, nz, float(Delta[0]), float(Delta[1]), float(Delta[2]), float(freq_hz), _dptr(e),
                     _dptr(sg), n, _dptr(pos), _dptr(mom), int(mode), float(tol), int(restart),
-                    x.view(np.float64).ctypes.data_as(_dp) if want_x else None, _dptr(p_abs))
+                    x.view(np.float64).ctypes.data_as(_dp) if want_x else None, _dptr(p_abs), int(basis))
         rid = ctypes.c_longlong(-1)
         _check(_lib.vie_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
         self._held[rid.value] = (p_abs, x)

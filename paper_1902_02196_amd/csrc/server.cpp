@@ -111,7 +111,8 @@ int run_request(Request& q) {
             q.error = vie_last_error();
         }
     };
-    const long long n = 12LL * r.nx * r.ny * r.nz * r.nrhs;
+    const int nc = r.basis == 3 ? 3 : 12;
+    const long long n = (long long)nc * r.nx * r.ny * r.nz * r.nrhs;
     do {
         int c = vie_create(&ctx, q.device, s);
         if (c) { fail(c); break; }
@@ -126,6 +127,7 @@ int run_request(Request& q) {
                 if (vie_fft_size(ctx, M) == VIE_OK) q.cache->put(key, ctx, q.device, operator_bytes(r.nx, r.ny, r.nz, M));
             }
         }
+        if (nc != 12 && (c = vie_set_basis(ctx, nc))) { fail(c); break; }   // the operator serves both bases
         if ((c = vie_set_contrast(ctx, q.eps.data(), q.sig.data(), 0))) { fail(c); break; }
         if (hipMalloc(&et, n * sizeof(double2)) != hipSuccess || hipMalloc(&x, n * sizeof(double2)) != hipSuccess) {
             rc = VIE_ENOMEM;
@@ -187,7 +189,8 @@ int vie_server_submit(vie_server* s, const vie_request* r, long long* id) {
     if (!s || !r || !id) return VIE_EINVAL;
     if (r->nx < 1 || r->ny < 1 || r->nz < 1 || r->nrhs < 1 || !r->eps_re || !r->sigma || !r->pos || !r->moment ||
         !(r->dx > 0 && r->dy > 0 && r->dz > 0 && r->freq_hz > 0) ||
-        (r->mode != VIE_SOLVE_FP64 && r->mode != VIE_SOLVE_FP32_IR))
+        (r->mode != VIE_SOLVE_FP64 && r->mode != VIE_SOLVE_FP32_IR) ||
+        (r->basis != 0 && r->basis != 12 && r->basis != 3))
         return VIE_EINVAL;
     auto q = std::make_shared<Request>();
     q->r = *r;
@@ -201,7 +204,7 @@ int vie_server_submit(vie_server* s, const vie_request* r, long long* id) {
     size_t fp = 0;
     if (vie_footprint_bytes(r->nx, r->ny, r->nz, r->nrhs, r->mode, r->restart > 0 ? r->restart : 50, &fp) != VIE_OK)
         return VIE_EINVAL;
-    fp += 2 * 12 * V * r->nrhs * sizeof(double2);   // request vectors (incident field, solution)
+    fp += 2 * (size_t)(r->basis == 3 ? 3 : 12) * V * r->nrhs * sizeof(double2);   // request vectors
     const long long k = s->sched->submit(fp, q);
     if (k < 0) return VIE_ENOMEM;                      // can never fit the budget
     *id = k;

@@ -5,7 +5,8 @@ counts are solved once each alone (one slot) and once all together (several
 slots, overlapping on the device).  Every kernel of the path is free of
 atomics on the result, so a request's solution and absorbed power are
 bitwise the same alone and in the mix.  The smallest request is also checked
-against the oracle's dense solution for the same dipole excitation.
+against the oracle's dense solution for the same dipole excitation, and a
+PWC request against the oracle's dense PWC solution.
 """
 import sys
 
@@ -13,7 +14,7 @@ import numpy as np
 import pytest
 
 import vie_inputs as vi
-from oracle import incident, matvec, physics, post, solve, toeplitz
+from oracle import incident, matvec, physics, post, pwc, solve, toeplitz
 from tests.layout import relerr, vec_from_lib, vox_to_lib
 
 pytestmark = pytest.mark.gpu
@@ -117,6 +118,44 @@ def test_served_solution_matches_oracle(vie):
     assert err < 1e-9
     pref = post.absorbed_power(xref, chi, D, f)
     assert abs(p[0] - pref) / abs(pref) < 1e-8
+
+
+def test_pwc_request_matches_oracle(vie):
+    """A PWC request (basis 3) served after a PWL request on the same grid
+    takes the cached operator (the PWL operator serves both bases) and
+    matches the oracle's dense PWC solution and absorbed power; the PWL
+    request beside it matches its own dense solution; a basis other than
+    12 or 3 is refused."""
+    N, D, f = (4, 4, 4), (0.005,) * 3, 298e6
+    e, s = vi.sphere(N, D, 0.0101, 50.0, 0.7)
+    pos, mom = vi.dipoles_on_cylinder(11, 1, 0.04, N[2] * D[2])
+    srv = vie.Server(0, hbm_budget=1 << 30, max_slots=2)
+    r12 = srv.submit(N, D, f, vox_to_lib(e), vox_to_lib(s), pos, mom, mode=0, tol=1e-12, restart=30, want_x=True)
+    srv.wait()
+    r3 = srv.submit(N, D, f, vox_to_lib(e), vox_to_lib(s), pos, mom, mode=0, tol=1e-12, restart=30, want_x=True,
+                    basis=3)
+    srv.wait()
+    info12, p12, x12 = srv.result(r12)
+    info3, p3, x3 = srv.result(r3)
+    _check_done(info12)
+    _check_done(info3)
+    assert x12.shape[1] == 12 and x3.shape[1] == 3
+    assert info3["operator_cached"] == 1
+    with pytest.raises(vie.VieError):
+        srv.submit(N, D, f, vox_to_lib(e), vox_to_lib(s), pos, mom, basis=5)
+    srv.close()
+    K = physics.k0(f)
+    T = toeplitz.toeplitz_full(N, D, K)
+    tau, chi = physics.tau(e, s, f), physics.chi(e, s, f)
+    et = incident.dipoles_tested(N, D, f, pos, mom, chi != 0, nq=4)[0]
+    x12ref = solve.solve_dense(T, tau, D, matvec.rhs_prec(et, tau, D, f))
+    T3 = pwc.blocks_from_pwl(T)
+    x3ref = pwc.solve_dense(T3, tau, D, pwc.rhs_prec(pwc.restrict(et), tau, D, f))
+    e12, e3 = relerr(vec_from_lib(x12[0]), x12ref), relerr(vec_from_lib(x3[0]), x3ref)
+    p3ref = pwc.absorbed_power(x3ref, chi, D, f)
+    _say("served PWL vs dense %.3e, PWC vs dense %.3e, PWC power %.4e (oracle %.4e)" % (e12, e3, p3[0], p3ref))
+    assert e12 < 1e-9 and e3 < 1e-9
+    assert abs(p3[0] - p3ref) / abs(p3ref) < 1e-8
 
 
 def test_operator_cache_off_gives_same_result(vie):
