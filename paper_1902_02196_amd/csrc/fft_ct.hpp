@@ -29,23 +29,29 @@ __host__ __device__ constexpr int ct_radix(int n, int s) {
 // HOUT: only the lower half of each row is used afterwards (a cropped inverse
 // transform, last pass only): the upper half is neither stored nor, once the
 // compiler drops the dead arithmetic, computed.
-// Rows are pitch = N elements apart before padding (every caller).
+// Rows are pitch = N elements apart before padding (every caller).  RP is
+// the padded row pitch: N + N / 16 (the lds_pad layout of a row-major block)
+// or, for N a multiple of 16, any larger value, with the elements of row t
+// at t RP + lds_pad(c).
 template <typename R, bool FWD, int N, int RAD, int NS, int NTHR, int MAXROWS, bool HIN = false,
-          bool HOUT = false>
+          bool HOUT = false, int RP = N + N / 16>
 __device__ __forceinline__ void ct_pass(C<R>* buf, const C<R>* twl, int rows, int pitch, int tid) {
     static_assert(!HIN || (NS == 1 && RAD % 2 == 0), "half-zero input only on an even first pass");
     static_assert(!HOUT || (NS * RAD == N && RAD % 2 == 0), "half output only on an even last pass");
+    static_assert(RP == N + N / 16 || (N % 16 == 0 && RP > N + N / 16), "row pitch");
+    // element c of row t (c < N)
+    auto at = [&](int t, int c) { return RP == N + N / 16 ? lds_pad(t * pitch + c) : t * RP + lds_pad(c); };
     constexpr int nb = N / RAD;
     constexpr int NB = (MAXROWS * nb + NTHR - 1) / NTHR;
     constexpr int twstep = N / (NS * RAD);
-    // Padded addresses lds_pad(t N + c) of a row made of whole 16-element
-    // blocks (N % 16 == 0; rows are N apart): t (N + N / 16) + c + (c >> 4).
+    // Padded addresses of a row made of whole 16-element blocks (N % 16 ==
+    // 0): t RP + c + (c >> 4).
     // For the c a butterfly touches, c = c0 + i S with stride S, the block
     // term splits into a per-thread part and a compile-time part when S is
     // a multiple of 16, or S divides 16 and c0's position keeps c0 + i S in
     // the block of i S (every pass below): then the address is one per-thread
     // base plus constant offsets, with no per-element index arithmetic.
-    constexpr int RB = N + N / 16;
+    constexpr int RB = RP;
     constexpr bool AFF_IN = N % 16 == 0 && (nb % 16 == 0 || 16 % nb == 0);
     constexpr bool AFF_OUT = N % 16 == 0 && (NS % 16 == 0 ||
                                              (16 % NS == 0 && ((NS * RAD) % 16 == 0 || 16 % (NS * RAD) == 0)));
@@ -61,9 +67,8 @@ __device__ __forceinline__ void ct_pass(C<R>* buf, const C<R>* twl, int rows, in
 #pragma unroll
                 for (int i = 0; i < (HIN ? RAD / 2 : RAD); ++i) v[q][i] = src[i * nb + ((i * nb) >> 4)];
             } else {
-                const int rb = t * pitch + j;
 #pragma unroll
-                for (int i = 0; i < (HIN ? RAD / 2 : RAD); ++i) v[q][i] = buf[lds_pad(rb + i * nb)];
+                for (int i = 0; i < (HIN ? RAD / 2 : RAD); ++i) v[q][i] = buf[at(t, j + i * nb)];
             }
         }
     }
@@ -90,9 +95,9 @@ __device__ __forceinline__ void ct_pass(C<R>* buf, const C<R>* twl, int rows, in
 #pragma unroll
                 for (int i = 0; i < (HOUT ? RAD / 2 : RAD); ++i) dst[i * NS + ((i * NS) >> 4)] = v[q][i];
             } else {
-                const int rb = t * pitch + (j - k) * RAD + k;
+                const int c0 = (j - k) * RAD + k;
 #pragma unroll
-                for (int i = 0; i < (HOUT ? RAD / 2 : RAD); ++i) buf[lds_pad(rb + i * NS)] = v[q][i];
+                for (int i = 0; i < (HOUT ? RAD / 2 : RAD); ++i) buf[at(t, c0 + i * NS)] = v[q][i];
             }
         }
     }
@@ -103,14 +108,15 @@ __device__ __forceinline__ void ct_pass(C<R>* buf, const C<R>* twl, int rows, in
 // first pass then skips the zero half when its radix is even
 // HOUT: only positions below N / 2 are read after the transform (cropped
 // inverse); the last pass then stores the lower half when its radix is even
-template <typename R, bool FWD, int N, int S, int NS, int NTHR, int MAXROWS, bool HIN = false, bool HOUT = false>
+template <typename R, bool FWD, int N, int S, int NS, int NTHR, int MAXROWS, bool HIN = false, bool HOUT = false,
+          int RP = N + N / 16>
 __device__ __forceinline__ void ct_passes(C<R>* buf, const C<R>* twl, int rows, int pitch, int tid) {
     constexpr int r = ct_radix(N, S);
     if constexpr (r > 0) {
         constexpr bool hin = HIN && S == 0 && r % 2 == 0;
         constexpr bool hout = HOUT && ct_radix(N, S + 1) == 0 && r % 2 == 0;
-        ct_pass<R, FWD, N, r, NS, NTHR, MAXROWS, hin, hout>(buf, twl, rows, pitch, tid);
-        ct_passes<R, FWD, N, S + 1, NS * r, NTHR, MAXROWS, false, HOUT>(buf, twl, rows, pitch, tid);
+        ct_pass<R, FWD, N, r, NS, NTHR, MAXROWS, hin, hout, RP>(buf, twl, rows, pitch, tid);
+        ct_passes<R, FWD, N, S + 1, NS * r, NTHR, MAXROWS, false, HOUT, RP>(buf, twl, rows, pitch, tid);
     }
 }
 

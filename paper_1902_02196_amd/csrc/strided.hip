@@ -20,10 +20,18 @@ namespace vie {
 // bytes, the long lengths, where 16 would leave one workgroup per CU) the
 // two tiles of each 128-byte line are then read through the same L2 instead
 // of twice, once per XCD.
+// LDS row pitch of a tile: one pencil per row, padded to an odd number of
+// complex elements when N is a multiple of 16, so that the T pencils of one
+// element index k (the loads and stores run along the pencils) fall on T
+// different bank pairs
+__host__ __device__ constexpr int strided_rp(int n) { return n % 16 == 0 ? ((n + n / 16) | 1) : n + n / 16; }
+
 template <typename R, bool FWD, bool EPI, int N, int T>
 __global__ void __launch_bounds__(256) k_strided_ct(const C<R>* in, C<R>* out, StridedPass p,
                                                     const C<R>* __restrict__ tw, Epilogue<R> ep) {
     constexpr int NT = 256;
+    constexpr int RP = strided_rp(N);
+    auto at = [](int t, int k) { return RP == N + N / 16 ? lds_pad(t * N + k) : t * RP + lds_pad(k); };
     extern __shared__ unsigned char smem_raw[];
     C<R>* twl = reinterpret_cast<C<R>*>(smem_raw);
     C<R>* buf = twl + N;
@@ -46,13 +54,13 @@ __global__ void __launch_bounds__(256) k_strided_ct(const C<R>* in, C<R>* out, S
             const int k = idx / T, t = idx - k * T;
             C<R> v = mk<R>(0, 0);
             if (k < p.n_in && t < tw_n) v = stream_load(&src[k * p.in_sk + t]);   // last read of the input
-            buf[lds_pad(t * N + k)] = v;
+            buf[at(t, k)] = v;
         }
     }
     __syncthreads();
-    if (FWD && 2 * p.n_in <= N) ct_passes<R, FWD, N, 0, 1, NT, T, FWD, false>(buf, twl, T, N, tid);   // zero-padded
-    else if (!FWD && 2 * p.n_out <= N) ct_passes<R, FWD, N, 0, 1, NT, T, false, !FWD>(buf, twl, T, N, tid);   // cropped
-    else ct_passes<R, FWD, N, 0, 1, NT, T>(buf, twl, T, N, tid);
+    if (FWD && 2 * p.n_in <= N) ct_passes<R, FWD, N, 0, 1, NT, T, FWD, false, RP>(buf, twl, T, N, tid);   // zero-padded
+    else if (!FWD && 2 * p.n_out <= N) ct_passes<R, FWD, N, 0, 1, NT, T, false, !FWD, RP>(buf, twl, T, N, tid);   // cropped
+    else ct_passes<R, FWD, N, 0, 1, NT, T, false, false, RP>(buf, twl, T, N, tid);
     const long long obase = rr * p.out_s1 + cc * p.out_sc;
     C<R>* dst = out + obase + o2 * p.out_s2 + t0;
     const int l = p.nc == 12 ? (cc & 3) : 0;
@@ -62,7 +70,7 @@ __global__ void __launch_bounds__(256) k_strided_ct(const C<R>* in, C<R>* out, S
         if (LN % NT == 0 || idx < LN) {
             const int k = idx / T, t = idx - k * T;
             if (k < p.n_out && t < tw_n) {
-                C<R> w = buf[lds_pad(t * N + k)];
+                C<R> w = buf[at(t, k)];
                 if (EPI) {
                     const long long v = o2 * p.out_s2 + k * p.out_sk + t0 + t;   // voxel
                     const long long e = obase + v;                                  // element
@@ -84,7 +92,7 @@ __global__ void __launch_bounds__(256) k_strided_ct(const C<R>* in, C<R>* out, S
 template <typename R, bool FWD, bool EPI, int N, int T>
 static void launch_strided_ct_nt(const C<R>* in, C<R>* out, const StridedPass& p, long long n_o2, long long n_o1,
                                  const C<R>* tw, const Epilogue<R>& ep, hipStream_t s) {
-    const size_t lds = ((size_t)N + lds_pad(N * T) + 2) * sizeof(C<R>);
+    const size_t lds = ((size_t)N + (size_t)T * strided_rp(N) + 2) * sizeof(C<R>);
     static std::once_flag once;
     std::call_once(once, [&] {
         (void)hipFuncSetAttribute((const void*)k_strided_ct<R, FWD, EPI, N, T>,
@@ -125,7 +133,7 @@ bool strided_ct_fits(int es, int n, int tile) {
 #define CASE(n_) case n_:
         VIE_STRIDED_LENGTHS(CASE)
 #undef CASE
-        return ((size_t)n + lds_pad(n * tile) + 2) * es <= 160 * 1024;
+        return ((size_t)n + (size_t)tile * strided_rp(n) + 2) * es <= 160 * 1024;
         default: return false;
     }
 }
