@@ -95,14 +95,15 @@ typedef struct {
                             steps computed past convergence                   */
     int s_step;          /* Arnoldi steps per pass over the basis: 1, the
                             classical step (one product, then Gram-Schmidt
-                            against the basis); 2, two products, then one
-                            dot and one update pass over the basis for both
-                            (s-step Arnoldi with s = 2, the second vector
-                            shifted by the Rayleigh quotient h_jj), which
-                            halves the basis reads per step; 0 (default):
-                            2.  reorth = 1 always runs single steps.  The
-                            iterates of 1 and 2 agree to rounding, not
-                            bitwise                                           */
+                            against the basis); 2 or 3, as many products,
+                            then one dot and one update pass over the basis
+                            for all of them (s-step Arnoldi, the new vectors
+                            shifted by the Rayleigh quotient h_jj and
+                            orthogonalised among themselves in FP64), which
+                            cuts the basis reads per step to about a half or
+                            a third; 0 (default): 3.  reorth = 1 always runs
+                            single steps.  The iterates of 1, 2 and 3 agree
+                            to rounding, not bitwise                          */
 } vie_solve_opts;
 
 typedef struct {
@@ -423,8 +424,8 @@ enum {
     VIE_K_FFT_Z_INV = 4,  /* inverse FFT along z, crop, contrast epilogue     */
     VIE_K_GS_DOT = 5,     /* Gram-Schmidt inner products (and their reduction) */
     VIE_K_GS_UPDATE = 6,  /* Gram-Schmidt update, norm and normalisation      */
-    VIE_K_GS_PAIR = 7,    /* two-step Arnoldi: the second new vector against
-                             the first (u_{j+2} = (w2 - gamma u_{j+1}) / beta) */
+    VIE_K_GS_PAIR = 7,    /* s-step Arnoldi: the later new vectors of a
+                             block against its first ones (one pass)      */
     VIE_K_COUNT = 8
 };
 

@@ -530,7 +530,7 @@ int vie_solve(vie_ctx* ctx, const vie_solve_opts* opts, int nrhs, const void* e_
         VIE_REQUIRE(o.mode == VIE_SOLVE_FP64 || o.mode == VIE_SOLVE_FP32_IR, VIE_EINVAL, "unknown mode");
         VIE_REQUIRE(o.mode != VIE_SOLVE_FP32_IR || o.max_refine >= 1, VIE_EINVAL, "max_refine must be >= 1");
         VIE_REQUIRE(o.sync_steps >= 0, VIE_EINVAL, "sync_steps must be >= 0");
-        VIE_REQUIRE(o.s_step >= 0 && o.s_step <= 2, VIE_EINVAL, "s_step must be 0, 1 or 2");
+        VIE_REQUIRE(o.s_step >= 0 && o.s_step <= 3, VIE_EINVAL, "s_step must be 0, 1, 2 or 3");
         rc = solve(c, o, nrhs, static_cast<const double2*>(e_t), static_cast<double2*>(x), stats);
         if (rc == VIE_ENOCONV) g_err = "solver stopped before reaching the tolerance";
         if (rc == VIE_ENAN) g_err = "non-finite residual";

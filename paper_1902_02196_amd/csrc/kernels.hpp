@@ -181,6 +181,28 @@ void launch_axpy_pair(C<R>* u1, long long ldv, long long n, long long rstride, c
 // Hessenberg column j + 1 of the pair, entries 0..j + 1, into col [na][j + 2]
 void launch_pair_column(ArnoldiState st, const double2* h, const double2* gcol, const double2* pc, double2* col,
                         int j, int na, hipStream_t s);
+// Three Arnoldi steps per pass over the basis (s = 3; krylov.hip states the
+// algebra): dot partials against w, w + ldw, w + 2 ldw (3 planes); g_k and
+// their update coefficients at g + k gst, coef + k gst; the three updates in
+// one pass with the block's Gram partials ([nrhs][nblocks][8]); the Cholesky
+// factor and storage coefficients tc [nrhs][8]; u_{j+2}, u_{j+3} formed in
+// place with their norm partials; Hessenberg columns j + 1 and j + 2.
+template <typename R>
+void launch_multidot3(double2* partial, const C<R>* Vb, long long ldv, int nvec, const C<R>* w, long long ldw,
+                      long long n, long long rstride_v, long long rstride_w, int nrhs, int nblocks, hipStream_t s);
+void launch_reduce_triple(double2* g, double2* coef, const double2* partial, int nvec, int nblocks, int nrhs,
+                          const double* ivn, long long ivn_ld, int jw, long long gst, hipStream_t s);
+template <typename R>
+void launch_update_triple(C<R>* w, const C<R>* Vb, long long ldv, int nvec, const double2* coef, long long gst,
+                          const double2* g, long long n, long long rstride_v, long long rstride_w,
+                          double* norm_partial, double* gram_partial, const double* ivn, long long ivn_ld, int jw,
+                          int nrhs, int nblocks, hipStream_t s);
+void launch_triple_coef(double2* tc, const double* gpart, int nblocks, int nrhs, hipStream_t s);
+template <typename R>
+void launch_axpy_triple(C<R>* u1, long long ldv, long long n, long long rstride, const double2* tc, double* np2,
+                        double* np3, int nrhs, int nblocks, hipStream_t s);
+void launch_triple_columns(ArnoldiState st, const double2* g, long long gst, const double2* tc, double2* col1,
+                           double2* col2, int j, int na, hipStream_t s);
 // y = R^-1 g over the first nvec columns, scaled by the basis vectors'
 // reciprocal norms (the coefficients of the stored vectors), y [na][nvec]
 void launch_backsolve(ArnoldiState st, const double* ivn, long long ivn_ld, double2* y, int nvec, int na,

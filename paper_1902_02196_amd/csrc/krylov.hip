@@ -67,7 +67,7 @@ __device__ __forceinline__ void dot_group(double2* __restrict__ partial,
                                           const typename Unit<R, PAIR>::T* __restrict__ V,
                                           const typename Unit<R, PAIR>::T* __restrict__ wr, long long ldwu,
                                           long long ldu, long long nu, int i0, int nvec, int r,
-                                          double (*red)[2 * 2 * kGroup]) {
+                                          double (*red)[2 * 3 * kGroup]) {
     using U = Unit<R, PAIR>;
     using T = typename U::T;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(kTpb) k_multidot(double2* __restrict__ partial
                                                    long long ldw, long long n, long long rsv, long long rsw) {
     using U = Unit<R, PAIR>;
     using T = typename U::T;
-    __shared__ double red[kTpb / 64][2 * 2 * kGroup];
+    __shared__ double red[kTpb / 64][2 * 3 * kGroup];
     const int r = blockIdx.y;
     const T* V = reinterpret_cast<const T*>(Vb + r * rsv);
     const T* wr = reinterpret_cast<const T*>(w + r * rsw);
@@ -165,6 +165,12 @@ template <typename R>
 void launch_multidot2(double2* partial, const C<R>* Vb, long long ldv, int nvec, const C<R>* w, long long ldw,
                       long long n, long long rsv, long long rsw, int nrhs, int nblocks, hipStream_t s) {
     multidot_nw<R, 2>(partial, Vb, ldv, nvec, w, ldw, n, rsv, rsw, nrhs, nblocks, s);
+}
+
+template <typename R>
+void launch_multidot3(double2* partial, const C<R>* Vb, long long ldv, int nvec, const C<R>* w, long long ldw,
+                      long long n, long long rsv, long long rsw, int nrhs, int nblocks, hipStream_t s) {
+    multidot_nw<R, 3>(partial, Vb, ldv, nvec, w, ldw, n, rsv, rsw, nrhs, nblocks, s);
 }
 
 // The basis is stored unnormalised: slot i holds u_i with v_i = u_i * ivn[i]
@@ -588,6 +594,365 @@ void launch_pair_column(ArnoldiState st, const double2* h, const double2* gcol, 
     VIE_HIP(hipGetLastError());
 }
 
+// ---- three Arnoldi steps per pass over the basis (s = 3) ----
+//
+// As the pair, with w1 = A u_j, w2 = A w1, w3 = A w2 (raw, in slots j + 1 ..
+// j + 3) and the shifted vectors z1 = sw w1 = A v_j, z2 = (A - sigma) z1,
+// z3 = (A - sigma)^2 z1 (sigma = h_jj).  One dot pass gives g_k = V^H z_k,
+// one update pass y_k = z_k - V g_k with the block's Gram matrix G = Y^H Y,
+// and its Cholesky factor R (G = R^H R, FP64) orthogonalises the block:
+// q_k = (Y R^-1)_k.  Stored: u_{j+1} = y1 (norm R11), u_{j+2} = (y2 - R12 /
+// R11 y1) / R11 and u_{j+3} = (y3 - R13 / R11 y1 - R23 / R22 (y2 - R12 / R11
+// y1)) / R22, so that each norm is the subdiagonal entry of its column.
+// Columns j + 1 and j + 2 follow from A z_k = z_{k+1} + sigma z_k:
+//   A q1 = (z2 + sigma z1 - A V g1) / R11,
+//   A q2 = (z3 + sigma z2 - A V g2 - R12 A q1) / R22,
+// with A V g = V_{j+2} H g over the unrotated columns 0..j.
+
+// one wave per (row i, slot r): g1 = h, g2, g3 (rows of V^H z_k) and the
+// update coefficients g_k ivn[i], from the 3 planes of dot partials
+__global__ void __launch_bounds__(64) k_reduce_triple(double2* __restrict__ g, double2* __restrict__ coef,
+                                                      const double2* __restrict__ partial, int nblocks, int nvec,
+                                                      int na, const double* __restrict__ ivn, long long ivn_ld,
+                                                      int jw, long long gst) {
+    const int i = blockIdx.x, r = blockIdx.y, lane = threadIdx.x, j = nvec - 1;
+    const double2* p1 = partial + ((long long)r * nvec + i) * nblocks;
+    const double2* p2 = partial + (((long long)na + r) * nvec + i) * nblocks;
+    const double2* p3 = partial + (((long long)2 * na + r) * nvec + i) * nblocks;
+    const double2* pj = partial + ((long long)r * nvec + j) * nblocks;
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 4
+    for (int k = lane; k < nblocks; k += 64) {
+        a[0] += p1[k].x;
+        a[1] += p1[k].y;
+        a[2] += p2[k].x;
+        a[3] += p2[k].y;
+        a[4] += p3[k].x;
+        a[5] += p3[k].y;
+        a[6] += pj[k].x;
+        a[7] += pj[k].y;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = wave_sum(a[q]);
+    if (lane == 0) {
+        const double sw = ivn[r * ivn_ld + jw], iv = ivn[r * ivn_ld + i], ivj = ivn[r * ivn_ld + j];
+        const double2 sg = make_double2(a[6] * sw * ivj, a[7] * sw * ivj);
+        const double2 P1 = make_double2(a[0] * sw * iv, a[1] * sw * iv);
+        const double2 P2 = make_double2(a[2] * sw * iv, a[3] * sw * iv);
+        const double2 P3 = make_double2(a[4] * sw * iv, a[5] * sw * iv);
+        const double2 g2 = csub(P2, cmul(sg, P1));
+        const double2 g3 = cadd(csub(P3, cscale(cmul(sg, P2), 2.0)), cmul(cmul(sg, sg), P1));
+        const long long o = (long long)r * nvec + i;
+        g[o] = P1;
+        g[gst + o] = g2;
+        g[2 * gst + o] = g3;
+        coef[o] = make_double2(P1.x * iv, P1.y * iv);
+        coef[gst + o] = make_double2(g2.x * iv, g2.y * iv);
+        coef[2 * gst + o] = make_double2(g3.x * iv, g3.y * iv);
+    }
+}
+
+void launch_reduce_triple(double2* g, double2* coef, const double2* partial, int nvec, int nblocks, int nrhs,
+                          const double* ivn, long long ivn_ld, int jw, long long gst, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_triple, dim3(nvec, nrhs), dim3(64), 0, s, g, coef, partial, nblocks, nvec, nrhs, ivn,
+                       ivn_ld, jw, gst);
+    VIE_HIP(hipGetLastError());
+}
+
+// y_k = z_k - sum_i c_k,i u_i (k = 1..3, z_k from the raw w's, in place in
+// slots j + 1 .. j + 3 = w, w + ldv, w + 2 ldv), with the partial sums of
+// |y1|^2 (norm_partial) and of the Gram entries (gram_partial [r][block][8]:
+// G11, G12, G13, G22, G23 as re/im, G11 and G22 real)
+template <typename R, bool PAIR>
+__global__ void __launch_bounds__(kTpb) k_update_triple(C<R>* __restrict__ w, const C<R>* __restrict__ Vb,
+                                                        long long ldv, int nvec, const double2* __restrict__ coef,
+                                                        long long gst, const double2* __restrict__ g, long long n,
+                                                        long long rsv, long long rsw,
+                                                        double* __restrict__ norm_partial,
+                                                        double* __restrict__ gram_partial,
+                                                        const double* __restrict__ ivn, long long ivn_ld, int jw) {
+    using U = Unit<R, PAIR>;
+    using T = typename U::T;
+    __shared__ double red[kTpb / 64][8];
+    const int r = blockIdx.y;
+    const T* V = reinterpret_cast<const T*>(Vb + r * rsv);
+    T* w1p = reinterpret_cast<T*>(w + r * rsw);
+    T* w2p = reinterpret_cast<T*>(w + r * rsw + ldv);
+    T* w3p = reinterpret_cast<T*>(w + r * rsw + 2 * ldv);
+    const long long nu = n / U::per, ldu = ldv / U::per;
+    const double2* c1 = coef + (long long)r * nvec;
+    const double2* c2 = c1 + gst;
+    const double2* c3 = c2 + gst;
+    const double2 sg = g[(long long)r * nvec + nvec - 1];
+    const double2 sg2 = cmul(sg, sg);
+    const double sw = ivn[r * ivn_ld + jw];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < nu; k += (long long)gridDim.x * kTpb) {
+        T a1 = w1p[k], a2 = w2p[k], a3 = w3p[k];
+        double2 y1[U::per], y2[U::per], y3[U::per];
+#pragma unroll
+        for (int q = 0; q < U::per; ++q) {
+            const double2 o1 = U::get(a1, q), o2 = U::get(a2, q), o3 = U::get(a3, q);
+            const double2 t2 = csub(o2, cmul(sg, o1));
+            const double2 t3 = cadd(csub(o3, cscale(cmul(sg, o2), 2.0)), cmul(sg2, o1));
+            y1[q] = make_double2(sw * o1.x, sw * o1.y);
+            y2[q] = make_double2(sw * t2.x, sw * t2.y);
+            y3[q] = make_double2(sw * t3.x, sw * t3.y);
+        }
+        int i = 0;
+        for (; i + 8 <= nvec; i += 8) {
+            T vu[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) vu[u] = stream_load(&V[(i + u) * ldu + k]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double2 p1 = c1[i + u], p2 = c2[i + u], p3 = c3[i + u];
+#pragma unroll
+                for (int q = 0; q < U::per; ++q) {
+                    const double2 v = U::get(vu[u], q);
+                    y1[q] = csub(y1[q], cmul(p1, v));
+                    y2[q] = csub(y2[q], cmul(p2, v));
+                    y3[q] = csub(y3[q], cmul(p3, v));
+                }
+            }
+        }
+        for (; i < nvec; ++i) {
+            const T vu = stream_load(&V[i * ldu + k]);
+            const double2 p1 = c1[i], p2 = c2[i], p3 = c3[i];
+#pragma unroll
+            for (int q = 0; q < U::per; ++q) {
+                const double2 v = U::get(vu, q);
+                y1[q] = csub(y1[q], cmul(p1, v));
+                y2[q] = csub(y2[q], cmul(p2, v));
+                y3[q] = csub(y3[q], cmul(p3, v));
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < U::per; ++q) {
+            U::set(a1, q, y1[q]);
+            U::set(a2, q, y2[q]);
+            U::set(a3, q, y3[q]);
+        }
+        w1p[k] = a1;
+        w2p[k] = a2;
+        w3p[k] = a3;
+#pragma unroll
+        for (int q = 0; q < U::per; ++q) {   // the stored (rounded) values
+            const double2 o1 = U::get(a1, q), o2 = U::get(a2, q), o3 = U::get(a3, q);
+            acc[0] += o1.x * o1.x + o1.y * o1.y;
+            acc[1] += o1.x * o2.x + o1.y * o2.y;   // conj(y1) y2
+            acc[2] += o1.x * o2.y - o1.y * o2.x;
+            acc[3] += o1.x * o3.x + o1.y * o3.y;   // conj(y1) y3
+            acc[4] += o1.x * o3.y - o1.y * o3.x;
+            acc[5] += o2.x * o2.x + o2.y * o2.y;
+            acc[6] += o2.x * o3.x + o2.y * o3.y;   // conj(y2) y3
+            acc[7] += o2.x * o3.y - o2.y * o3.x;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const double v = wave_sum(acc[q]);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        double t = 0;
+        for (int wv = 0; wv < kTpb / 64; ++wv) t += red[wv][threadIdx.x];
+        gram_partial[((long long)r * gridDim.x + blockIdx.x) * 8 + threadIdx.x] = t;
+        if (threadIdx.x == 0) norm_partial[(long long)r * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+template <typename R>
+void launch_update_triple(C<R>* w, const C<R>* Vb, long long ldv, int nvec, const double2* coef, long long gst,
+                          const double2* g, long long n, long long rsv, long long rsw, double* norm_partial,
+                          double* gram_partial, const double* ivn, long long ivn_ld, int jw, int nrhs, int nblocks,
+                          hipStream_t s) {
+    if (pair_units<R>(Vb, w, n, ldv, rsv, rsw))
+        hipLaunchKernelGGL((k_update_triple<R, true>), dim3(nblocks, nrhs), dim3(kTpb), 0, s, w, Vb, ldv, nvec, coef,
+                           gst, g, n, rsv, rsw, norm_partial, gram_partial, ivn, ivn_ld, jw);
+    else
+        hipLaunchKernelGGL((k_update_triple<R, false>), dim3(nblocks, nrhs), dim3(kTpb), 0, s, w, Vb, ldv, nvec, coef,
+                           gst, g, n, rsv, rsw, norm_partial, gram_partial, ivn, ivn_ld, jw);
+    VIE_HIP(hipGetLastError());
+}
+
+// per slot: the Gram sums (lane-strided, fixed order), the Cholesky factor
+// and the coefficients of the stored vectors, tc[8 s ..]: (R11, R22), R12,
+// R13, R23, (1 / R11, 1 / R22), a21 = R12 / R11, b31 = R13 / R11, b32 =
+// R23 / R22 (zero where a pivot is not positive)
+__global__ void __launch_bounds__(64) k_triple_coef(double2* __restrict__ tc, const double* __restrict__ gpart,
+                                                    int nblocks) {
+    const int r = blockIdx.x, lane = threadIdx.x;
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 4
+    for (int b = lane; b < nblocks; b += 64) {
+        const double* p = gpart + ((long long)r * nblocks + b) * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] += p[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = wave_sum(a[q]);
+    if (lane == 0) {
+        const double g11 = a[0], g22 = a[5];
+        const double2 g12 = make_double2(a[1], a[2]), g13 = make_double2(a[3], a[4]), g23 = make_double2(a[6], a[7]);
+        const double r11 = g11 > 0 ? sqrt(g11) : 0.0, i11 = r11 > 0 ? 1.0 / r11 : 0.0;
+        const double2 r12 = cscale(g12, i11), r13 = cscale(g13, i11);
+        const double d22 = g22 - (r12.x * r12.x + r12.y * r12.y);
+        const double r22 = d22 > 0 ? sqrt(d22) : 0.0, i22 = r22 > 0 ? 1.0 / r22 : 0.0;
+        const double2 r23 = cscale(csub(g23, cmulc(r12, r13)), i22);   // (G23 - conj(R12) R13) / R22
+        double2* o = tc + 8 * r;
+        o[0] = make_double2(r11, r22);
+        o[1] = r12;
+        o[2] = r13;
+        o[3] = r23;
+        o[4] = make_double2(i11, i22);
+        o[5] = cscale(r12, i11);
+        o[6] = cscale(r13, i11);
+        o[7] = cscale(r23, i22);
+    }
+}
+
+void launch_triple_coef(double2* tc, const double* gpart, int nblocks, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_triple_coef, dim3(nrhs), dim3(64), 0, s, tc, gpart, nblocks);
+    VIE_HIP(hipGetLastError());
+}
+
+// u2 <- (y2 - a21 y1) / R11, u3 <- (y3 - b31 y1 - b32 (y2 - a21 y1)) / R22 in
+// place (y_k in slots j + 1 .. j + 3 = u1, u1 + ldv, u1 + 2 ldv), with the
+// partial sums of |u2|^2 and |u3|^2 over the stored values
+template <typename R, bool PAIR>
+__global__ void __launch_bounds__(kTpb) k_axpy_triple(C<R>* __restrict__ u1, long long ldv, long long n,
+                                                      long long rs, const double2* __restrict__ tc,
+                                                      double* __restrict__ np2, double* __restrict__ np3) {
+    using U = Unit<R, PAIR>;
+    using T = typename U::T;
+    __shared__ double red[kTpb / 64][2];
+    const int r = blockIdx.y;
+    const T* a = reinterpret_cast<const T*>(u1 + r * rs);
+    T* b = reinterpret_cast<T*>(u1 + r * rs + ldv);
+    T* c = reinterpret_cast<T*>(u1 + r * rs + 2 * ldv);
+    const long long nu = n / U::per;
+    const double2* t = tc + 8 * r;
+    const double i11 = t[4].x, i22 = t[4].y;
+    const double2 a21 = t[5], b31 = t[6], b32 = t[7];
+    double s2 = 0.0, s3 = 0.0;
+    for (long long k = blockIdx.x * (long long)kTpb + threadIdx.x; k < nu; k += (long long)gridDim.x * kTpb) {
+        const T au = a[k];
+        T bu = b[k], cu = c[k];
+#pragma unroll
+        for (int q = 0; q < U::per; ++q) {
+            const double2 y1 = U::get(au, q), y2 = U::get(bu, q), y3 = U::get(cu, q);
+            const double2 d2 = csub(y2, cmul(a21, y1));
+            const double2 d3 = csub(csub(y3, cmul(b31, y1)), cmul(b32, d2));
+            U::set(bu, q, cscale(d2, i11));
+            U::set(cu, q, cscale(d3, i22));
+        }
+        b[k] = bu;
+        c[k] = cu;
+#pragma unroll
+        for (int q = 0; q < U::per; ++q) {
+            const double2 o2 = U::get(bu, q), o3 = U::get(cu, q);
+            s2 += o2.x * o2.x + o2.y * o2.y;
+            s3 += o3.x * o3.x + o3.y * o3.y;
+        }
+    }
+    s2 = wave_sum(s2);
+    s3 = wave_sum(s3);
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6][0] = s2;
+        red[threadIdx.x >> 6][1] = s3;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double v = 0;
+        for (int i = 0; i < kTpb / 64; ++i) v += red[i][threadIdx.x];
+        (threadIdx.x ? np3 : np2)[(long long)r * gridDim.x + blockIdx.x] = v;
+    }
+}
+
+template <typename R>
+void launch_axpy_triple(C<R>* u1, long long ldv, long long n, long long rs, const double2* tc, double* np2,
+                        double* np3, int nrhs, int nblocks, hipStream_t s) {
+    if (pair_units<R>(u1, u1, n, ldv, rs, rs))
+        hipLaunchKernelGGL((k_axpy_triple<R, true>), dim3(nblocks, nrhs), dim3(kTpb), 0, s, u1, ldv, n, rs, tc, np2,
+                           np3);
+    else
+        hipLaunchKernelGGL((k_axpy_triple<R, false>), dim3(nblocks, nrhs), dim3(kTpb), 0, s, u1, ldv, n, rs, tc, np2,
+                           np3);
+    VIE_HIP(hipGetLastError());
+}
+
+// Hessenberg columns j + 1 (entries 0..j + 1) and j + 2 (entries 0..j + 2)
+// of a triple into col1 [na][j + 2] and col2 [na][j + 3] (the subdiagonal
+// entries come from the stored norms): one workgroup of 4 waves per slot,
+// the products A V g1 and A V g2 over the unrotated columns 0..j summed by
+// the waves in LDS in a fixed order, then wave 0 forms the entries
+__global__ void __launch_bounds__(64 * kColWaves) k_triple_columns(ArnoldiState st, const double2* __restrict__ g,
+                                                                   long long gst, const double2* __restrict__ tc,
+                                                                   double2* __restrict__ col1,
+                                                                   double2* __restrict__ col2, int j) {
+    __shared__ double2 part[2][kColWaves][kColRows];
+    const int r = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6, m = st.m, nvec = j + 1;
+    const double2* g1 = g + (long long)r * nvec;
+    const double2* g2 = g1 + gst;
+    const double2* g3 = g2 + gst;
+    const double2* Hr = st.Hr + (long long)r * m * (m + 1);
+    for (int i = lane; i <= j + 1; i += 64) {
+        double2 a1 = make_double2(0.0, 0.0), a2 = make_double2(0.0, 0.0);
+#pragma unroll 4
+        for (int k = wv; k <= j; k += kColWaves)
+            if (k >= i - 1) {
+                const double2 hk = Hr[(long long)k * (m + 1) + i];
+                a1 = cadd(a1, cmul(hk, g1[k]));
+                a2 = cadd(a2, cmul(hk, g2[k]));
+            }
+        part[0][wv][i] = a1;
+        part[1][wv][i] = a2;
+    }
+    __syncthreads();
+    if (wv == 0) {
+        const double2* t = tc + 8 * r;
+        const double r11 = t[0].x, r22 = t[0].y, i11 = t[4].x, i22 = t[4].y;
+        const double2 r12 = t[1], r13 = t[2], r23 = t[3];
+        const double2 sg = g1[j];
+        double2* o1 = col1 + (long long)r * (j + 2);   // the strides the Givens kernel reads
+        double2* o2 = col2 + (long long)r * (j + 3);
+        for (int i = lane; i <= j + 1; i += 64) {
+            double2 hv1 = part[0][0][i], hv2 = part[1][0][i];
+            for (int w = 1; w < kColWaves; ++w) {
+                hv1 = cadd(hv1, part[0][w][i]);
+                hv2 = cadd(hv2, part[1][w][i]);
+            }
+            // column j + 1, row i: (z2 + sigma z1 - A V g1)_i / R11
+            double2 c1;
+            if (i <= j) c1 = cscale(csub(cadd(g2[i], cmul(sg, g1[i])), hv1), i11);
+            else c1 = cscale(r12, i11);   // row j + 1: R12 / R11
+            o1[i] = c1;
+            // column j + 2, row i: (z3 + sigma z2 - A V g2 - R12 A q1)_i / R22
+            double2 c2;
+            if (i <= j) c2 = csub(cadd(g3[i], cmul(sg, g2[i])), hv2);
+            else c2 = csub(cadd(r13, cmul(sg, r12)), hv2);   // row j + 1 (z1 has no q1 part beyond R11)
+            c2 = csub(c2, cmul(r12, c1));
+            o2[i] = cscale(c2, i22);
+        }
+        if (lane == 0) {
+            // column j + 2, row j + 2: (R23 + sigma R22 - R12 (A q1)_{j+2}) / R22, (A q1)_{j+2} = R22 / R11
+            const double2 aq = make_double2(r22 * i11, 0.0);
+            o2[j + 2] = cscale(csub(cadd(r23, cscale(sg, r22)), cmul(r12, aq)), i22);
+        }
+        (void)r11;
+    }
+}
+
+void launch_triple_columns(ArnoldiState st, const double2* g, long long gst, const double2* tc, double2* col1,
+                           double2* col2, int j, int na, hipStream_t s) {
+    VIE_REQUIRE(st.Hr != nullptr && j + 2 < st.m && j + 2 < kColRows, VIE_EINVAL,
+                "triple columns without the unrotated Hessenberg matrix");
+    hipLaunchKernelGGL(k_triple_columns, dim3(na), dim3(64 * kColWaves), 0, s, st, g, gst, tc, col1, col2, j);
+    VIE_HIP(hipGetLastError());
+}
+
 // norms from partial sums of squares; with inv != nullptr also their
 // reciprocals (0 for a zero norm) at inv[r * inv_ld]
 __global__ void k_reduce_norm(double* __restrict__ out, const double* __restrict__ partial, int nblocks,
@@ -925,6 +1290,13 @@ void launch_nonfinite(int* flag, const double2* v, long long n, hipStream_t s) {
                                         const double*, long long, int, int, int, hipStream_t);                   \
     template void launch_axpy_pair<R>(C<R>*, long long, long long, long long, const double2*, double*, int, int, \
                                       hipStream_t);                                                               \
+    template void launch_multidot3<R>(double2*, const C<R>*, long long, int, const C<R>*, long long, long long,  \
+                                      long long, long long, int, int, hipStream_t);                               \
+    template void launch_update_triple<R>(C<R>*, const C<R>*, long long, int, const double2*, long long,        \
+                                          const double2*, long long, long long, long long, double*, double*,     \
+                                          const double*, long long, int, int, int, hipStream_t);                 \
+    template void launch_axpy_triple<R>(C<R>*, long long, long long, long long, const double2*, double*,        \
+                                        double*, int, int, hipStream_t);                                          \
     template void launch_scale_into<R>(C<R>*, const C<R>*, const double*, long long, long long, long long, int, \
                                        hipStream_t);                                                             \
     template void launch_combine<R>(double2*, const C<R>*, long long, int, const double2*, long long, long long, \

@@ -62,6 +62,11 @@ struct Layout {
     // the assembled column j + 1
     double2 *Hr, *coef2, *dpart, *pc, *col;
     double* npart2;
+    // three-step Arnoldi: g_1..3 and their coefficients (3 [na][m + 1]
+    // blocks each), Gram partials, Cholesky coefficients, the two assembled
+    // columns, norm partials of u_{j+3}
+    double2 *g3, *coef3, *tc, *col2;
+    double *gpart, *npart3;
 };
 
 // Arnoldi steps between host checks of the convergence flag: several while
@@ -209,10 +214,45 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
             launch_pair_column(as, L.h1, L.h2, L.pc, L.col, j, na, c.stream);
             launch_givens(as, L.col, nullptr, L.npart2, nb, L.nrm, L.ivn + (j + 2), ivld, j + 1, na, c.stream);
         };
-        // s = 2 unless asked otherwise; the second Gram-Schmidt pass runs
-        // with single steps
+        // Arnoldi three steps per pass over the basis:
+        // w1 = P^-1 A u_j, w2 = P^-1 A w1, w3 = P^-1 A w2 in slots j + 1 ..
+        // j + 3, one dot and one update pass for the three, then u_{j+2} and
+        // u_{j+3} against the block (the algebra is stated with the kernels)
+        const long long gst = (long long)na * (m + 1);
+        auto triple = [&](int j) {
+            C<R>* vj = Vb + (long long)j * ldv;
+            C<R>* w1 = Vb + (long long)(j + 1) * ldv;
+            apply_op<R>(c, OP_PREC, na, vj, w1, nullptr);
+            apply_op<R>(c, OP_PREC, na, w1, w1 + ldv, nullptr);
+            apply_op<R>(c, OP_PREC, na, w1 + ldv, w1 + 2 * ldv, nullptr);
+            const int nvec = j + 1;
+            const double vb = (double)na * n * sizeof(C<R>);
+            {
+                ProfScope ps(c.prof, c.stream, VIE_K_GS_DOT, vb * (nvec + 3.0 * ((nvec + 7) / 8)));
+                launch_multidot3<R>(L.partial, Vb, ldv, nvec, w1, ldv, n, n, n, na, nbd, c.stream);
+                launch_reduce_triple(L.g3, L.coef3, L.partial, nvec, nbd, na, L.ivn, ivld, j, gst, c.stream);
+            }
+            {   // reads the basis, reads and writes w1..w3
+                ProfScope ps(c.prof, c.stream, VIE_K_GS_UPDATE, vb * (nvec + 6));
+                launch_update_triple<R>(w1, Vb, ldv, nvec, L.coef3, gst, L.g3, n, n, n, L.npart, L.gpart, L.ivn, ivld,
+                                        j, na, nb, c.stream);
+            }
+            launch_givens(as, L.g3, nullptr, L.npart, nb, L.nrm, L.ivn + (j + 1), ivld, j, na, c.stream);
+            launch_triple_coef(L.tc, L.gpart, nb, na, c.stream);
+            {   // reads y1..y3, writes u_{j+2}, u_{j+3}
+                ProfScope ps(c.prof, c.stream, VIE_K_GS_PAIR, vb * 5);
+                launch_axpy_triple<R>(w1, ldv, n, n, L.tc, L.npart2, L.npart3, na, nb, c.stream);
+            }
+            launch_triple_columns(as, L.g3, gst, L.tc, L.col, L.col2, j, na, c.stream);
+            launch_givens(as, L.col, nullptr, L.npart2, nb, L.nrm, L.ivn + (j + 2), ivld, j + 1, na, c.stream);
+            launch_givens(as, L.col2, nullptr, L.npart3, nb, L.nrm, L.ivn + (j + 3), ivld, j + 2, na, c.stream);
+        };
+        // s = 3 by default (pairs and single steps fill the end of a
+        // cycle), 2 or 1 on request; the second Gram-Schmidt pass runs with
+        // single steps
         const long long vec_bytes = na * n * (long long)sizeof(C<R>);
         const bool two = o.s_step != 1 && !o.reorth && m >= 2;
+        const bool three = (o.s_step == 0 || o.s_step == 3) && !o.reorth && m >= 3;
 
         // steps [j0, j1): launched one by one, or replayed from a graph
         // (the product's workspace is grown first, so that no step
@@ -222,7 +262,10 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
         auto enqueue = [&](int j0, int j1) {
             auto run_steps = [&] {
                 for (int j = j0; j < j1;) {
-                    if (two && j + 1 < j1) {
+                    if (three && j + 2 < j1) {
+                        triple(j);
+                        j += 3;
+                    } else if (two && j + 1 < j1) {
                         pair(j);
                         j += 2;
                     } else {
@@ -235,7 +278,7 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
                 run_steps();
                 return;
             }
-            const std::vector<long long> key{(long long)sizeof(R), na, m, o.reorth, two, j0, j1, n,
+            const std::vector<long long> key{(long long)sizeof(R), na, m, o.reorth, two, three, j0, j1, n,
                                              (long long)reinterpret_cast<uintptr_t>(Vb), ldv,
                                              (long long)reinterpret_cast<uintptr_t>(L.rhs),
                                              (long long)reinterpret_cast<uintptr_t>(c.ws.p),
@@ -278,7 +321,8 @@ static int run(Ctx& c, const vie_solve_opts& o, int nrhs, double2* x, const Layo
         // the device does not idle on the round trip; a chunk queued behind
         // the converged one runs with its Givens updates turned off.
         int S = o.sync_steps > 0 ? o.sync_steps : auto_sync_steps(vec_bytes);
-        if (two) S += S & 1;   // chunks of whole pairs
+        if (three) S = (S + 2) / 3 * 3;   // chunks of whole triples
+        else if (two) S += S & 1;        // chunks of whole pairs
         const int nch = (m + S - 1) / S;
         int* pin = static_cast<int*>(c.hpin.get(2 * 4 * sizeof(int)));
         for (auto& e : c.col_ev)
@@ -337,7 +381,7 @@ int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2*
         return o_;
     };
     const size_t o_rhs = take((size_t)nrhs * n * 16), o_r = take((size_t)nrhs * n * 16);
-    const size_t o_part = take((size_t)2 * nrhs * (m + 1) * std::max(nb, dot_blocks_for(n)) * 16);
+    const size_t o_part = take((size_t)3 * nrhs * (m + 1) * std::max(nb, dot_blocks_for(n)) * 16);
     const size_t o_h1 = take((size_t)nrhs * (m + 1) * 16), o_h2 = take((size_t)nrhs * (m + 1) * 16);
     const size_t o_coef = take((size_t)nrhs * (m + 1) * 16), o_ivn = take((size_t)nrhs * (m + 1) * 8);
     const size_t o_y = take((size_t)nrhs * m * 16);
@@ -349,6 +393,9 @@ int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2*
     const size_t o_Hr = take((size_t)nrhs * m * (m + 1) * 16), o_coef2 = take((size_t)nrhs * (m + 1) * 16);
     const size_t o_dp = take((size_t)nrhs * nb * 16), o_pc = take((size_t)nrhs * 2 * 16);
     const size_t o_col = take((size_t)nrhs * (m + 1) * 16), o_np2 = take((size_t)nrhs * nb * 8);
+    const size_t o_g3 = take((size_t)3 * nrhs * (m + 1) * 16), o_coef3 = take((size_t)3 * nrhs * (m + 1) * 16);
+    const size_t o_tc = take((size_t)nrhs * 8 * 16), o_col2 = take((size_t)nrhs * (m + 2) * 16);
+    const size_t o_gp = take((size_t)nrhs * nb * 8 * 8), o_np3 = take((size_t)nrhs * nb * 8);
     char* base = static_cast<char*>(c.vecs.get(off));
     Layout L{};
     L.rhs = reinterpret_cast<double2*>(base + o_rhs);
@@ -376,6 +423,12 @@ int solve(Ctx& c, const vie_solve_opts& o, int nrhs, const double2* et, double2*
     L.pc = reinterpret_cast<double2*>(base + o_pc);
     L.col = reinterpret_cast<double2*>(base + o_col);
     L.npart2 = reinterpret_cast<double*>(base + o_np2);
+    L.g3 = reinterpret_cast<double2*>(base + o_g3);
+    L.coef3 = reinterpret_cast<double2*>(base + o_coef3);
+    L.tc = reinterpret_cast<double2*>(base + o_tc);
+    L.col2 = reinterpret_cast<double2*>(base + o_col2);
+    L.gpart = reinterpret_cast<double*>(base + o_gp);
+    L.npart3 = reinterpret_cast<double*>(base + o_np3);
     if (st)
         for (int r = 0; r < nrhs; ++r) st[r] = vie_solve_stats{};
 
